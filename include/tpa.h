@@ -1,0 +1,184 @@
+/*
+ * tpa.h -- C ABI of the MI355X (gfx950) implementation of TPA's hot path.
+ *
+ * Method: Yoon, Jung, Kang, "TPA: Fast, Scalable, and Accurate Method for
+ * Approximate Random Walk with Restart on Billion Scale Graphs".
+ *   RWR:        r = (1-c) A~^T r + c q                      (Section 2.2)
+ *   CPI:        x(0) = c q,  x(i) = (1-c) A~^T x(i-1),  r = sum_i x(i)
+ *                                                      (Section 2.3, Alg. 1)
+ *   TPA:        r_TPA = r_family + r~_neighbor + r~_stranger    (Section 3)
+ *     r_family    = x(0) + ... + x(S-1)          (online, per seed, Alg. 3)
+ *     r~_neighbor = ((1-c)^S - (1-c)^T) / (1 - (1-c)^S) * r_family
+ *                                               (Section 3.2, Lemma 2)
+ *     r~_stranger = the PageRank terms x'(T) + x'(T+1) + ..., with
+ *                   x'(0) = (c/n) 1           (preprocessing, Alg. 2, 3.1)
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers on the current HIP device
+ *     unless the argument's comment says "host".  The caller owns them.
+ *   - Work is enqueued on `stream` and returns without synchronising,
+ *     except where a comment says "synchronous" (graph construction,
+ *     export of sizes).  A NULL stream is the default stream.
+ *   - Nothing throws across the ABI.  Each call returns a tpa_status; the
+ *     text of the last failure on the calling thread is available from
+ *     tpa_last_error_message().  A failed call leaves the handle usable.
+ *   - A tpa_graph_t owns its device arrays (both orientations of A~, the
+ *     stranger vector, work schedules and workspace).  It may be used by
+ *     one stream at a time; after tpa_preprocess it is read-only for
+ *     queries, which share the handle's workspace (serialise queries on
+ *     one stream, or use one handle per stream).
+ *   - Computation is FP32 with FP32 accumulation (compensated summation for
+ *     the stranger tail); node ids are int32, edge offsets int64.  Results
+ *     are deterministic: the same call on the same inputs gives the same
+ *     bits (no floating-point atomics).
+ */
+#ifndef TPA_H
+#define TPA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tpa_status {
+    TPA_OK = 0,
+    TPA_ERR_INVALID_ARG = -1,      /* bad size, pointer, parameter or node id   */
+    TPA_ERR_NOT_PREPROCESSED = -2, /* query/backward before tpa_preprocess      */
+    TPA_ERR_PARAM_MISMATCH = -3,   /* query (c, T) differs from preprocess      */
+    TPA_ERR_OUT_OF_MEMORY = -4,    /* device allocation failed                  */
+    TPA_ERR_HIP = -5,              /* a HIP runtime call failed                 */
+    TPA_ERR_INDEX_OVERFLOW = -6,   /* node count does not fit int32 ids         */
+    TPA_ERR_CAPTURE = -7           /* would allocate while the stream captures  */
+} tpa_status;
+
+typedef struct tpa_graph *tpa_graph_t;
+
+/* ------------------------------------------------------------------------
+ * Graph construction (synchronous on `stream`).
+ *
+ * Every constructor produces the row-normalised adjacency A~ of Section 2
+ * (Table 1): duplicate edges are merged, each node without an out-edge gets
+ * a self-loop (so every row of A~ sums to 1, as Theorem 1 and Lemma 2
+ * require), and A~_uv = 1/outdeg(u) in FP32 (IEEE division).  Both A~ (rows
+ * = sources) and A~^T (rows = destinations) are stored, columns ascending,
+ * int64 row offsets, int32 column ids.
+ * ---------------------------------------------------------------------- */
+
+/* R-MAT graph on `n_nodes` nodes (n_nodes <= 2^scale; 0 means 2^scale):
+ * raw sample e draws `scale` quadrants, most significant bit first, level l
+ * from the top 32 bits of the (e*scale + l)-th output of SplitMix64 seeded
+ * with `seed`; quadrant probabilities (a, b, c, 1-a-b-c) map to (u bit,
+ * v bit) = (0,0), (0,1), (1,0), (1,1).  Samples with an endpoint >= n_nodes
+ * are rejected; `samples` accepted samples are kept.
+ * Errors: INVALID_ARG (scale outside 1..31, samples < 0, bad probabilities,
+ * n_nodes > 2^scale), OUT_OF_MEMORY, HIP. */
+tpa_status tpa_graph_rmat(int scale, int64_t n_nodes, int64_t samples, uint64_t seed,
+                          double a, double b, double c, hipStream_t stream,
+                          tpa_graph_t *out);
+
+/* Graph from an edge list src[i] -> dst[i], i < m, node ids in [0, n).
+ * `device_ptrs` != 0: src/dst are device pointers; 0: host pointers.
+ * Errors: INVALID_ARG (n < 1, m < 0, null pointer, id out of range -- the
+ * range check is synchronous), INDEX_OVERFLOW (n > 2^31 - 1), OOM, HIP. */
+tpa_status tpa_graph_from_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                int device_ptrs, hipStream_t stream, tpa_graph_t *out);
+
+/* Block-diagonal packing of `count` graphs into one (node ids of graph g
+ * are offset by the node counts of graphs 0..g-1).  Each block keeps its
+ * own PageRank restart c/n_g in tpa_preprocess, so queries on the packed
+ * graph equal queries on each graph alone.  The inputs stay valid and are
+ * not modified; edge logits are not carried over.
+ * Errors: INVALID_ARG (count < 1, null handle), INDEX_OVERFLOW, OOM, HIP. */
+tpa_status tpa_graph_pack(const tpa_graph_t *graphs, int count, hipStream_t stream,
+                          tpa_graph_t *out);
+
+tpa_status tpa_graph_destroy(tpa_graph_t g);
+
+/* Sizes (host outputs; any may be NULL). nblocks is 1 unless packed. */
+tpa_status tpa_graph_info(tpa_graph_t g, int64_t *n, int64_t *m, int64_t *nblocks);
+
+/* Host copy of the block offsets (nblocks + 1 entries). */
+tpa_status tpa_graph_blocks(tpa_graph_t g, int64_t *offsets_host);
+
+/* Copy one orientation out: transpose = 0 gives A~ (rows = sources),
+ * 1 gives A~^T (rows = destinations).  row_ptr int64[n+1], col int32[m],
+ * w float[m] (the current weights); any of them may be NULL. */
+tpa_status tpa_graph_export(tpa_graph_t g, int transpose, int64_t *row_ptr, int32_t *col,
+                            float *w, hipStream_t stream);
+
+/* mask[u] = 1 where the builder added a self-loop (u had no out-edge). */
+tpa_status tpa_graph_padded(tpa_graph_t g, uint8_t *mask, hipStream_t stream);
+
+/* Per-edge logits theta (float[m], A~ order): A~_uv becomes the softmax of
+ * theta over u's out-edges.  NULL restores 1/outdeg.  Invalidates the
+ * stranger vector (tpa_preprocess must run again).  Errors: INVALID_ARG,
+ * OOM, HIP. */
+tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * TPA.
+ * ---------------------------------------------------------------------- */
+
+/* Preprocessing phase (Algorithm 2, Section 3.1): r~_stranger = sum of
+ * x'(i) for T <= i <= K, x'(0) = (c/n_g) on every node of block g.  K is
+ * the first i with c(1-c)^i < eps -- Algorithm 1's L1 break evaluated with
+ * Lemma 2's closed form ||x'(i)||_1 = c(1-c)^i per block -- so K = 116 at
+ * c = 0.15, eps = 1e-9.  tpa_preprocess uses eps = 1e-9 (the paper's
+ * setting, Section 4.1).  Errors: INVALID_ARG (c outside (0,1), T < 0,
+ * eps <= 0), OOM, HIP. */
+tpa_status tpa_preprocess(tpa_graph_t g, double c, int T, hipStream_t stream);
+tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double eps, hipStream_t stream);
+
+/* Copy r~_stranger (float[n]) out.  Errors: NOT_PREPROCESSED. */
+tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t stream);
+
+/* Online phase (Algorithm 3) for k seed nodes: out[j*n + v] = r_TPA of
+ * seed seeds[j] at node v (seed-major float[k][n]).  r_family is computed
+ * in Horner form y <- c q + (1-c) A~^T y (S-1 steps; same sum), the neighbor
+ * scale uses Lemma 2's closed form, and the combine
+ * out = (1 + scale) y + r~_stranger is fused into the last step.
+ * Requires S >= 1, T >= S, and (c, T) equal to tpa_preprocess's.
+ * Seeds must lie in [0, n); the check runs on the device: an out-of-range
+ * seed makes its output row all NaN and sets the sticky error returned by
+ * tpa_get_device_error.  On a packed graph this computes over the whole
+ * packed node set (use tpa_query_packed for per-block seeds).
+ * Errors: INVALID_ARG, NOT_PREPROCESSED, PARAM_MISMATCH, OOM, HIP,
+ * CAPTURE (workspace would have to grow during stream capture: call
+ * tpa_reserve first). */
+tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
+                     float *out, hipStream_t stream);
+
+/* Online phase on a block-diagonal graph with `per_block` seed slots per
+ * block: seeds[b*per_block + j] is a node of block b; out[j*n + v] is the
+ * r_TPA of block(v)'s j-th seed at node v (float[per_block][n]).  One
+ * SpMM over all blocks.  Errors as tpa_query; a seed outside its block
+ * counts as out of range. */
+tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, double c,
+                            int S, int T, float *out, hipStream_t stream);
+
+/* Pre-allocate the query workspace for up to k seeds (or per_block slots),
+ * so that later queries allocate nothing (e.g. under stream capture). */
+tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
+
+/* Query tuning: seed-tile width kt (seeds per SpMM pass: 1, 2, 4, 8, 16,
+ * 32 or 64; 0 = automatic) and edges per wave work item (64..4096, a
+ * multiple of 64; 0 = automatic). */
+tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item);
+tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
+
+/* Sticky device-side error (synchronises `stream`): TPA_ERR_INVALID_ARG if
+ * any query since the last call saw an out-of-range seed, else TPA_OK.
+ * Clears the flag. */
+tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
+
+const char *tpa_status_string(tpa_status s);
+const char *tpa_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPA_H */

@@ -1,0 +1,267 @@
+"""Python binding of libtpa (include/tpa.h): TPA's hot path on MI355X.
+
+Argument marshalling only.  Every step of graph construction, preprocessing
+and querying runs in the HIP kernels of libtpa.so; torch provides device
+memory (tensors) and the current HIP stream.  There is no CPU fallback: if
+the library is missing or no HIP device is present, calls raise.
+
+The raw C entry points are exposed under their C names (``tpa_query`` ...)
+taking plain integers / pointers; ``Graph`` wraps them for torch tensors.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libtpa.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "tpa.h")
+
+TPA_OK = 0
+STATUS = {
+    0: "TPA_OK", -1: "TPA_ERR_INVALID_ARG", -2: "TPA_ERR_NOT_PREPROCESSED",
+    -3: "TPA_ERR_PARAM_MISMATCH", -4: "TPA_ERR_OUT_OF_MEMORY", -5: "TPA_ERR_HIP",
+    -6: "TPA_ERR_INDEX_OVERFLOW", -7: "TPA_ERR_CAPTURE",
+}
+
+_i = C.c_int
+_i64 = C.c_int64
+_u64 = C.c_uint64
+_d = C.c_double
+_vp = C.c_void_p
+
+# name -> (restype, argtypes); mirrors include/tpa.h
+_SIGS = {
+    "tpa_graph_rmat": (_i, [_i, _i64, _i64, _u64, _d, _d, _d, _vp, _vp]),
+    "tpa_graph_from_edges": (_i, [_i64, _i64, _vp, _vp, _i, _vp, _vp]),
+    "tpa_graph_pack": (_i, [_vp, _i, _vp, _vp]),
+    "tpa_graph_destroy": (_i, [_vp]),
+    "tpa_graph_info": (_i, [_vp, _vp, _vp, _vp]),
+    "tpa_graph_blocks": (_i, [_vp, _vp]),
+    "tpa_graph_export": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
+    "tpa_graph_padded": (_i, [_vp, _vp, _vp]),
+    "tpa_graph_set_logits": (_i, [_vp, _vp, _vp]),
+    "tpa_preprocess": (_i, [_vp, _d, _i, _vp]),
+    "tpa_preprocess_ex": (_i, [_vp, _d, _i, _d, _vp]),
+    "tpa_stranger": (_i, [_vp, _vp, _vp]),
+    "tpa_query": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
+    "tpa_query_packed": (_i, [_vp, _vp, _i, _d, _i, _i, _vp, _vp]),
+    "tpa_reserve": (_i, [_vp, _i64]),
+    "tpa_set_tuning": (_i, [_vp, _i, _i]),
+    "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
+    "tpa_get_device_error": (_i, [_vp, _vp]),
+    "tpa_status_string": (C.c_char_p, [_i]),
+    "tpa_last_error_message": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class TPAError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+
+
+def load_library():
+    """Load libtpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1708_02574_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Names of the functions declared in include/tpa.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpa_[a-z_]+)\s*\(", txt)))
+
+
+def _check(status: int, where: str):
+    if status != TPA_OK:
+        msg = _lib.tpa_last_error_message().decode(errors="replace")
+        raise TPAError(status, where, msg)
+
+
+def _call(name: str, *args):
+    lib = load_library()
+    _check(getattr(lib, name)(*args), name)
+
+
+# raw entry points under their C names -------------------------------------
+def __getattr__(name):
+    if name in _SIGS:
+        return getattr(load_library(), name)
+    raise AttributeError(name)
+
+
+# --------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libtpa needs a HIP device (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+def _ptr(t):
+    return _vp(t.data_ptr())
+
+
+class Graph:
+    """Owning wrapper of a tpa_graph_t (device CSR of A~ and A~^T)."""
+
+    def __init__(self, handle: int, _keep=()):
+        self._h = _vp(handle)
+        self._keep = _keep
+        n, m, nb = C.c_int64(), C.c_int64(), C.c_int64()
+        _call("tpa_graph_info", self._h, C.byref(n), C.byref(m), C.byref(nb))
+        self.n, self.m, self.nblocks = n.value, m.value, nb.value
+
+    # -- constructors ------------------------------------------------------
+    @classmethod
+    def rmat(cls, scale: int, samples: int, seed: int, n_nodes: int = 0,
+             abcd=(0.57, 0.19, 0.19, 0.05), stream=None) -> "Graph":
+        _torch()
+        h = _vp()
+        _call("tpa_graph_rmat", scale, n_nodes, samples, seed & 0xFFFFFFFFFFFFFFFF,
+              abcd[0], abcd[1], abcd[2], _stream(stream), C.byref(h))
+        return cls(h.value)
+
+    @classmethod
+    def from_edges(cls, n: int, src, dst, stream=None) -> "Graph":
+        torch = _torch()
+        if isinstance(src, torch.Tensor) and src.is_cuda:
+            s = src.to(torch.int32).contiguous()
+            d = dst.to(torch.int32).contiguous()
+            dev = 1
+            ps, pd = _ptr(s), _ptr(d)
+            m = s.numel()
+        else:
+            s = np.ascontiguousarray(np.asarray(src), np.int32)
+            d = np.ascontiguousarray(np.asarray(dst), np.int32)
+            dev = 0
+            ps, pd = s.ctypes.data_as(_vp), d.ctypes.data_as(_vp)
+            m = s.size
+        if (d.numel() if dev else d.size) != m:
+            raise ValueError("src and dst differ in length")
+        h = _vp()
+        _call("tpa_graph_from_edges", n, m, ps, pd, dev, _stream(stream), C.byref(h))
+        return cls(h.value)
+
+    @classmethod
+    def pack(cls, graphs, stream=None) -> "Graph":
+        _torch()
+        arr = (_vp * len(graphs))(*[g._h.value for g in graphs])
+        h = _vp()
+        _call("tpa_graph_pack", arr, len(graphs), _stream(stream), C.byref(h))
+        return cls(h.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tpa_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- accessors ---------------------------------------------------------
+    def block_offsets(self) -> np.ndarray:
+        out = np.empty(self.nblocks + 1, np.int64)
+        _call("tpa_graph_blocks", self._h, out.ctypes.data_as(_vp))
+        return out
+
+    def export(self, transpose: bool = False, stream=None):
+        torch = _torch()
+        rp = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
+        col = torch.empty(self.m, dtype=torch.int32, device="cuda")
+        w = torch.empty(self.m, dtype=torch.float32, device="cuda")
+        _call("tpa_graph_export", self._h, int(transpose), _ptr(rp), _ptr(col), _ptr(w), _stream(stream))
+        return rp, col, w
+
+    def padded(self, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        _call("tpa_graph_padded", self._h, _ptr(out), _stream(stream))
+        return out
+
+    def set_logits(self, theta=None, stream=None):
+        if theta is None:
+            _call("tpa_graph_set_logits", self._h, None, _stream(stream))
+            return
+        th = theta.to(dtype=_torch().float32).contiguous()
+        if th.numel() != self.m or not th.is_cuda:
+            raise ValueError("theta must be a device tensor with one entry per edge")
+        _call("tpa_graph_set_logits", self._h, _ptr(th), _stream(stream))
+
+    # -- TPA ---------------------------------------------------------------
+    def preprocess(self, c: float, T: int, eps: float | None = None, stream=None):
+        if eps is None:
+            _call("tpa_preprocess", self._h, c, T, _stream(stream))
+        else:
+            _call("tpa_preprocess_ex", self._h, c, T, eps, _stream(stream))
+
+    def stranger(self, stream=None):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        _call("tpa_stranger", self._h, _ptr(out), _stream(stream))
+        return out
+
+    def query(self, seeds, c: float, S: int, T: int, out=None, stream=None):
+        """r_TPA for each seed: float32 [k, n] on the device."""
+        torch = _torch()
+        sd = seeds.to(device="cuda", dtype=torch.int32).contiguous()
+        k = sd.numel()
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.float32, device="cuda")
+        elif out.shape != (k, self.n) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [k, n] device tensor")
+        _call("tpa_query", self._h, _ptr(sd), k, c, S, T, _ptr(out), _stream(stream))
+        return out
+
+    def query_packed(self, seeds, c: float, S: int, T: int, out=None, stream=None):
+        """seeds: int [nblocks, P] (node ids of each block); returns [P, n]."""
+        torch = _torch()
+        sd = seeds.to(device="cuda", dtype=torch.int32).contiguous()
+        if sd.dim() != 2 or sd.shape[0] != self.nblocks:
+            raise ValueError("seeds must be [nblocks, per_block]")
+        P = sd.shape[1]
+        if out is None:
+            out = torch.empty((P, self.n), dtype=torch.float32, device="cuda")
+        _call("tpa_query_packed", self._h, _ptr(sd), P, c, S, T, _ptr(out), _stream(stream))
+        return out
+
+    def reserve(self, k: int):
+        _call("tpa_reserve", self._h, k)
+
+    def set_tuning(self, seed_tile: int = 0, edges_per_item: int = 0):
+        _call("tpa_set_tuning", self._h, seed_tile, edges_per_item)
+
+    def get_tuning(self):
+        a, b = C.c_int(), C.c_int()
+        _call("tpa_get_tuning", self._h, C.byref(a), C.byref(b))
+        return a.value, b.value
+
+    def device_error(self, stream=None):
+        """Raise TPAError if a query since the last check saw a bad seed."""
+        _call("tpa_get_device_error", self._h, _stream(stream))

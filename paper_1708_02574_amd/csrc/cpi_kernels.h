@@ -1,0 +1,60 @@
+// Launch interface of the CPI step kernels (cpi_kernels.hip).
+#pragma once
+
+#include "tpa_internal.h"
+
+namespace tpa {
+
+enum StepMode : int { kFamily = 0, kStranger = 1 };
+
+// One CPI step y = (1-c) A~^T x over a seed tile of kt columns (node-major
+// [n][kt] vectors), pulled over the rows of A~^T, plus the step's epilogue:
+//   family   (Horner form): y = c*[v == seed] + (1-c)*sum; the next gathered
+//            vector is y * (1/outdeg) (uniform weights) or y (explicit
+//            weights); on the last step out = alpha*y + r~_stranger instead.
+//   stranger : x = (1-c)*sum; next gathered vector as above; when
+//            `accumulate` is set r~_stranger += x (Kahan-compensated).
+struct StepParams {
+    const int64_t *rowptr = nullptr;
+    const int32_t *col = nullptr;
+    const float *w = nullptr;          // per-edge weights in A~^T order, or null
+    const float *inv = nullptr;        // 1/outdeg (uniform weights)
+    const float *zin = nullptr;        // gathered vector [n][kt]
+    float *zout = nullptr;             // next gathered vector [n][kt]
+    float *partials = nullptr;         // [slots][kt] chunk sums of long rows
+    float omc = 0.f;                   // 1 - c
+    float c = 0.f;
+    int kt = 1;
+    // family
+    const int32_t *seeds = nullptr;    // tile seeds; -1 inactive, -2 invalid
+    const int32_t *node_block = nullptr;
+    int seed_stride = 0;               // seeds per block (packed graphs)
+    int ncols = 0;                     // active columns of this tile
+    int last = 0;
+    float alpha = 0.f;
+    const float *str = nullptr;
+    float *out = nullptr;              // seed-major [*, n]
+    int64_t n = 0;
+    int64_t out_col0 = 0;
+    // stranger
+    float *acc = nullptr;
+    float *comp = nullptr;
+    int accumulate = 0;
+};
+
+tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams &p, hipStream_t st);
+
+// x'(0) for the stranger chain: zout = c*r0*(1/outdeg or 1), acc = c*r0 if
+// T == 0 else 0, comp = 0, where r0 = 1/n or 1/n_block(v).
+tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, float *zout, float *acc,
+                                float *comp, hipStream_t st);
+
+// S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
+tpa_status launch_combine_only(const StepParams &p, hipStream_t st);
+
+// Validate seeds into `dst` (k entries): out of range, or outside its block
+// for packed graphs, becomes -2 and raises the sticky error flag.
+tpa_status launch_check_seeds(const int32_t *seeds, int64_t k, int per_block, const tpa_graph *g,
+                              int32_t *dst, hipStream_t st);
+
+}  // namespace tpa

@@ -1,0 +1,708 @@
+// Graph store construction on the GPU: R-MAT sampling, sort + dedupe,
+// dangling self-loops, CSR of A~ and A~^T, 1/outdeg weights, edge-logit
+// softmax, block-diagonal packing, and the wave work schedule.
+//
+// The graph is the row-normalised adjacency A~ of the paper's Section 2
+// (Table 1); every row of A~ must sum to 1 (Theorem 1, Lemma 2), hence the
+// self-loop on each node without out-edges.
+
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "tpa_internal.h"
+
+namespace tpa {
+
+int key_bits(int64_t n) {
+    int b = 1;
+    while (b < 62 && (int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------------ kernels
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 30));
+}
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output j of the generator
+// seeded with `seed` is the mixing function applied to seed + (j+1)*gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t j) {
+    uint64_t z = seed + (j + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// One raw R-MAT sample per thread; key = (u << bits) | v.
+__global__ void rmat_kernel(uint64_t seed, int scale, int64_t raw_begin, int64_t count,
+                            uint32_t t0, uint32_t t1, uint32_t t2, int64_t n_nodes, int bits,
+                            uint64_t *keys, int64_t *accept) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = (uint64_t)(raw_begin + i);
+        uint64_t u = 0, v = 0;
+        for (int l = 0; l < scale; ++l) {
+            const uint32_t r = (uint32_t)(splitmix64_at(seed, e * (uint64_t)scale + (uint64_t)l) >> 32);
+            const uint32_t q = (uint32_t)(r >= t0) + (uint32_t)(r >= t1) + (uint32_t)(r >= t2);
+            u = (u << 1) | (q >> 1);
+            v = (v << 1) | (q & 1u);
+        }
+        const bool ok = (int64_t)u < n_nodes && (int64_t)v < n_nodes;
+        keys[i] = ok ? ((u << bits) | v) : 0;
+        if (accept) accept[i] = ok ? 1 : 0;
+    }
+}
+
+__global__ void pack_edges_kernel(const int32_t *src, const int32_t *dst, int64_t m, int bits,
+                                  int64_t n, uint64_t *keys, int32_t *bad) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = src[i], v = dst[i];
+        if (u < 0 || u >= n || v < 0 || v >= n) {
+            *bad = 1;
+            keys[i] = 0;
+        } else {
+            keys[i] = ((uint64_t)u << bits) | (uint64_t)v;
+        }
+    }
+}
+
+// out[pos[i]] = in[i] where flag[i] (pos = exclusive scan of flags).
+__global__ void compact_kernel(const uint64_t *in, const int64_t *flag, const int64_t *pos,
+                               int64_t count, int64_t limit, int64_t out_base, uint64_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (flag[i]) {
+            const int64_t p = out_base + pos[i];
+            if (p < limit) out[p] = in[i];
+        }
+    }
+}
+
+__global__ void unique_flags_kernel(const uint64_t *k, int64_t count, int64_t *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || k[i] != k[i - 1]) ? 1 : 0;
+}
+
+__global__ void count_rows_kernel(const uint64_t *k, int64_t count, int bits, int32_t *deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&deg[k[i] >> bits], 1);
+}
+
+__global__ void count_cols_kernel(const int32_t *col, int64_t count, int32_t *deg) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&deg[col[i]], 1);
+}
+
+// deg -> (deg64, deg2 = max(deg,1), padded, 1/deg2); entry n is 0.
+__global__ void degree_kernel(const int32_t *deg, int64_t n, int64_t *deg64, int64_t *deg2,
+                              uint8_t *padded, float *inv) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u <= n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        if (u == n) {
+            deg64[n] = 0;
+            deg2[n] = 0;
+        } else {
+            const int32_t d = deg[u];
+            deg64[u] = d;
+            deg2[u] = d > 0 ? d : 1;
+            padded[u] = d == 0;
+            inv[u] = 1.0f / (float)(d > 0 ? d : 1);
+        }
+    }
+}
+
+__global__ void widen_kernel(const int32_t *in, int64_t n, int64_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = i < n ? in[i] : 0;
+}
+
+// Place unique edge i at its A~ slot and emit its transposed key.
+__global__ void fill_a_kernel(const uint64_t *uk, int64_t mu, int bits, const int64_t *a_rowptr,
+                              const int64_t *ustart, int32_t *a_col, uint64_t *tkeys) {
+    const uint64_t mask = (bits >= 64) ? ~0ull : ((1ull << bits) - 1);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mu;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = uk[i];
+        const int64_t u = (int64_t)(k >> bits), v = (int64_t)(k & mask);
+        const int64_t p = a_rowptr[u] + (i - ustart[u]);
+        a_col[p] = (int32_t)v;
+        tkeys[p] = ((uint64_t)v << bits) | (uint64_t)u;
+    }
+}
+
+__global__ void fill_selfloops_kernel(const uint8_t *padded, int64_t n, int bits,
+                                      const int64_t *a_rowptr, int32_t *a_col, uint64_t *tkeys) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        if (padded[u]) {
+            const int64_t p = a_rowptr[u];
+            a_col[p] = (int32_t)u;
+            tkeys[p] = ((uint64_t)u << bits) | (uint64_t)u;
+        }
+    }
+}
+
+__global__ void low_bits_kernel(const uint64_t *k, int64_t count, int bits, int32_t *out) {
+    const uint64_t mask = (1ull << bits) - 1;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (int32_t)(k[i] & mask);
+}
+
+// Transposed keys + A~ edge ids, one thread per row of A~.
+__global__ void tkeys_with_ids_kernel(const int64_t *a_rowptr, const int32_t *a_col, int64_t n,
+                                      int bits, uint64_t *tkeys, int64_t *ids) {
+    for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < n;
+         u += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = a_rowptr[u]; e < a_rowptr[u + 1]; ++e) {
+            tkeys[e] = ((uint64_t)a_col[e] << bits) | (uint64_t)u;
+            ids[e] = e;
+        }
+    }
+}
+
+// Row softmax of the logits over A~'s rows, one wave per row (fixed-order
+// reductions, so the weights are deterministic).
+__global__ void softmax_rows_kernel(const int64_t *rowptr, int64_t n, const float *theta,
+                                    float *w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    float mx = -INFINITY;
+    for (int64_t i = b + lane; i < e; i += 64) mx = fmaxf(mx, theta[i]);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+    float s = 0.0f;
+    for (int64_t i = b + lane; i < e; i += 64) s += expf(theta[i] - mx);
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    for (int64_t i = b + lane; i < e; i += 64) w[i] = expf(theta[i] - mx) / s;
+}
+
+__global__ void gather_w_kernel(const float *aw, const int64_t *t2a, int64_t m, float *tw) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        tw[i] = aw[t2a[i]];
+}
+
+__global__ void uniform_w_kernel(const int64_t *rowptr, const int32_t *col, const float *inv,
+                                 int64_t n, int transpose, float *w) {
+    // transpose == 0: w[e] = inv[row]; transpose == 1: w[e] = inv[col[e]]
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t e = rowptr[r]; e < rowptr[r + 1]; ++e) w[e] = transpose ? inv[col[e]] : inv[r];
+}
+
+__global__ void offset_i64_kernel(const int64_t *in, int64_t count, int64_t add, int64_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + add;
+}
+
+__global__ void offset_i32_kernel(const int32_t *in, int64_t count, int32_t add, int32_t *out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i] + add;
+}
+
+__global__ void fill_block_kernel(int32_t *node_block, float *restart, int64_t begin, int64_t count,
+                                  int32_t b, float inv_nb) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        node_block[begin + i] = b;
+        restart[begin + i] = inv_nb;
+    }
+}
+
+struct Plus64 {
+    __host__ __device__ int64_t operator()(int64_t a, int64_t b) const { return a + b; }
+};
+
+// Exclusive prefix sum of count int64 values (rocPRIM device scan).
+tpa_status exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t count, hipStream_t st) {
+    size_t bytes = 0;
+    TPA_TRY_HIP(rocprim::exclusive_scan(nullptr, bytes, in, out, int64_t(0), (size_t)count,
+                                        Plus64(), st));
+    void *tmp = nullptr;
+    TPA_TRY(dmalloc(&tmp, std::max<size_t>(bytes, 16), st));
+    hipError_t e = rocprim::exclusive_scan(tmp, bytes, in, out, int64_t(0), (size_t)count,
+                                           Plus64(), st);
+    dfree(tmp);
+    TPA_TRY_HIP(e);
+    return TPA_OK;
+}
+
+// Sort keys (bits [0, end_bit)); returns the buffer holding the result and
+// frees the other one.
+tpa_status sort_keys(uint64_t *keys, int64_t count, int end_bit, hipStream_t st, uint64_t **result) {
+    uint64_t *alt = nullptr;
+    TPA_TRY(dalloc(&alt, std::max<int64_t>(count, 1), st));
+    rocprim::double_buffer<uint64_t> db(keys, alt);
+    size_t bytes = 0;
+    hipError_t e = rocprim::radix_sort_keys(nullptr, bytes, db, (size_t)count, 0u,
+                                            (unsigned)end_bit, st);
+    if (e != hipSuccess) { dfree(alt); TPA_TRY_HIP(e); }
+    void *tmp = nullptr;
+    tpa_status s = dmalloc(&tmp, std::max<size_t>(bytes, 16), st);
+    if (s != TPA_OK) { dfree(alt); return s; }
+    e = rocprim::radix_sort_keys(tmp, bytes, db, (size_t)count, 0u, (unsigned)end_bit, st);
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    dfree(tmp);
+    if (e != hipSuccess) { dfree(alt); TPA_TRY_HIP(e); }
+    *result = db.current();
+    dfree(db.alternate());
+    return TPA_OK;
+}
+
+template <class T>
+T read_back(const T *dptr, hipStream_t st) {
+    T v{};
+    if (hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, st) != hipSuccess) return v;
+    (void)hipStreamSynchronize(st);
+    return v;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ build
+tpa_status graph_alloc_common(tpa_graph *g, hipStream_t st) {
+    TPA_TRY(dalloc(&g->dev_err, 1, st));
+    TPA_TRY_HIP(hipMemsetAsync(g->dev_err, 0, sizeof(int32_t), st));
+    g->block_off = {0, g->n};
+    g->nblocks = 1;
+    return TPA_OK;
+}
+
+// Takes ownership of `keys` ((u << bits) | v, nkeys entries).
+tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t st) {
+    const int64_t n = g->n;
+    const int bits = g->bits;
+    uint64_t *sorted = keys;
+    if (nkeys > 0) {
+        tpa_status s = sort_keys(keys, nkeys, 2 * bits, st, &sorted);
+        if (s != TPA_OK) { dfree(keys); return s; }
+    }
+    // unique
+    int64_t *flag = nullptr, *pos = nullptr;
+    uint64_t *uk = nullptr;
+    int64_t mu = 0;
+    if (nkeys > 0) {
+        TPA_TRY(dalloc(&flag, nkeys + 1, st));
+        TPA_TRY(dalloc(&pos, nkeys + 1, st));
+        unique_flags_kernel<<<grid_for(nkeys), kBlock, 0, st>>>(sorted, nkeys, flag);
+        TPA_TRY(exclusive_scan_i64(flag, pos, nkeys, st));
+        mu = read_back(pos + nkeys - 1, st) + read_back(flag + nkeys - 1, st);
+        TPA_TRY(dalloc(&uk, std::max<int64_t>(mu, 1), st));
+        compact_kernel<<<grid_for(nkeys), kBlock, 0, st>>>(sorted, flag, pos, nkeys, mu, 0, uk);
+        TPA_TRY_HIP(hipStreamSynchronize(st));
+        dfree(flag);
+        dfree(pos);
+        dfree(sorted);
+    }
+    // out-degrees, dangling self-loops, A~ row offsets
+    int32_t *deg = nullptr;
+    int64_t *deg64 = nullptr, *deg2 = nullptr, *ustart = nullptr;
+    TPA_TRY(dalloc(&deg, n, st));
+    TPA_TRY(dalloc(&deg64, n + 1, st));
+    TPA_TRY(dalloc(&deg2, n + 1, st));
+    TPA_TRY(dalloc(&ustart, n + 1, st));
+    TPA_TRY(dalloc(&g->a.rowptr, n + 1, st));
+    TPA_TRY(dalloc(&g->padded, n, st));
+    TPA_TRY(dalloc(&g->inv_deg, n, st));
+    TPA_TRY_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * n, st));
+    if (mu > 0) count_rows_kernel<<<grid_for(mu), kBlock, 0, st>>>(uk, mu, bits, deg);
+    degree_kernel<<<grid_for(n + 1), kBlock, 0, st>>>(deg, n, deg64, deg2, g->padded, g->inv_deg);
+    TPA_TRY(exclusive_scan_i64(deg64, ustart, n + 1, st));
+    TPA_TRY(exclusive_scan_i64(deg2, g->a.rowptr, n + 1, st));
+    g->m = read_back(g->a.rowptr + n, st);
+    const int64_t m = g->m;
+    // A~ columns + transposed keys
+    uint64_t *tkeys = nullptr;
+    TPA_TRY(dalloc(&g->a.col, m, st));
+    TPA_TRY(dalloc(&tkeys, m, st));
+    if (mu > 0)
+        fill_a_kernel<<<grid_for(mu), kBlock, 0, st>>>(uk, mu, bits, g->a.rowptr, ustart, g->a.col, tkeys);
+    fill_selfloops_kernel<<<grid_for(n), kBlock, 0, st>>>(g->padded, n, bits, g->a.rowptr, g->a.col, tkeys);
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    dfree(uk);
+    dfree(ustart);
+    dfree(deg2);
+    // A~^T: sort transposed keys; row offsets from in-degrees
+    uint64_t *tsorted = nullptr;
+    TPA_TRY(sort_keys(tkeys, m, 2 * bits, st, &tsorted));
+    TPA_TRY(dalloc(&g->t.col, m, st));
+    TPA_TRY(dalloc(&g->t.rowptr, n + 1, st));
+    low_bits_kernel<<<grid_for(m), kBlock, 0, st>>>(tsorted, m, bits, g->t.col);
+    TPA_TRY_HIP(hipMemsetAsync(deg, 0, sizeof(int32_t) * n, st));
+    count_cols_kernel<<<grid_for(m), kBlock, 0, st>>>(g->a.col, m, deg);
+    widen_kernel<<<grid_for(n + 1), kBlock, 0, st>>>(deg, n, deg64);
+    TPA_TRY(exclusive_scan_i64(deg64, g->t.rowptr, n + 1, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    dfree(tsorted);
+    dfree(deg);
+    dfree(deg64);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status ensure_t2a(tpa_graph *g, hipStream_t st) {
+    if (g->t2a) return TPA_OK;
+    const int64_t n = g->n, m = g->m;
+    uint64_t *k0 = nullptr, *k1 = nullptr;
+    int64_t *v0 = nullptr, *v1 = nullptr;
+    TPA_TRY(dalloc(&k0, m, st));
+    TPA_TRY(dalloc(&k1, m, st));
+    TPA_TRY(dalloc(&v0, m, st));
+    TPA_TRY(dalloc(&v1, m, st));
+    tkeys_with_ids_kernel<<<grid_for(n), kBlock, 0, st>>>(g->a.rowptr, g->a.col, n, g->bits, k0, v0);
+    rocprim::double_buffer<uint64_t> kb(k0, k1);
+    rocprim::double_buffer<int64_t> vb(v0, v1);
+    size_t bytes = 0;
+    TPA_TRY_HIP(rocprim::radix_sort_pairs(nullptr, bytes, kb, vb, (size_t)m, 0u, (unsigned)(2 * g->bits), st));
+    void *tmp = nullptr;
+    TPA_TRY(dmalloc(&tmp, std::max<size_t>(bytes, 16), st));
+    TPA_TRY_HIP(rocprim::radix_sort_pairs(tmp, bytes, kb, vb, (size_t)m, 0u, (unsigned)(2 * g->bits), st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    dfree(tmp);
+    g->t2a = vb.current();
+    dfree(vb.alternate());
+    dfree(k0);
+    dfree(k1);
+    return TPA_OK;
+}
+
+// ------------------------------------------------------------------ schedule
+void Schedule::release() {
+    dfree(items);
+    dfree(longs);
+    items = nullptr;
+    longs = nullptr;
+}
+
+// Rows of A~^T are cut into wave items: rows longer than EL edges into
+// EL-edge chunks (partials + a finish pass), rows of EW..EL edges into one
+// whole-row item each, and runs of short rows into groups of at most 64
+// rows whose first edges lie in one EW-aligned window (so < 2*EW edges).
+// Heavy items come first so that they start early in the grid.
+tpa_status get_schedule(tpa_graph *g, int ew, hipStream_t st, const Schedule **out) {
+    auto it = g->sched_t.find(ew);
+    if (it != g->sched_t.end()) { *out = &it->second; return TPA_OK; }
+    const int64_t n = g->n;
+    const int el = 8 * ew;
+    std::vector<int64_t> rp(n + 1);
+    TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->t.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    std::vector<Item> heavy, whole, shorts;
+    std::vector<LongRow> longs;
+    int64_t slots = 0, maxch = 0;
+    int64_t gstart = -1;
+    auto close_group = [&](int64_t end) {
+        if (gstart >= 0 && end > gstart) shorts.push_back({(int32_t)gstart, (int32_t)end, -1, -1});
+        gstart = -1;
+    };
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d > el) {
+            close_group(r);
+            const int64_t nch = (d + el - 1) / el;
+            if (slots + nch > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many partial slots");
+            longs.push_back({(int32_t)r, (int32_t)nch, (int32_t)slots, 0});
+            for (int64_t ch = 0; ch < nch; ++ch) heavy.push_back({(int32_t)r, (int32_t)(r + 1), (int32_t)ch, (int32_t)(slots + ch)});
+            slots += nch;
+            maxch = std::max(maxch, nch);
+        } else if (d > ew) {
+            close_group(r);
+            whole.push_back({(int32_t)r, (int32_t)(r + 1), -2, -1});
+        } else {
+            if (gstart >= 0 && (r - gstart >= 64 || rp[r] / ew != rp[gstart] / ew)) close_group(r);
+            if (gstart < 0) gstart = r;
+        }
+    }
+    close_group(n);
+    Schedule s;
+    s.ew = ew;
+    s.el = el;
+    std::vector<Item> all;
+    all.reserve(heavy.size() + whole.size() + shorts.size());
+    all.insert(all.end(), heavy.begin(), heavy.end());
+    all.insert(all.end(), whole.begin(), whole.end());
+    all.insert(all.end(), shorts.begin(), shorts.end());
+    s.n_items = (int64_t)all.size();
+    s.n_long = (int64_t)longs.size();
+    s.n_slots = slots;
+    s.max_chunks = maxch;
+    if (s.n_items > 0) {
+        TPA_TRY(dalloc(&s.items, s.n_items, st));
+        TPA_TRY_HIP(hipMemcpyAsync(s.items, all.data(), sizeof(Item) * s.n_items, hipMemcpyHostToDevice, st));
+    }
+    if (s.n_long > 0) {
+        TPA_TRY(dalloc(&s.longs, s.n_long, st));
+        TPA_TRY_HIP(hipMemcpyAsync(s.longs, longs.data(), sizeof(LongRow) * s.n_long, hipMemcpyHostToDevice, st));
+    }
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    auto ins = g->sched_t.emplace(ew, s);
+    *out = &ins.first->second;
+    return TPA_OK;
+}
+
+void graph_release(tpa_graph *g) {
+    dfree(g->node_block); dfree(g->restart_pr);
+    dfree(g->a.rowptr); dfree(g->a.col); dfree(g->a.w);
+    dfree(g->t.rowptr); dfree(g->t.col); dfree(g->t.w);
+    dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
+    dfree(g->str); dfree(g->ws); dfree(g->dev_err);
+    for (auto &kv : g->sched_t) kv.second.release();
+    g->sched_t.clear();
+}
+
+}  // namespace tpa
+
+using namespace tpa;
+
+// ==================================================================== C ABI
+extern "C" tpa_status tpa_graph_rmat(int scale, int64_t n_nodes, int64_t samples, uint64_t seed,
+                                     double a, double b, double c, hipStream_t st,
+                                     tpa_graph_t *out) {
+    if (!out) return fail(TPA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (scale < 1 || scale > 31) return fail(TPA_ERR_INVALID_ARG, "scale must be in 1..31");
+    if (samples < 0) return fail(TPA_ERR_INVALID_ARG, "samples must be >= 0");
+    if (!(a >= 0 && b >= 0 && c >= 0 && a + b + c <= 1.0))
+        return fail(TPA_ERR_INVALID_ARG, "R-MAT probabilities must be >= 0 with a+b+c <= 1");
+    const int64_t full = int64_t(1) << scale;
+    if (n_nodes == 0) n_nodes = full;
+    if (n_nodes < 1 || n_nodes > full) return fail(TPA_ERR_INVALID_ARG, "n_nodes must be in 1..2^scale");
+    if (n_nodes > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "node ids must fit int32");
+    const uint32_t t0 = (uint32_t)std::llround(a * 4294967296.0);
+    const uint32_t t1 = (uint32_t)std::llround((a + b) * 4294967296.0);
+    const uint32_t t2 = (uint32_t)std::llround((a + b + c) * 4294967296.0);
+
+    tpa_graph *g = new tpa_graph();
+    TPA_TRY_HIP(hipGetDevice(&g->device));
+    g->n = n_nodes;
+    g->bits = key_bits(n_nodes);
+    uint64_t *keys = nullptr;
+    tpa_status s = dalloc(&keys, std::max<int64_t>(samples, 1), st);
+    if (s != TPA_OK) { delete g; return s; }
+    if (n_nodes == full) {
+        if (samples > 0)
+            rmat_kernel<<<grid_for(samples), kBlock, 0, st>>>(seed, scale, 0, samples, t0, t1, t2,
+                                                             n_nodes, g->bits, keys, nullptr);
+    } else {
+        // rejection: raw batches, keep accepted samples in counter order
+        int64_t got = 0, raw = 0;
+        const int64_t max_raw = 64 * samples + 1024;
+        while (got < samples && raw < max_raw) {
+            const int64_t batch = std::min<int64_t>(max_raw - raw, std::max<int64_t>(2 * (samples - got), 1 << 16));
+            uint64_t *bk = nullptr;
+            int64_t *fl = nullptr, *ps = nullptr;
+            if ((s = dalloc(&bk, batch, st)) != TPA_OK || (s = dalloc(&fl, batch, st)) != TPA_OK ||
+                (s = dalloc(&ps, batch, st)) != TPA_OK) {
+                dfree(bk); dfree(fl); dfree(ps); dfree(keys); delete g; return s;
+            }
+            rmat_kernel<<<grid_for(batch), kBlock, 0, st>>>(seed, scale, raw, batch, t0, t1, t2, n_nodes,
+                                                           g->bits, bk, fl);
+            s = exclusive_scan_i64(fl, ps, batch, st);
+            if (s == TPA_OK) {
+                const int64_t acc = read_back(ps + batch - 1, st) + read_back(fl + batch - 1, st);
+                compact_kernel<<<grid_for(batch), kBlock, 0, st>>>(bk, fl, ps, batch, samples, got, keys);
+                (void)hipStreamSynchronize(st);
+                got = std::min(samples, got + acc);
+            }
+            dfree(bk); dfree(fl); dfree(ps);
+            if (s != TPA_OK) { dfree(keys); delete g; return s; }
+            raw += batch;
+        }
+        if (got < samples) {
+            dfree(keys); delete g;
+            return fail(TPA_ERR_INVALID_ARG, "R-MAT rejection did not reach the requested sample count");
+        }
+    }
+    if ((s = graph_alloc_common(g, st)) != TPA_OK || (s = build_from_keys(g, keys, samples, st)) != TPA_OK) {
+        graph_release(g); delete g; return s;
+    }
+    *out = g;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_from_edges(int64_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                                           int device_ptrs, hipStream_t st, tpa_graph_t *out) {
+    if (!out) return fail(TPA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || m < 0) return fail(TPA_ERR_INVALID_ARG, "need n >= 1 and m >= 0");
+    if (n > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "node ids must fit int32");
+    if (m > 0 && (!src || !dst)) return fail(TPA_ERR_INVALID_ARG, "src/dst is NULL");
+    tpa_graph *g = new tpa_graph();
+    TPA_TRY_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->bits = key_bits(n);
+    uint64_t *keys = nullptr;
+    int32_t *ds = nullptr, *dd = nullptr, *bad = nullptr;
+    tpa_status s = TPA_OK;
+    auto bail = [&](tpa_status e) {
+        dfree(keys); if (!device_ptrs) { dfree(ds); dfree(dd); } dfree(bad);
+        graph_release(g); delete g; return e;
+    };
+    if ((s = dalloc(&keys, std::max<int64_t>(m, 1), st)) != TPA_OK) return bail(s);
+    if ((s = dalloc(&bad, 1, st)) != TPA_OK) return bail(s);
+    if (m > 0) {
+        if (device_ptrs) {
+            ds = const_cast<int32_t *>(src);
+            dd = const_cast<int32_t *>(dst);
+        } else {
+            if ((s = dalloc(&ds, m, st)) != TPA_OK || (s = dalloc(&dd, m, st)) != TPA_OK) return bail(s);
+            if (hipMemcpyAsync(ds, src, sizeof(int32_t) * m, hipMemcpyHostToDevice, st) != hipSuccess ||
+                hipMemcpyAsync(dd, dst, sizeof(int32_t) * m, hipMemcpyHostToDevice, st) != hipSuccess)
+                return bail(fail(TPA_ERR_HIP, "edge upload failed"));
+        }
+        (void)hipMemsetAsync(bad, 0, sizeof(int32_t), st);
+        pack_edges_kernel<<<grid_for(m), kBlock, 0, st>>>(ds, dd, m, g->bits, n, keys, bad);
+        const int32_t isbad = read_back(bad, st);
+        if (!device_ptrs) { dfree(ds); dfree(dd); }
+        ds = dd = nullptr;
+        if (isbad) return bail(fail(TPA_ERR_INVALID_ARG, "edge endpoint outside [0, n)"));
+    }
+    dfree(bad);
+    bad = nullptr;
+    if ((s = graph_alloc_common(g, st)) != TPA_OK) return bail(s);
+    s = build_from_keys(g, keys, m, st);
+    keys = nullptr;
+    if (s != TPA_OK) return bail(s);
+    *out = g;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_pack(const tpa_graph_t *gs, int count, hipStream_t st, tpa_graph_t *out) {
+    if (!out) return fail(TPA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!gs || count < 1) return fail(TPA_ERR_INVALID_ARG, "need at least one graph");
+    int64_t n = 0, m = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!gs[i]) return fail(TPA_ERR_INVALID_ARG, "NULL graph handle");
+        n += gs[i]->n;
+        m += gs[i]->m;
+    }
+    if (n > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "packed node ids must fit int32");
+    tpa_graph *g = new tpa_graph();
+    TPA_TRY_HIP(hipGetDevice(&g->device));
+    g->n = n;
+    g->m = m;
+    g->bits = key_bits(n);
+    tpa_status s;
+    auto bail = [&](tpa_status e) { graph_release(g); delete g; return e; };
+    if ((s = graph_alloc_common(g, st)) != TPA_OK) return bail(s);
+    if ((s = dalloc(&g->a.rowptr, n + 1, st)) != TPA_OK || (s = dalloc(&g->a.col, m, st)) != TPA_OK ||
+        (s = dalloc(&g->t.rowptr, n + 1, st)) != TPA_OK || (s = dalloc(&g->t.col, m, st)) != TPA_OK ||
+        (s = dalloc(&g->inv_deg, n, st)) != TPA_OK || (s = dalloc(&g->padded, n, st)) != TPA_OK ||
+        (s = dalloc(&g->node_block, n, st)) != TPA_OK || (s = dalloc(&g->restart_pr, n, st)) != TPA_OK)
+        return bail(s);
+    g->nblocks = count;
+    g->block_off.assign(count + 1, 0);
+    int64_t no = 0, eo = 0;
+    for (int i = 0; i < count; ++i) {
+        const tpa_graph *h = gs[i];
+        offset_i64_kernel<<<grid_for(h->n), kBlock, 0, st>>>(h->a.rowptr, h->n, eo, g->a.rowptr + no);
+        offset_i64_kernel<<<grid_for(h->n), kBlock, 0, st>>>(h->t.rowptr, h->n, eo, g->t.rowptr + no);
+        offset_i32_kernel<<<grid_for(h->m), kBlock, 0, st>>>(h->a.col, h->m, (int32_t)no, g->a.col + eo);
+        offset_i32_kernel<<<grid_for(h->m), kBlock, 0, st>>>(h->t.col, h->m, (int32_t)no, g->t.col + eo);
+        if (hipMemcpyAsync(g->inv_deg + no, h->inv_deg, sizeof(float) * h->n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(g->padded + no, h->padded, h->n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return bail(fail(TPA_ERR_HIP, "pack copy failed"));
+        fill_block_kernel<<<grid_for(h->n), kBlock, 0, st>>>(g->node_block, g->restart_pr, no, h->n, i,
+                                                            (float)(1.0 / (double)h->n));
+        no += h->n;
+        eo += h->m;
+        g->block_off[i + 1] = no;
+    }
+    const int64_t tail[1] = {m};
+    TPA_TRY_HIP(hipMemcpyAsync(g->a.rowptr + n, tail, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    TPA_TRY_HIP(hipMemcpyAsync(g->t.rowptr + n, tail, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    TPA_TRY_HIP(hipGetLastError());
+    *out = g;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_destroy(tpa_graph_t g) {
+    if (!g) return TPA_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    graph_release(g);
+    if (cur != g->device) (void)hipSetDevice(cur);
+    delete g;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_info(tpa_graph_t g, int64_t *n, int64_t *m, int64_t *nblocks) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (nblocks) *nblocks = g->nblocks;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_blocks(tpa_graph_t g, int64_t *offsets) {
+    if (!g || !offsets) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    std::copy(g->block_off.begin(), g->block_off.end(), offsets);
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_export(tpa_graph_t g, int transpose, int64_t *row_ptr, int32_t *col,
+                                       float *w, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    const Csr &c = transpose ? g->t : g->a;
+    if (row_ptr)
+        TPA_TRY_HIP(hipMemcpyAsync(row_ptr, c.rowptr, sizeof(int64_t) * (g->n + 1), hipMemcpyDeviceToDevice, st));
+    if (col) TPA_TRY_HIP(hipMemcpyAsync(col, c.col, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, st));
+    if (w) {
+        if (c.w) {
+            TPA_TRY_HIP(hipMemcpyAsync(w, c.w, sizeof(float) * g->m, hipMemcpyDeviceToDevice, st));
+        } else {
+            uniform_w_kernel<<<grid_for(g->n), kBlock, 0, st>>>(c.rowptr, c.col, g->inv_deg, g->n, transpose, w);
+            TPA_TRY_HIP(hipGetLastError());
+        }
+    }
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_padded(tpa_graph_t g, uint8_t *mask, hipStream_t st) {
+    if (!g || !mask) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    TPA_TRY_HIP(hipMemcpyAsync(mask, g->padded, g->n, hipMemcpyDeviceToDevice, st));
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    g->preprocessed = false;
+    if (!theta) {
+        dfree(g->a.w); dfree(g->t.w);
+        g->a.w = g->t.w = nullptr;
+        g->weighted = false;
+        return TPA_OK;
+    }
+    TPA_TRY(ensure_t2a(g, st));
+    if (!g->a.w) TPA_TRY(dalloc(&g->a.w, g->m, st));
+    if (!g->t.w) TPA_TRY(dalloc(&g->t.w, g->m, st));
+    const int64_t threads = g->n * 64;
+    softmax_rows_kernel<<<grid_for(threads), kBlock, 0, st>>>(g->a.rowptr, g->n, theta, g->a.w);
+    gather_w_kernel<<<grid_for(g->m), kBlock, 0, st>>>(g->a.w, g->t2a, g->m, g->t.w);
+    TPA_TRY_HIP(hipGetLastError());
+    g->weighted = true;
+    return TPA_OK;
+}

@@ -1,0 +1,284 @@
+// C ABI of the TPA hot path: preprocessing (Algorithm 2) and the online
+// phase (Algorithm 3), driving the CPI step kernels.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "cpi_kernels.h"
+#include "tpa_internal.h"
+
+namespace tpa {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+tpa_status fail(tpa_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+tpa_status dmalloc(void **p, size_t bytes, hipStream_t stream) {
+    *p = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(TPA_ERR_CAPTURE, "device allocation requested while the stream is capturing");
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? TPA_ERR_OUT_OF_MEMORY : TPA_ERR_HIP,
+                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    return TPA_OK;
+}
+
+void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+
+namespace {
+
+constexpr int kDefaultEW = 256;
+
+// First i >= 1 with c (1-c)^i < eps: Algorithm 1's L1 break, with the
+// per-block norm ||x'(i)||_1 = c (1-c)^i of Lemma 2.
+int64_t stranger_last_iteration(double c, double eps) {
+    double norm = c;
+    for (int64_t i = 1; i < 100000; ++i) {
+        norm = c * std::pow(1.0 - c, (double)i);
+        if (norm < eps) return i;
+    }
+    return 100000;
+}
+
+int choose_ew(const tpa_graph *g) { return g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW; }
+
+int choose_kt(const tpa_graph *g, int64_t k) {
+    if (g->seed_tile > 0) return g->seed_tile;
+    if (k <= 1) return 1;
+    int kt = 2;
+    while (kt < k && kt < 16) kt <<= 1;
+    return kt;
+}
+
+// Workspace layout (floats): z0 [n*kt] | z1 [n*kt] | partials [slots*kt] | seeds (int32) [k]
+size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, int64_t k) {
+    const size_t zf = (size_t)g->n * kt;
+    const size_t pf = (size_t)std::max<int64_t>(s->n_slots, 1) * kt;
+    return sizeof(float) * (2 * zf + pf) + sizeof(int32_t) * (size_t)std::max<int64_t>(k, 1) + 256;
+}
+
+tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
+    if (g->ws_bytes >= bytes) return TPA_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(TPA_ERR_CAPTURE, "query workspace too small during stream capture; call tpa_reserve first");
+    if (g->ws) {
+        TPA_TRY_HIP(hipStreamSynchronize(st));
+        dfree(g->ws);
+        g->ws = nullptr;
+        g->ws_bytes = 0;
+    }
+    TPA_TRY(dmalloc(reinterpret_cast<void **>(&g->ws), bytes, st));
+    g->ws_bytes = bytes;
+    return TPA_OK;
+}
+
+tpa_status check_query_args(tpa_graph *g, double c, int S, int T) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (!g->preprocessed) return fail(TPA_ERR_NOT_PREPROCESSED, "tpa_preprocess has not run on this graph");
+    if (!(c > 0.0 && c < 1.0)) return fail(TPA_ERR_INVALID_ARG, "c must lie in (0, 1)");
+    if (S < 1) return fail(TPA_ERR_INVALID_ARG, "S must be >= 1");
+    if (T < S) return fail(TPA_ERR_INVALID_ARG, "T must be >= S");
+    if (c != g->c || T != g->T)
+        return fail(TPA_ERR_PARAM_MISMATCH, "query (c, T) differs from the preprocessed (c, T)");
+    return TPA_OK;
+}
+
+// Shared driver: `k` columns, seeds [k] (plain) or [nblocks][k] (packed).
+tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed, double c, int S, int T,
+                     float *out, hipStream_t st) {
+    TPA_TRY(check_query_args(g, c, S, T));
+    if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
+    if (k == 0) return TPA_OK;
+    if (!seeds || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/out is NULL");
+    if (packed && !g->node_block) return fail(TPA_ERR_INVALID_ARG, "graph is not packed");
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_ew(g), st, &s));
+    const int kt = choose_kt(g, k);
+    const int64_t nseeds = packed ? k * g->nblocks : k;
+    TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt, nseeds), st));
+    float *z0 = g->ws;
+    float *z1 = z0 + (size_t)g->n * kt;
+    float *part = z1 + (size_t)g->n * kt;
+    int32_t *sws = reinterpret_cast<int32_t *>(part + (size_t)std::max<int64_t>(s->n_slots, 1) * kt);
+    TPA_TRY(launch_check_seeds(seeds, nseeds, packed ? (int)k : 0, g, sws, st));
+
+    const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
+    StepParams p;
+    p.rowptr = g->t.rowptr;
+    p.col = g->t.col;
+    p.w = g->weighted ? g->t.w : nullptr;
+    p.inv = g->inv_deg;
+    p.partials = part;
+    p.omc = (float)(1.0 - c);
+    p.c = (float)c;
+    p.kt = kt;
+    p.node_block = packed ? g->node_block : nullptr;
+    p.seed_stride = packed ? (int)k : 0;
+    p.alpha = (float)((1.0 - pT) / (1.0 - pS));  // 1 + neighbor scale
+    p.str = g->str;
+    p.out = out;
+    p.n = g->n;
+    for (int64_t base = 0; base < k; base += kt) {
+        p.seeds = sws + base;
+        p.ncols = (int)std::min<int64_t>(kt, k - base);
+        p.out_col0 = base;
+        if (S == 1) {
+            p.last = 1;
+            TPA_TRY(launch_combine_only(p, st));
+            continue;
+        }
+        for (int step = 1; step <= S - 1; ++step) {
+            p.zin = (step & 1) ? z0 : z1;
+            p.zout = (step & 1) ? z1 : z0;
+            p.last = step == S - 1;
+            TPA_TRY(launch_step(*s, kFamily, step == 1, p, st));
+        }
+    }
+    return TPA_OK;
+}
+
+}  // namespace
+}  // namespace tpa
+
+using namespace tpa;
+
+extern "C" const char *tpa_status_string(tpa_status s) {
+    switch (s) {
+        case TPA_OK: return "ok";
+        case TPA_ERR_INVALID_ARG: return "invalid argument";
+        case TPA_ERR_NOT_PREPROCESSED: return "graph not preprocessed";
+        case TPA_ERR_PARAM_MISMATCH: return "query parameters differ from preprocessing";
+        case TPA_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case TPA_ERR_HIP: return "HIP runtime error";
+        case TPA_ERR_INDEX_OVERFLOW: return "index overflow";
+        case TPA_ERR_CAPTURE: return "allocation needed during stream capture";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *tpa_last_error_message(void) { return g_last_error.c_str(); }
+
+extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double eps, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (!(c > 0.0 && c < 1.0)) return fail(TPA_ERR_INVALID_ARG, "c must lie in (0, 1)");
+    if (T < 0) return fail(TPA_ERR_INVALID_ARG, "T must be >= 0");
+    if (!(eps > 0.0)) return fail(TPA_ERR_INVALID_ARG, "eps must be > 0");
+    g->preprocessed = false;
+    const int64_t K = stranger_last_iteration(c, eps);
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_ew(g), st, &s));
+    if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
+    float *tmp = nullptr;
+    const size_t n = (size_t)g->n;
+    TPA_TRY(dalloc(&tmp, 3 * n + (size_t)std::max<int64_t>(s->n_slots, 1), st));
+    float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
+    tpa_status rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, st);
+    StepParams p;
+    p.rowptr = g->t.rowptr;
+    p.col = g->t.col;
+    p.w = g->weighted ? g->t.w : nullptr;
+    p.inv = g->inv_deg;
+    p.partials = part;
+    p.omc = (float)(1.0 - c);
+    p.c = (float)c;
+    p.kt = 1;
+    p.n = g->n;
+    p.acc = g->str;
+    p.comp = comp;
+    for (int64_t i = 1; rc == TPA_OK && i <= K; ++i) {
+        p.zin = (i & 1) ? z0 : z1;
+        p.zout = (i & 1) ? z1 : z0;
+        p.accumulate = i >= T;
+        rc = launch_step(*s, kStranger, false, p, st);
+    }
+    hipError_t e = hipStreamSynchronize(st);
+    dfree(tmp);
+    if (rc != TPA_OK) return rc;
+    TPA_TRY_HIP(e);
+    g->c = c;
+    g->T = T;
+    g->eps = eps;
+    g->K = K;
+    g->preprocessed = true;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_preprocess(tpa_graph_t g, double c, int T, hipStream_t st) {
+    return tpa_preprocess_ex(g, c, T, 1e-9, st);
+}
+
+extern "C" tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t st) {
+    if (!g || !out) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    if (!g->preprocessed) return fail(TPA_ERR_NOT_PREPROCESSED, "tpa_preprocess has not run on this graph");
+    TPA_TRY_HIP(hipMemcpyAsync(out, g->str, sizeof(float) * g->n, hipMemcpyDeviceToDevice, st));
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
+                                float *out, hipStream_t st) {
+    return run_query(g, seeds, k, false, c, S, T, out, st);
+}
+
+extern "C" tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, double c, int S,
+                                       int T, float *out, hipStream_t st) {
+    if (per_block < 1) return fail(TPA_ERR_INVALID_ARG, "per_block must be >= 1");
+    return run_query(g, seeds, per_block, true, c, S, T, out, st);
+}
+
+extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
+    if (!g || k < 0) return fail(TPA_ERR_INVALID_ARG, "bad argument");
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_ew(g), nullptr, &s));
+    const int kt = choose_kt(g, k);
+    return ensure_ws(g, query_ws_bytes(g, s, kt, std::max<int64_t>(k, 1) * g->nblocks), nullptr);
+}
+
+extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (seed_tile != 0 && seed_tile != 1 && seed_tile != 2 && seed_tile != 4 && seed_tile != 8 &&
+        seed_tile != 16 && seed_tile != 32 && seed_tile != 64)
+        return fail(TPA_ERR_INVALID_ARG, "seed tile must be 0, 1, 2, 4, 8, 16, 32 or 64");
+    if (edges_per_item != 0 && (edges_per_item < 64 || edges_per_item > 4096 || edges_per_item % 64))
+        return fail(TPA_ERR_INVALID_ARG, "edges per item must be 0 or a multiple of 64 in 64..4096");
+    g->seed_tile = seed_tile;
+    g->edges_per_item = edges_per_item;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (seed_tile) *seed_tile = g->seed_tile;
+    if (edges_per_item) *edges_per_item = g->edges_per_item;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    int32_t v = 0;
+    TPA_TRY_HIP(hipMemcpyAsync(&v, g->dev_err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    if (v) {
+        TPA_TRY_HIP(hipMemsetAsync(g->dev_err, 0, sizeof(int32_t), st));
+        TPA_TRY_HIP(hipStreamSynchronize(st));
+        return fail(TPA_ERR_INVALID_ARG, "a query saw a seed outside [0, n) or outside its block");
+    }
+    return TPA_OK;
+}

@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP sources of libtpa.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "tpa.h"
+
+namespace tpa {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+
+#define TPA_TRY_HIP(expr)                                                        \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            ::tpa::set_error(std::string(#expr) + ": " + hipGetErrorString(e_)); \
+            return e_ == hipErrorOutOfMemory ? TPA_ERR_OUT_OF_MEMORY : TPA_ERR_HIP; \
+        }                                                                        \
+    } while (0)
+
+#define TPA_TRY(expr)                    \
+    do {                                 \
+        tpa_status s_ = (expr);          \
+        if (s_ != TPA_OK) return s_;     \
+    } while (0)
+
+tpa_status fail(tpa_status s, const std::string &msg);
+
+// Device allocation that reports OOM as a status (refuses during capture).
+tpa_status dmalloc(void **p, size_t bytes, hipStream_t stream);
+template <class T>
+tpa_status dalloc(T **p, size_t count, hipStream_t stream) {
+    return dmalloc(reinterpret_cast<void **>(p), count * sizeof(T), stream);
+}
+void dfree(void *p);
+
+// ---------------------------------------------------------------- schedule
+// A wave work item over one CSR orientation.
+//   chunk == -1 : rows [row0, row1) (at most 64 rows, fewer than 2*EW edges)
+//   chunk == -2 : the single row row0, processed whole by one wave
+//   chunk >=  0 : chunk `chunk` (EL edges) of the long row row0; its partial
+//                 sum goes to slot `slot` and a finish pass adds the chunks
+struct Item {
+    int32_t row0, row1, chunk, slot;
+};
+struct LongRow {
+    int32_t row, nchunks, slot0, pad;
+};
+
+struct Schedule {
+    int ew = 0, el = 0;
+    Item *items = nullptr;       // device
+    int64_t n_items = 0;
+    LongRow *longs = nullptr;    // device
+    int64_t n_long = 0;
+    int64_t n_slots = 0;
+    int64_t max_chunks = 0;
+    void release();
+};
+
+struct Csr {
+    int64_t *rowptr = nullptr;  // n+1
+    int32_t *col = nullptr;     // m
+    float *w = nullptr;         // m, only when weights are not 1/outdeg
+};
+
+}  // namespace tpa
+
+struct tpa_graph {
+    int device = 0;
+    int64_t n = 0, m = 0;
+    int bits = 1;                           // bits of a node id (key packing)
+    int64_t nblocks = 1;
+    std::vector<int64_t> block_off;         // host, nblocks+1
+    int32_t *node_block = nullptr;          // device, n (only when nblocks > 1)
+    float *restart_pr = nullptr;            // device, n: 1/n_block(v) (packed only)
+
+    tpa::Csr a;                             // A~   (rows = sources)
+    tpa::Csr t;                             // A~^T (rows = destinations)
+    int64_t *t2a = nullptr;                 // A~^T entry -> A~ entry (lazy)
+    float *inv_deg = nullptr;               // 1/outdeg(u), FP32
+    uint8_t *padded = nullptr;
+    bool weighted = false;                  // weights from logits (a.w, t.w set)
+
+    // preprocessing state
+    bool preprocessed = false;
+    double c = 0.0, eps = 0.0;
+    int T = 0;
+    int64_t K = 0;
+    float *str = nullptr;                   // r~_stranger, n
+
+    // schedules over A~^T keyed by edges-per-item
+    std::map<int, tpa::Schedule> sched_t;
+
+    // query workspace
+    float *ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t *dev_err = nullptr;             // sticky device error flag
+
+    // tuning
+    int seed_tile = 0;                      // 0 = automatic
+    int edges_per_item = 0;                 // 0 = automatic
+};
+
+namespace tpa {
+
+tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);
+tpa_status get_schedule(tpa_graph *g, int ew, hipStream_t stream, const Schedule **out);
+tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
+tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
+void graph_release(tpa_graph *g);
+int key_bits(int64_t n);
+
+}  // namespace tpa

@@ -1,0 +1,276 @@
+"""HIP path vs the FP64 oracle, through the C ABI.
+
+Integer graph construction must be bit-exact; r_TPA must agree within
+L1 <= 1e-5 per seed (FP32 values and accumulation on the device).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tpa_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+c, S, T, EPS = ti.C, ti.S, ti.T, ti.EPS
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def tpa(torch):
+    import paper_1708_02574_amd as _tpa
+    _tpa.load_library()
+    return _tpa
+
+
+@pytest.fixture(scope="module")
+def rmat13(tpa):
+    scale, samples, seed = ti.GRAPHS["rmat13"]
+    og = oracle.Graph.rmat(scale, samples, seed)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(scale, samples, seed)
+    gg.preprocess(c, T)
+    return og, gg
+
+
+def l1_rows(a, b):
+    return np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum(axis=-1)
+
+
+def compare_graph(og, gg, torch):
+    ex = og.export()
+    rp, col, w = gg.export(transpose=False)
+    trp, tcol, tw = gg.export(transpose=True)
+    torch.cuda.synchronize()
+    assert gg.n == og.n and gg.m == og.m
+    assert np.array_equal(rp.cpu().numpy(), ex["a_rowptr"])
+    assert np.array_equal(col.cpu().numpy(), ex["a_col"])
+    assert np.array_equal(trp.cpu().numpy(), ex["t_rowptr"])
+    assert np.array_equal(tcol.cpu().numpy(), ex["t_col"])
+    assert np.array_equal(gg.padded().cpu().numpy(), ex["padded"])
+    deg = np.diff(ex["a_rowptr"]).astype(np.float32)
+    w_expect = (np.float32(1.0) / deg)[np.repeat(np.arange(og.n), np.diff(ex["a_rowptr"]))]
+    assert np.array_equal(w.cpu().numpy(), w_expect)  # IEEE FP32 division, bit for bit
+    assert np.array_equal(tw.cpu().numpy(), w_expect[ex["t2a"]])
+
+
+# ---------------------------------------------------------------- graph store
+def test_rmat13_graph_bit_exact(rmat13, torch):
+    og, gg = rmat13
+    compare_graph(og, gg, torch)
+
+
+def test_rmat_rejection_graph_bit_exact(tpa, torch):
+    og = oracle.Graph.rmat(12, 48000, 0xABC, n_nodes=3000)
+    gg = tpa.Graph.rmat(12, 48000, 0xABC, n_nodes=3000)
+    compare_graph(og, gg, torch)
+
+
+@pytest.mark.parametrize("device_edges", [False, True])
+def test_from_edges_bit_exact(tpa, torch, device_edges):
+    r = np.random.default_rng(5)
+    n, m = 1000, 6000
+    src = r.integers(0, n, m).astype(np.int32)
+    dst = r.integers(0, n, m).astype(np.int32)
+    src[:500] = src[500:1000]          # duplicates
+    dst[:500] = dst[500:1000]
+    src[src % 7 == 3] = 0              # many nodes without out-edges
+    og = oracle.Graph(n, src, dst)
+    if device_edges:
+        gg = tpa.Graph.from_edges(n, torch.from_numpy(src).cuda(), torch.from_numpy(dst).cuda())
+    else:
+        gg = tpa.Graph.from_edges(n, src, dst)
+    compare_graph(og, gg, torch)
+
+
+def test_from_edges_rejects_bad_ids(tpa):
+    with pytest.raises(tpa.TPAError) as e:
+        tpa.Graph.from_edges(10, np.array([1, 2], np.int32), np.array([3, 10], np.int32))
+    assert e.value.status == -1
+
+
+# ---------------------------------------------------------------- preprocess
+def test_stranger_parity(rmat13, torch):
+    og, gg = rmat13
+    st = gg.stranger().cpu().numpy()
+    assert l1_rows(st, og.str) <= TOL
+    assert st.min() >= 0
+
+
+@pytest.mark.parametrize("Tq", [0, 1, 10, 30])
+def test_stranger_parity_various_T(tpa, torch, Tq):
+    og = oracle.Graph.rmat(10, 12000, 3)
+    ost = og.preprocess(c, Tq, EPS)
+    gg = tpa.Graph.rmat(10, 12000, 3)
+    gg.preprocess(c, Tq)
+    assert l1_rows(gg.stranger().cpu().numpy(), ost) <= TOL
+
+
+# ---------------------------------------------------------------- queries
+def seeds_for(og, k, seed):
+    return ti.draw_seeds(og.export()["padded"] == 0, k, seed)
+
+
+def test_single_seed_queries(rmat13, torch):
+    og, gg = rmat13
+    seeds = seeds_for(og, 12, 101)
+    for s in seeds:
+        r = gg.query(torch.tensor([s]), c, S, T).cpu().numpy()[0]
+        assert l1_rows(r, og.query(int(s), c, S, T)) <= TOL
+
+
+@pytest.mark.parametrize("k,kt", [(1, 1), (3, 2), (17, 4), (64, 8), (100, 16), (70, 32), (130, 64), (5, 0)])
+def test_batched_queries(rmat13, torch, k, kt):
+    og, gg = rmat13
+    seeds = seeds_for(og, k, 7 + k)
+    gg.set_tuning(seed_tile=kt)
+    try:
+        R = gg.query(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+    finally:
+        gg.set_tuning(0, 0)
+    expect = np.stack([og.query(int(s), c, S, T) for s in seeds])
+    assert np.all(l1_rows(R, expect) <= TOL)
+
+
+@pytest.mark.parametrize("ew", [64, 128, 1024])
+@pytest.mark.parametrize("kt", [1, 4])
+def test_schedules_with_long_rows(rmat13, torch, ew, kt):
+    """Small edges-per-item makes the hub rows of A~^T long (chunks + finish)."""
+    og, gg = rmat13
+    seeds = seeds_for(og, 9, 55)
+    gg.set_tuning(seed_tile=kt, edges_per_item=ew)
+    try:
+        R = gg.query(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+    finally:
+        gg.set_tuning(0, 0)
+    expect = np.stack([og.query(int(s), c, S, T) for s in seeds])
+    assert np.all(l1_rows(R, expect) <= TOL)
+
+
+@pytest.mark.parametrize("Sq,Tq", [(1, 10), (2, 10), (5, 5), (3, 7), (8, 10)])
+def test_query_S_T_cases(tpa, torch, Sq, Tq):
+    og = oracle.Graph.rmat(11, 30000, 17)
+    og.preprocess(c, Tq, EPS)
+    gg = tpa.Graph.rmat(11, 30000, 17)
+    gg.preprocess(c, Tq)
+    seeds = seeds_for(og, 6, 3)
+    R = gg.query(torch.from_numpy(seeds), c, Sq, Tq).cpu().numpy()
+    expect = np.stack([og.query(int(s), c, Sq, Tq) for s in seeds])
+    assert np.all(l1_rows(R, expect) <= TOL)
+
+
+def test_dangling_seed_and_hub_seed(rmat13, torch):
+    og, gg = rmat13
+    ex = og.export()
+    dangling = int(np.flatnonzero(ex["padded"])[0])
+    hub = int(np.argmax(np.diff(ex["a_rowptr"])))
+    for s in (dangling, hub, 0, og.n - 1):
+        r = gg.query(torch.tensor([s]), c, S, T).cpu().numpy()[0]
+        assert l1_rows(r, og.query(s, c, S, T)) <= TOL
+
+
+def test_mass_and_determinism(rmat13, torch):
+    og, gg = rmat13
+    seeds = torch.from_numpy(seeds_for(og, 40, 9))
+    a = gg.query(seeds, c, S, T)
+    b = gg.query(seeds, c, S, T)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    mass = a.double().sum(dim=1).cpu().numpy()
+    assert np.all(np.abs(mass - (1 - (1 - c) ** 117)) < 1e-5)
+
+
+def test_cycle_closed_form_on_gpu(tpa, torch):
+    n = 200
+    src = np.arange(n, dtype=np.int32)
+    dst = ((np.arange(n) + 1) % n).astype(np.int32)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    gg.preprocess(c, T)
+    K = 116
+    st = gg.stranger().cpu().numpy()
+    assert np.allclose(st, ((1 - c) ** T - (1 - c) ** (K + 1)) / n, rtol=1e-5, atol=0)
+    r = gg.query(torch.tensor([190]), c, S, T).cpu().numpy()[0]
+    alpha = (1 - (1 - c) ** T) / (1 - (1 - c) ** S)
+    expect = st.astype(np.float64).copy()
+    for j in range(S):
+        expect[(190 + j) % n] += alpha * c * (1 - c) ** j
+    assert l1_rows(r, expect) <= TOL
+
+
+# ---------------------------------------------------------------- packed
+def test_packed_blocks_equal_separate_graphs(tpa, torch):
+    params = [(9, 4000, 1, 400), (10, 9000, 2, 0), (8, 1500, 3, 200)]
+    ogs, ggs = [], []
+    for scale, samples, seed, nn in params:
+        n_nodes = nn or (1 << scale)
+        og = oracle.Graph.rmat(scale, samples, seed, n_nodes=n_nodes)
+        og.preprocess(c, T, EPS)
+        ogs.append(og)
+        ggs.append(tpa.Graph.rmat(scale, samples, seed, n_nodes=n_nodes))
+    pk = tpa.Graph.pack(ggs)
+    off = pk.block_offsets()
+    assert pk.nblocks == 3 and off[-1] == pk.n
+    pk.preprocess(c, T)
+    st = pk.stranger().cpu().numpy()
+    P = 4
+    seeds = np.stack([off[b] + seeds_for(ogs[b], P, 20 + b) for b in range(3)]).astype(np.int32)
+    for kt in (1, 4, 0):
+        pk.set_tuning(seed_tile=kt)
+        R = pk.query_packed(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+        for b, og in enumerate(ogs):
+            lo, hi = off[b], off[b + 1]
+            assert l1_rows(st[lo:hi], og.str) <= TOL
+            for j in range(P):
+                assert l1_rows(R[j, lo:hi], og.query(int(seeds[b, j] - lo), c, S, T)) <= TOL
+
+
+# ---------------------------------------------------------------- weights
+def test_logit_weights_forward(tpa, torch):
+    og = oracle.Graph.rmat(10, 12000, 21)
+    gg = tpa.Graph.rmat(10, 12000, 21)
+    theta = ti.draw_logits(og.m, 4)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    _, _, w = gg.export()
+    assert np.abs(w.cpu().numpy() - og.export()["a_w"]).max() < 1e-6
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
+    seeds = seeds_for(og, 8, 1)
+    for kt in (1, 8):
+        gg.set_tuning(seed_tile=kt)
+        R = gg.query(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+        expect = np.stack([og.query(int(s), c, S, T) for s in seeds])
+        assert np.all(l1_rows(R, expect) <= TOL)
+
+
+# ---------------------------------------------------------------- errors
+def test_query_errors(tpa, torch):
+    gg = tpa.Graph.rmat(8, 2000, 1)
+    s = torch.tensor([1], dtype=torch.int32)
+    with pytest.raises(tpa.TPAError) as e:
+        gg.query(s, c, S, T)
+    assert e.value.status == -2
+    gg.preprocess(c, T)
+    for args, code in (((0.2, S, T), -3), ((c, S, 12), -3), ((c, 0, T), -1), ((c, 6, 5), -1), ((1.5, S, T), -1)):
+        with pytest.raises(tpa.TPAError) as e:
+            gg.query(s, *args)
+        assert e.value.status == code
+    gg.query(s, c, S, T)  # still usable
+
+
+def test_bad_seed_gives_nan_row_and_sticky_error(tpa, torch):
+    gg = tpa.Graph.rmat(8, 2000, 1)
+    gg.preprocess(c, T)
+    R = gg.query(torch.tensor([3, 256, -1, 7], dtype=torch.int32), c, S, T).cpu().numpy()
+    assert np.all(np.isnan(R[1])) and np.all(np.isnan(R[2]))
+    assert np.all(np.isfinite(R[0])) and np.all(np.isfinite(R[3]))
+    with pytest.raises(tpa.TPAError):
+        gg.device_error()
+    gg.device_error()  # cleared
