@@ -164,8 +164,9 @@ tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, 
 tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
 
 /* Query tuning: seed-tile width kt (seeds per SpMM pass: 1, 2, 4, 8, 16,
- * 32 or 64; 0 = automatic) and edges per wave work item (64..4096, a
- * multiple of 64; 0 = automatic). */
+ * 32 or 64; 0 = automatic) and the edge budget of a wave work item that
+ * groups short rows (64..512, a multiple of 64; 0 = automatic; rows longer
+ * than 8x the budget are split into chunks).  Applies to later calls. */
 tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item);
 tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
 

@@ -21,12 +21,12 @@ struct StepParams {
     const float *inv = nullptr;        // 1/outdeg (uniform weights)
     const float *zin = nullptr;        // gathered vector [n][kt]
     float *zout = nullptr;             // next gathered vector [n][kt]
-    float *partials = nullptr;         // [slots][kt] chunk sums of long rows
+    float *partials = nullptr;         // [chunk items][kt] chunk sums of long rows
     float omc = 0.f;                   // 1 - c
     float c = 0.f;
     int kt = 1;
     // family
-    const int32_t *seeds = nullptr;    // tile seeds; -1 inactive, -2 invalid
+    const int32_t *seeds = nullptr;    // tile seeds (caller memory; validated on the last step)
     const int32_t *node_block = nullptr;
     int seed_stride = 0;               // seeds per block (packed graphs)
     int ncols = 0;                     // active columns of this tile
@@ -36,6 +36,7 @@ struct StepParams {
     float *out = nullptr;              // seed-major [*, n]
     int64_t n = 0;
     int64_t out_col0 = 0;
+    int32_t *err = nullptr;            // sticky error flag (invalid seed)
     // stranger
     float *acc = nullptr;
     float *comp = nullptr;
@@ -50,11 +51,10 @@ tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, flo
                                 float *comp, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
+// A seed outside [0, n) (or outside its block on a packed graph) gives a
+// NaN output column and raises the sticky error flag, here and on the last
+// CPI step.
 tpa_status launch_combine_only(const StepParams &p, hipStream_t st);
 
-// Validate seeds into `dst` (k entries): out of range, or outside its block
-// for packed graphs, becomes -2 and raises the sticky error flag.
-tpa_status launch_check_seeds(const int32_t *seeds, int64_t k, int per_block, const tpa_graph *g,
-                              int32_t *dst, hipStream_t st);
 
 }  // namespace tpa

@@ -1,28 +1,32 @@
 // CPI step kernels for gfx950.
 //
 // One CPI step (Section 2.3, Algorithm 1) is x(i) = (1-c) A~^T x(i-1): a
-// pull over the rows of A~^T, i.e. an irregular gather with about 2 flops
-// per 8 bytes.  It is bound by HBM (and by the gather's cache behaviour),
-// not by arithmetic, so there is no matrix-core work here; what matters is
-// coalesced index streams, enough loads in flight, and balance across
-// power-law rows.
+// pull over the rows of A~^T, an irregular gather with about 2 flops per
+// 8 bytes.  It is bound by memory (HBM and the gather's cache behaviour),
+// not arithmetic, so there is no matrix-core work here; what matters is
+// coalesced index streams, many loads in flight per wave, and balance
+// across power-law rows.
 //
-// Work decomposition (built once per graph, see get_schedule): one wave
-// (64 lanes) per work item; four independent waves per 256-thread block.
-//   * short-row group (<= 64 rows, < 2*EW edges): the item's edges are read
-//     64 at a time, one per lane (coalesced index loads); each lane finds its
-//     row by a binary search over the row starts held across the wave, a
-//     segmented wave scan adds up each row's part of the strip, and the lane
-//     owning the row picks its total -- no LDS, no atomics;
-//   * whole row (EW..EL edges): one wave, lanes stride over the edges;
-//   * chunk of a long row (> EL edges): as above into a partial slot; a
-//     finish pass adds a row's chunk sums in chunk order.
-// All sums are in a fixed order, so results are bitwise reproducible.
+// Work decomposition (built once per graph, get_schedule): one wave (64
+// lanes) per work item, four independent waves per 256-thread block.
 //
-// Seed tiles (kt > 1 columns, node-major [n][kt] vectors): lanes are split
-// into 64/kt sub-groups of kt lanes; lane (sub, j) adds column j over every
-// (64/kt)-th edge of a row, so each gathered row segment of kt floats is one
-// contiguous access; sub-groups are then combined by xor shuffles.
+// Single vector (kt == 1):
+//   * group item (<= 63 rows, <= EW edges): the item's edges are read one
+//     per lane, 64 at a time, all strips issued before the first use
+//     (coalesced index loads, then the gathers); the products go to the
+//     wave's LDS slice; lane r then adds up row r's slice when the row has
+//     <= 32 edges, and the whole wave adds up each longer row;
+//   * row item: lanes stride over one row's edges, then a xor butterfly;
+//   * chunk item (rows longer than EL): as a row item into a partial slot;
+//     a finish pass (second launch, only when such rows exist) adds each
+//     long row's partials in chunk order and applies the epilogue.
+// Seed tile of 64 (kt == 64, one column per lane): the wave walks its
+//   item's edges in order with wave-uniform control; column ids are loaded
+//   64 at a time and broadcast with readlane, and 16 row gathers of 256 B
+//   (one per edge, contiguous across the lanes) are in flight at once.
+// Seed tiles of 2..32 (generic): lanes (sub, j) with 64/kt sub-groups add
+//   column j over every (64/kt)-th edge of a row; xor shuffles combine.
+// Every sum is taken in a fixed order: results are bitwise reproducible.
 
 #include <cmath>
 
@@ -33,173 +37,321 @@ namespace {
 
 constexpr int kWaves = 4;          // waves (items) per block
 constexpr int kThreads = 64 * kWaves;
+constexpr int kGroupMax = 512;     // max edges of a group item (LDS floats per wave)
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float qnan() { return __int_as_float(0x7fc00000); }
+
+// Seed of column j for the block of node v (plain graphs: one block).
 __device__ __forceinline__ int32_t seed_of(const StepParams &p, int64_t v, int j) {
     if (j >= p.ncols) return -1;
     const int64_t b = p.node_block ? (int64_t)p.node_block[v] * p.seed_stride : 0;
     return p.seeds[b + j];
 }
 
-// Epilogue for row v, column j, with pulled sum `sum`.
+__device__ __forceinline__ bool seed_valid(const StepParams &p, int64_t v, int32_t s) {
+    if (s < 0 || (int64_t)s >= p.n) return false;
+    return p.node_block ? p.node_block[s] == p.node_block[v] : true;
+}
+
+// Per-row operands of the epilogue, loadable ahead of the sum:
+//   family   a = r~_stranger[v] (last step) or 1/outdeg(v)
+//   stranger a = 1/outdeg(v), b = r~_stranger[v], c = Kahan compensation
+struct EpiPre {
+    float a = 0.f, b = 0.f, c = 0.f;
+};
+
 template <int MODE>
-__device__ __forceinline__ void epilogue(const StepParams &p, int64_t v, int j, float sum) {
+__device__ __forceinline__ EpiPre epi_load(const StepParams &p, int64_t v) {
+    EpiPre q;
+    if (MODE == kFamily) {
+        if (p.last) q.a = p.str[v];
+        else if (!p.w) q.a = p.inv[v];
+    } else {
+        if (!p.w) q.a = p.inv[v];
+        if (p.accumulate) {
+            q.b = p.acc[v];
+            q.c = p.comp[v];
+        }
+    }
+    return q;
+}
+
+__device__ __forceinline__ EpiPre epi_readlane(const EpiPre &q, int r) {
+    EpiPre o;
+    o.a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.a), r));
+    o.b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.b), r));
+    o.c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.c), r));
+    return o;
+}
+
+// Epilogue for row v, column j, with pulled sum `sum` and operands q.
+template <int MODE>
+__device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j, float sum, const EpiPre &q) {
     if (MODE == kFamily) {
         if (j >= p.ncols) return;
         const int32_t seed = seed_of(p, v, j);
         const float y = fmaf(p.omc, sum, (v == (int64_t)seed) ? p.c : 0.0f);
         if (p.last) {
-            const float o = (seed == -2) ? __int_as_float(0x7fc00000) : fmaf(p.alpha, y, p.str[v]);
+            float o;
+            if (seed_valid(p, v, seed)) {
+                o = fmaf(p.alpha, y, q.a);
+            } else {
+                o = qnan();
+                *p.err = 1;
+            }
             p.out[(p.out_col0 + j) * p.n + v] = o;
         } else {
-            p.zout[v * p.kt + j] = p.w ? y : y * p.inv[v];
+            p.zout[v * p.kt + j] = p.w ? y : y * q.a;
         }
     } else {
         const float x = p.omc * sum;
-        p.zout[v] = p.w ? x : x * p.inv[v];
+        p.zout[v] = p.w ? x : x * q.a;
         if (p.accumulate) {
             // Kahan-compensated r~_stranger += x
-            const float a = p.acc[v];
-            const float yk = x - p.comp[v];
-            const float t = a + yk;
-            p.comp[v] = (t - a) - yk;
+            const float yk = x - q.c;
+            const float t = q.b + yk;
+            p.comp[v] = (t - q.b) - yk;
             p.acc[v] = t;
         }
     }
 }
 
-// Value contributed by edge e (source u) to column j of a row whose seed is
-// `seed` (only used on the first family step, where x(0) = c e_seed).
-template <bool FIRST>
-__device__ __forceinline__ float edge_value(const StepParams &p, int64_t e, int32_t u, int j,
-                                            int32_t seed) {
+template <int MODE>
+__device__ __forceinline__ void epilogue(const StepParams &p, int64_t v, int j, float sum) {
+    epi_store<MODE>(p, v, j, sum, epi_load<MODE>(p, v));
+}
+
+// Contribution of edge e = (u -> row) to column j.  On the first family
+// step x(0) = c e_seed, so only the seed's own out-edges contribute and no
+// vector is gathered (the source is in the row's block, so its seed is
+// looked up through u).  Uniform weights: the gathered vector is already
+// scaled by 1/outdeg; explicit weights: multiply by w[e].
+template <bool FIRST, bool WEIGHTED, int KT>
+__device__ __forceinline__ float edge_value(const StepParams &p, int64_t e, int32_t u, int j) {
     if (FIRST) {
-        if (u != seed) return 0.0f;
-        return p.c * (p.w ? p.w[e] : p.inv[u]);
+        if (u != seed_of(p, u, j)) return 0.0f;
+        return p.c * (WEIGHTED ? p.w[e] : p.inv[u]);
     }
-    const float z = p.zin[(int64_t)u * p.kt + j];
-    return p.w ? p.w[e] * z : z;
+    const float z = p.zin[(int64_t)u * KT + j];
+    return WEIGHTED ? p.w[e] * z : z;
+}
+
+// Finish pass over long rows: add each row's chunk partials in chunk order
+// and apply the epilogue (a separate launch after the step kernel, so no
+// cross-workgroup synchronisation is needed inside the step).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
+                                                          StepParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_long) return;
+    const LongRow lr = longs[wid];
+    const int kt = p.kt;
+    if (kt == 1) {
+        float t = 0.0f;
+        for (int i = lane; i < lr.nchunks; i += 64) t += p.partials[(int64_t)lr.first_item + i];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) epilogue<MODE>(p, lr.row, 0, t);
+    } else {
+        for (int j = lane; j < kt; j += 64) {
+            float t = 0.0f;
+            for (int i = 0; i < lr.nchunks; ++i) t += p.partials[((int64_t)lr.first_item + i) * kt + j];
+            epilogue<MODE>(p, lr.row, j, t);
+        }
+    }
 }
 
 // ------------------------------------------------------------ kt == 1
-template <int MODE, bool FIRST>
-__device__ void short_group_1(const StepParams &p, const Item it, int lane) {
-    constexpr int UNR = 4;
-    const int r0 = it.row0, nrows = it.row1 - it.row0;
-    const int64_t e0 = p.rowptr[r0];
-    const int nnz = (int)(p.rowptr[it.row1] - e0);
-    const int lr = lane < nrows ? lane : nrows;
-    const int rel_start = (int)(p.rowptr[r0 + lr] - e0);
-    const int rel_end = lane < nrows ? (int)(p.rowptr[r0 + lane + 1] - e0) : rel_start;
-    const bool packed = p.node_block != nullptr;
-    int32_t seed_uniform = -1;
-    if (MODE == kFamily && FIRST && !packed) seed_uniform = p.seeds[0];
-    float acc = 0.0f;
+template <int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict__ items, int64_t n_items,
+                                                          StepParams p) {
+    __shared__ float lds[kWaves][kGroupMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items) return;
+    const Item it = items[wid];
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    const int32_t *col = p.col + it.e0;
+    if (kind == (int)kItemGroup) {
+        constexpr int NS = kGroupMax / 64;
+        const int nrows = (int)item_nrows(it.meta);
+        const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        // all index loads, the epilogue operands, then all gathers, then LDS
+        int32_t u[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = s * 64 + lane;
+            u[s] = e < nnz ? col[e] : -1;
+        }
+        EpiPre q;
+        if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
+        float v[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            v[s] = u[s] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + s * 64 + lane, u[s], 0) : 0.0f;
+        float *my = lds[wv];
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (s * 64 < nnz) my[s * 64 + lane] = v[s];
+        const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
+        wave_sync();
+        // rows of <= 32 edges: lane r adds row r's slice; longer rows: the
+        // whole wave strides over the slice, then a xor butterfly
+        const int len = rel_next - rel;
+        if (lane < nrows && len <= 32) {
+            float acc = 0.0f;
+            for (int k = rel; k < rel_next; ++k) acc += my[k];
+            epi_store<MODE>(p, it.row0 + lane, 0, acc, q);
+        }
+        uint64_t big = __ballot(lane < nrows && len > 32);
+        while (big) {
+            const int r = __builtin_ctzll(big);
+            big &= big - 1;
+            const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel_next, r);
+            const EpiPre qr = epi_readlane(q, r);
+            float t = 0.0f;
+            for (int k = b + lane; k < en; k += 64) t += my[k];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) epi_store<MODE>(p, it.row0 + r, 0, t, qr);
+        }
+        return;
+    }
+    // one row, or one chunk of a long row
+    constexpr int UNR = 16;
+    EpiPre q;
+    if (kind == (int)kItemRow && lane == 0) q = epi_load<MODE>(p, it.row0);
+    float s = 0.0f;
     for (int base = 0; base < nnz; base += 64 * UNR) {
         int32_t u[UNR];
 #pragma unroll
-        for (int s = 0; s < UNR; ++s) {
-            const int e = base + s * 64 + lane;
-            u[s] = (e < nnz) ? p.col[e0 + e] : -1;
-        }
-        float val[UNR];
-        if (!FIRST) {
-#pragma unroll
-            for (int s = 0; s < UNR; ++s) {
-                const int e = base + s * 64 + lane;
-                val[s] = (u[s] >= 0) ? edge_value<false>(p, e0 + e, u[s], 0, -1) : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < UNR; ++s) {
-            const int sb = base + s * 64;
-            if (sb >= nnz) break;
-            const int e = sb + lane;
-            // row of edge e: largest row j with start_j <= e
-            int lo = 0;
-#pragma unroll
-            for (int step = 32; step >= 1; step >>= 1) {
-                const int mid = lo + step;
-                const int sm = __shfl(rel_start, mid, 64);
-                if (mid < nrows && sm <= e) lo = mid;
-            }
-            float v;
-            if (FIRST) {
-                int32_t seed = seed_uniform;
-                if (packed) seed = seed_of(p, r0 + lo, 0);
-                v = (u[s] >= 0) ? edge_value<true>(p, e0 + e, u[s], 0, seed) : 0.0f;
-            } else {
-                v = val[s];
-            }
-            // segmented inclusive scan over the strip (rows are contiguous)
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const float t = __shfl_up(v, d, 64);
-                const int rr = __shfl_up(lo, d, 64);
-                if (lane >= d && rr == lo) v += t;
-            }
-            // the lane owning a row picks the scan value at its last edge in the strip
-            const int send = min(sb + 64, nnz);
-            const bool hit = lane < nrows && rel_end > rel_start && rel_start < send && rel_end > sb;
-            const int tail = min(rel_end, send) - 1 - sb;
-            const float got = __shfl(v, hit ? tail : 0, 64);
-            if (hit) acc += got;
-        }
-    }
-    if (lane < nrows) epilogue<MODE>(p, r0 + lane, 0, acc);
-}
-
-template <int MODE, bool FIRST>
-__device__ void single_row_1(const StepParams &p, const Item it, int lane, int el) {
-    constexpr int UNR = 8;
-    const int64_t row = it.row0;
-    int64_t e0 = p.rowptr[row], e1 = p.rowptr[row + 1];
-    if (it.chunk >= 0) {
-        e0 += (int64_t)it.chunk * el;
-        e1 = min(e1, e0 + (int64_t)el);
-    }
-    int32_t seed = -1;
-    if (MODE == kFamily && FIRST) seed = seed_of(p, row, 0);
-    float s = 0.0f;
-    for (int64_t base = e0; base < e1; base += 64 * UNR) {
-        int32_t u[UNR];
-#pragma unroll
         for (int k = 0; k < UNR; ++k) {
-            const int64_t e = base + k * 64 + lane;
-            u[k] = (e < e1) ? p.col[e] : -1;
+            const int e = base + k * 64 + lane;
+            u[k] = e < nnz ? col[e] : -1;
         }
+        float v[UNR];
 #pragma unroll
-        for (int k = 0; k < UNR; ++k) {
-            const int64_t e = base + k * 64 + lane;
-            if (u[k] >= 0) s += edge_value<FIRST>(p, e, u[k], 0, seed);
-        }
+        for (int k = 0; k < UNR; ++k)
+            v[k] = u[k] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + base + k * 64 + lane, u[k], 0) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) s += v[k];
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
-        if (it.chunk >= 0)
-            p.partials[it.slot] = s;
+        if (kind == (int)kItemRow)
+            epi_store<MODE>(p, it.row0, 0, s, q);
         else
-            epilogue<MODE>(p, row, 0, s);
+            p.partials[wid] = s;
     }
 }
 
-template <int MODE, bool FIRST>
-__global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *items, int64_t n_items, int el,
-                                                          StepParams p) {
+// ------------------------------------------------------------ kt == 64
+// Value of one edge for lane j; u and (for explicit weights) w are uniform.
+template <bool FIRST, bool WEIGHTED>
+__device__ __forceinline__ float walk_value(const StepParams &p, int32_t u, float w, int j,
+                                            int32_t seed_plain, float cinv_plain) {
+    if (FIRST) {
+        int32_t seed = seed_plain;
+        if (p.node_block) seed = (j < p.ncols) ? p.seeds[(int64_t)p.node_block[u] * p.seed_stride + j] : -1;
+        if (u != seed) return 0.0f;
+        return WEIGHTED ? p.c * w : (p.node_block ? p.c * p.inv[u] : cinv_plain);
+    }
+    const float z = p.zin[(int64_t)u * 64 + j];
+    return WEIGHTED ? w * z : z;
+}
+
+template <int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_64(const Item *__restrict__ items, int64_t n_items,
+                                                           StepParams p) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (wid >= n_items) return;
     const Item it = items[wid];
-    if (it.chunk == -1)
-        short_group_1<MODE, FIRST>(p, it, lane);
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    int32_t seed_plain = -1;
+    float cinv_plain = 0.0f;
+    if (FIRST && !p.node_block && lane < p.ncols) {
+        seed_plain = p.seeds[lane];
+        if (!WEIGHTED && seed_plain >= 0 && (int64_t)seed_plain < p.n) cinv_plain = p.c * p.inv[seed_plain];
+    }
+    constexpr int U = 16;
+    if (kind == (int)kItemGroup) {
+        const int nrows = (int)item_nrows(it.meta);
+        const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        int r = 0;
+        int rend = __builtin_amdgcn_readlane(rel, 1);
+        float acc = 0.0f;
+        for (int base = 0; base < nnz; base += 64) {
+            const int cnt = min(64, nnz - base);
+            const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
+            const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
+            for (int t0 = 0; t0 < cnt; t0 += U) {
+                float v[U];
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
+                    const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
+                    v[k] = walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain);
+                }
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if (t0 + k < cnt) {
+                        const int e = base + t0 + k;
+                        while (e >= rend) {
+                            epilogue<MODE>(p, it.row0 + r, lane, acc);
+                            acc = 0.0f;
+                            ++r;
+                            rend = __builtin_amdgcn_readlane(rel, r + 1);
+                        }
+                        acc += v[k];
+                    }
+                }
+            }
+        }
+        for (; r < nrows; ++r) {
+            epilogue<MODE>(p, it.row0 + r, lane, acc);
+            acc = 0.0f;
+        }
+        return;
+    }
+    // one row (or a chunk of one): U edges in flight, sequential per lane
+    float s = 0.0f;
+    for (int base = 0; base < nnz; base += 64) {
+        const int cnt = min(64, nnz - base);
+        const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
+        const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
+        for (int t0 = 0; t0 < cnt; t0 += U) {
+            float v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
+                const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
+                v[k] = walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (t0 + k < cnt) s += v[k];
+        }
+    }
+    if (kind == (int)kItemRow)
+        epilogue<MODE>(p, it.row0, lane, s);
     else
-        single_row_1<MODE, FIRST>(p, it, lane, el);
+        p.partials[wid * 64 + lane] = s;
 }
 
-// ------------------------------------------------------------ kt > 1
-template <int KT, int MODE, bool FIRST>
-__device__ __forceinline__ float row_range_sum(const StepParams &p, int64_t e0, int64_t e1, int sub,
-                                               int j, int32_t seed) {
+// ------------------------------------------------------------ kt = 2..32
+template <int KT, bool FIRST, bool WEIGHTED>
+__device__ __forceinline__ float range_sum_kt(const StepParams &p, int64_t e0, int64_t e1, int sub, int j) {
     constexpr int SUBS = 64 / KT;
     constexpr int UNR = 4;
     float s = 0.0f;
@@ -210,72 +362,43 @@ __device__ __forceinline__ float row_range_sum(const StepParams &p, int64_t e0, 
             const int64_t e = base + k * SUBS;
             u[k] = (e < e1) ? p.col[e] : -1;
         }
+        float v[UNR];
 #pragma unroll
-        for (int k = 0; k < UNR; ++k) {
-            const int64_t e = base + k * SUBS;
-            if (u[k] >= 0) s += edge_value<FIRST>(p, e, u[k], j, seed);
-        }
+        for (int k = 0; k < UNR; ++k)
+            v[k] = u[k] >= 0 ? edge_value<FIRST, WEIGHTED, KT>(p, base + k * SUBS, u[k], j) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) s += v[k];
     }
 #pragma unroll
     for (int off = KT; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
     return s;
 }
 
-template <int KT, int MODE, bool FIRST>
-__global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *items, int64_t n_items, int el,
+template <int KT, int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restrict__ items, int64_t n_items,
                                                            StepParams p) {
     const int lane = threadIdx.x & 63;
     const int j = lane % KT, sub = lane / KT;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (wid >= n_items) return;
     const Item it = items[wid];
-    const bool packed = p.node_block != nullptr;
-    int32_t seed = -1;
-    if (MODE == kFamily && !packed) seed = j < p.ncols ? p.seeds[j] : -1;
-    if (it.chunk == -1) {
-        for (int64_t r = it.row0; r < it.row1; ++r) {
-            if (MODE == kFamily && packed) seed = seed_of(p, r, j);
-            const float s = row_range_sum<KT, MODE, FIRST>(p, p.rowptr[r], p.rowptr[r + 1], sub, j, seed);
-            if (sub == 0) epilogue<MODE>(p, r, j, s);
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    if (kind == (int)kItemGroup) {
+        const int nrows = (int)item_nrows(it.meta);
+        for (int r = 0; r < nrows; ++r) {
+            const int64_t row = it.row0 + r;
+            const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, p.rowptr[row], p.rowptr[row + 1], sub, j);
+            if (sub == 0) epilogue<MODE>(p, row, j, s);
         }
-    } else {
-        const int64_t row = it.row0;
-        int64_t e0 = p.rowptr[row], e1 = p.rowptr[row + 1];
-        if (it.chunk >= 0) {
-            e0 += (int64_t)it.chunk * el;
-            e1 = min(e1, e0 + (int64_t)el);
-        }
-        if (MODE == kFamily && packed) seed = seed_of(p, row, j);
-        const float s = row_range_sum<KT, MODE, FIRST>(p, e0, e1, sub, j, seed);
-        if (sub == 0) {
-            if (it.chunk >= 0)
-                p.partials[(int64_t)it.slot * KT + j] = s;
-            else
-                epilogue<MODE>(p, row, j, s);
-        }
+        return;
     }
-}
-
-// Finish pass: add the chunk sums of each long row in chunk order.
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *longs, int64_t n_long, StepParams p) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_long) return;
-    const LongRow lr = longs[wid];
-    const int kt = p.kt;
-    if (kt == 1) {
-        float s = 0.0f;
-        for (int i = lane; i < lr.nchunks; i += 64) s += p.partials[(int64_t)lr.slot0 + i];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) epilogue<MODE>(p, lr.row, 0, s);
-    } else {
-        for (int j = lane; j < kt; j += 64) {
-            float s = 0.0f;
-            for (int i = 0; i < lr.nchunks; ++i) s += p.partials[((int64_t)lr.slot0 + i) * kt + j];
-            epilogue<MODE>(p, lr.row, j, s);
-        }
+    const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0, it.e0 + nnz, sub, j);
+    if (sub == 0) {
+        if (kind == (int)kItemRow)
+            epilogue<MODE>(p, it.row0, j, s);
+        else
+            p.partials[wid * KT + j] = s;
     }
 }
 
@@ -299,20 +422,14 @@ __global__ void combine_only_kernel(StepParams p) {
         const int64_t v = i - (int64_t)j * p.n;
         const int32_t seed = seed_of(p, v, j);
         const float y = (v == (int64_t)seed) ? p.c : 0.0f;
-        p.out[(p.out_col0 + j) * p.n + v] =
-            (seed == -2) ? __int_as_float(0x7fc00000) : fmaf(p.alpha, y, p.str[v]);
-    }
-}
-
-__global__ void check_seeds_kernel(const int32_t *seeds, int64_t k, int per_block, int64_t n,
-                                   const int32_t *node_block, int32_t *dst, int32_t *err) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < k;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t s = seeds[i];
-        bool ok = s >= 0 && (int64_t)s < n;
-        if (ok && node_block) ok = (int64_t)node_block[s] == i / per_block;
-        dst[i] = ok ? s : -2;
-        if (!ok) *err = 1;
+        float o;
+        if (seed_valid(p, v, seed)) {
+            o = fmaf(p.alpha, y, p.str[v]);
+        } else {
+            o = qnan();
+            *p.err = 1;
+        }
+        p.out[(p.out_col0 + j) * p.n + v] = o;
     }
 }
 
@@ -323,19 +440,27 @@ inline unsigned grid_1d(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
 }
 
-template <int MODE, bool FIRST>
+template <int MODE, bool FIRST, bool WEIGHTED>
 void launch_kt(const Schedule &s, const StepParams &p, hipStream_t st) {
     const unsigned grid = blocks_for(s.n_items);
+    const Item *it = s.items;
+    const int64_t ni = s.n_items;
     switch (p.kt) {
-        case 1: step_kernel_1<MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 2: step_kernel_kt<2, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 4: step_kernel_kt<4, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 8: step_kernel_kt<8, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 16: step_kernel_kt<16, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 32: step_kernel_kt<32, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
-        case 64: step_kernel_kt<64, MODE, FIRST><<<grid, kThreads, 0, st>>>(s.items, s.n_items, s.el, p); break;
+        case 1: step_kernel_1<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 2: step_kernel_kt<2, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 4: step_kernel_kt<4, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 8: step_kernel_kt<8, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 16: step_kernel_kt<16, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 32: step_kernel_kt<32, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 64: step_kernel_64<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
         default: break;
     }
+}
+
+template <int MODE, bool FIRST>
+void launch_w(const Schedule &s, const StepParams &p, hipStream_t st) {
+    if (p.w) launch_kt<MODE, FIRST, true>(s, p, st);
+    else launch_kt<MODE, FIRST, false>(s, p, st);
 }
 
 }  // namespace
@@ -344,12 +469,13 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (p.kt != 1 && p.kt != 2 && p.kt != 4 && p.kt != 8 && p.kt != 16 && p.kt != 32 && p.kt != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
+    if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
     if (s.n_items > 0) {
         if (mode == kFamily) {
-            if (first) launch_kt<kFamily, true>(s, p, st);
-            else launch_kt<kFamily, false>(s, p, st);
+            if (first) launch_w<kFamily, true>(s, p, st);
+            else launch_w<kFamily, false>(s, p, st);
         } else {
-            launch_kt<kStranger, false>(s, p, st);
+            launch_w<kStranger, false>(s, p, st);
         }
     }
     if (s.n_long > 0) {
@@ -372,14 +498,6 @@ tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, flo
 
 tpa_status launch_combine_only(const StepParams &p, hipStream_t st) {
     combine_only_kernel<<<grid_1d(p.n * (int64_t)p.ncols), 256, 0, st>>>(p);
-    TPA_TRY_HIP(hipGetLastError());
-    return TPA_OK;
-}
-
-tpa_status launch_check_seeds(const int32_t *seeds, int64_t k, int per_block, const tpa_graph *g,
-                              int32_t *dst, hipStream_t st) {
-    check_seeds_kernel<<<grid_1d(k), 256, 0, st>>>(seeds, k, per_block > 0 ? per_block : 1, g->n,
-                                                   per_block > 0 ? g->node_block : nullptr, dst, g->dev_err);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

@@ -393,58 +393,67 @@ void Schedule::release() {
     longs = nullptr;
 }
 
-// Rows of A~^T are cut into wave items: rows longer than EL edges into
-// EL-edge chunks (partials + a finish pass), rows of EW..EL edges into one
-// whole-row item each, and runs of short rows into groups of at most 64
-// rows whose first edges lie in one EW-aligned window (so < 2*EW edges).
-// Heavy items come first so that they start early in the grid.
-tpa_status get_schedule(tpa_graph *g, int ew, hipStream_t st, const Schedule **out) {
-    auto it = g->sched_t.find(ew);
+// Rows of A~^T are cut into wave items, heaviest first so they start early:
+//   * rows longer than EL edges: chunks of CH edges (chunk items);
+//   * rows of EW+1..EL edges: one item per row;
+//   * runs of rows with <= EW edges: greedy groups of at most 63 rows and
+//     EW edges (rows of <= DS = 32 edges are summed one lane per row, longer
+//     ones by the whole wave).
+tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Schedule **out) {
+    auto it = g->sched_t.find(shape);
     if (it != g->sched_t.end()) { *out = &it->second; return TPA_OK; }
     const int64_t n = g->n;
-    const int el = 8 * ew;
+    const int ew = shape.ew, el = shape.el, chunk = shape.chunk;
+    if (ew < 1 || el < ew || chunk < 1 || el > (1 << 16) || chunk > (1 << 16))
+        return fail(TPA_ERR_INVALID_ARG, "bad schedule shape");
+    const int ds = std::min(32, ew);
     std::vector<int64_t> rp(n + 1);
     TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->t.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
     TPA_TRY_HIP(hipStreamSynchronize(st));
-    std::vector<Item> heavy, whole, shorts;
+    std::vector<Item> chunks, rows, groups;
     std::vector<LongRow> longs;
-    int64_t slots = 0, maxch = 0;
-    int64_t gstart = -1;
+    int64_t gstart = -1, gnnz = 0;
     auto close_group = [&](int64_t end) {
-        if (gstart >= 0 && end > gstart) shorts.push_back({(int32_t)gstart, (int32_t)end, -1, -1});
+        if (gstart >= 0 && end > gstart)
+            groups.push_back({rp[gstart], (int32_t)gstart, item_meta((uint32_t)(end - gstart), (uint32_t)gnnz, kItemGroup)});
         gstart = -1;
+        gnnz = 0;
     };
     for (int64_t r = 0; r < n; ++r) {
         const int64_t d = rp[r + 1] - rp[r];
         if (d > el) {
             close_group(r);
-            const int64_t nch = (d + el - 1) / el;
-            if (slots + nch > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many partial slots");
-            longs.push_back({(int32_t)r, (int32_t)nch, (int32_t)slots, 0});
-            for (int64_t ch = 0; ch < nch; ++ch) heavy.push_back({(int32_t)r, (int32_t)(r + 1), (int32_t)ch, (int32_t)(slots + ch)});
-            slots += nch;
-            maxch = std::max(maxch, nch);
+            const int64_t nch = (d + chunk - 1) / chunk;
+            if ((int64_t)chunks.size() + nch > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many chunk items");
+            longs.push_back({(int32_t)r, (int32_t)nch, (int32_t)chunks.size(), 0});
+            for (int64_t ch = 0; ch < nch; ++ch) {
+                const int64_t e0 = rp[r] + ch * chunk;
+                const int64_t len = std::min<int64_t>(chunk, rp[r + 1] - e0);
+                chunks.push_back({e0, (int32_t)(longs.size() - 1), item_meta(1, (uint32_t)len, kItemChunk)});
+            }
         } else if (d > ew) {
             close_group(r);
-            whole.push_back({(int32_t)r, (int32_t)(r + 1), -2, -1});
+            rows.push_back({rp[r], (int32_t)r, item_meta(1, (uint32_t)d, kItemRow)});
         } else {
-            if (gstart >= 0 && (r - gstart >= 64 || rp[r] / ew != rp[gstart] / ew)) close_group(r);
+            if (gstart >= 0 && (r - gstart >= 63 || gnnz + d > ew)) close_group(r);
             if (gstart < 0) gstart = r;
+            gnnz += d;
         }
     }
     close_group(n);
     Schedule s;
     s.ew = ew;
+    s.ds = ds;
     s.el = el;
+    s.chunk = chunk;
     std::vector<Item> all;
-    all.reserve(heavy.size() + whole.size() + shorts.size());
-    all.insert(all.end(), heavy.begin(), heavy.end());
-    all.insert(all.end(), whole.begin(), whole.end());
-    all.insert(all.end(), shorts.begin(), shorts.end());
+    all.reserve(chunks.size() + rows.size() + groups.size());
+    all.insert(all.end(), chunks.begin(), chunks.end());
+    all.insert(all.end(), rows.begin(), rows.end());
+    all.insert(all.end(), groups.begin(), groups.end());
     s.n_items = (int64_t)all.size();
+    s.n_chunk_items = (int64_t)chunks.size();
     s.n_long = (int64_t)longs.size();
-    s.n_slots = slots;
-    s.max_chunks = maxch;
     if (s.n_items > 0) {
         TPA_TRY(dalloc(&s.items, s.n_items, st));
         TPA_TRY_HIP(hipMemcpyAsync(s.items, all.data(), sizeof(Item) * s.n_items, hipMemcpyHostToDevice, st));
@@ -454,7 +463,7 @@ tpa_status get_schedule(tpa_graph *g, int ew, hipStream_t st, const Schedule **o
         TPA_TRY_HIP(hipMemcpyAsync(s.longs, longs.data(), sizeof(LongRow) * s.n_long, hipMemcpyHostToDevice, st));
     }
     TPA_TRY_HIP(hipStreamSynchronize(st));
-    auto ins = g->sched_t.emplace(ew, s);
+    auto ins = g->sched_t.emplace(shape, s);
     *out = &ins.first->second;
     return TPA_OK;
 }

@@ -44,7 +44,8 @@ void dfree(void *p) {
 
 namespace {
 
-constexpr int kDefaultEW = 256;
+constexpr int kDefaultEW1 = 512;   // group edge budget, single vector
+constexpr int kDefaultEW64 = 256;  // group edge budget, seed tiles
 
 // First i >= 1 with c (1-c)^i < eps: Algorithm 1's L1 break, with the
 // per-block norm ||x'(i)||_1 = c (1-c)^i of Lemma 2.
@@ -57,7 +58,17 @@ int64_t stranger_last_iteration(double c, double eps) {
     return 100000;
 }
 
-int choose_ew(const tpa_graph *g) { return g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW; }
+// Schedule shape per seed-tile width: a single vector takes groups of up to
+// 512 edges, rows of up to 4*EW edges as one item and chunks of 2*EW; seed
+// tiles move kt floats per edge, so their items are shorter.
+SchedShape choose_shape(const tpa_graph *g, int kt) {
+    if (kt == 1) {
+        const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW1;
+        return {ew, 4 * ew, 2 * ew};
+    }
+    const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW64;
+    return {ew, 2 * ew, ew};
+}
 
 int choose_kt(const tpa_graph *g, int64_t k) {
     if (g->seed_tile > 0) return g->seed_tile;
@@ -67,11 +78,11 @@ int choose_kt(const tpa_graph *g, int64_t k) {
     return kt;
 }
 
-// Workspace layout (floats): z0 [n*kt] | z1 [n*kt] | partials [slots*kt] | seeds (int32) [k]
-size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, int64_t k) {
+// Workspace layout (floats): z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt]
+size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt) {
     const size_t zf = (size_t)g->n * kt;
-    const size_t pf = (size_t)std::max<int64_t>(s->n_slots, 1) * kt;
-    return sizeof(float) * (2 * zf + pf) + sizeof(int32_t) * (size_t)std::max<int64_t>(k, 1) + 256;
+    const size_t pf = (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;
+    return sizeof(float) * (2 * zf + pf) + 256;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -109,16 +120,13 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed,
     if (k == 0) return TPA_OK;
     if (!seeds || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/out is NULL");
     if (packed && !g->node_block) return fail(TPA_ERR_INVALID_ARG, "graph is not packed");
-    const Schedule *s = nullptr;
-    TPA_TRY(get_schedule(g, choose_ew(g), st, &s));
     const int kt = choose_kt(g, k);
-    const int64_t nseeds = packed ? k * g->nblocks : k;
-    TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt, nseeds), st));
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
+    TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt), st));
     float *z0 = g->ws;
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
-    int32_t *sws = reinterpret_cast<int32_t *>(part + (size_t)std::max<int64_t>(s->n_slots, 1) * kt);
-    TPA_TRY(launch_check_seeds(seeds, nseeds, packed ? (int)k : 0, g, sws, st));
 
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     StepParams p;
@@ -127,6 +135,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed,
     p.w = g->weighted ? g->t.w : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
+    p.err = g->dev_err;
     p.omc = (float)(1.0 - c);
     p.c = (float)c;
     p.kt = kt;
@@ -137,7 +146,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed,
     p.out = out;
     p.n = g->n;
     for (int64_t base = 0; base < k; base += kt) {
-        p.seeds = sws + base;
+        p.seeds = seeds + base;
         p.ncols = (int)std::min<int64_t>(kt, k - base);
         p.out_col0 = base;
         if (S == 1) {
@@ -184,11 +193,11 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     g->preprocessed = false;
     const int64_t K = stranger_last_iteration(c, eps);
     const Schedule *s = nullptr;
-    TPA_TRY(get_schedule(g, choose_ew(g), st, &s));
+    TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
     if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
     float *tmp = nullptr;
     const size_t n = (size_t)g->n;
-    TPA_TRY(dalloc(&tmp, 3 * n + (size_t)std::max<int64_t>(s->n_slots, 1), st));
+    TPA_TRY(dalloc(&tmp, 3 * n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));
     float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
     tpa_status rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, st);
     StepParams p;
@@ -245,10 +254,10 @@ extern "C" tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int 
 
 extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     if (!g || k < 0) return fail(TPA_ERR_INVALID_ARG, "bad argument");
-    const Schedule *s = nullptr;
-    TPA_TRY(get_schedule(g, choose_ew(g), nullptr, &s));
     const int kt = choose_kt(g, k);
-    return ensure_ws(g, query_ws_bytes(g, s, kt, std::max<int64_t>(k, 1) * g->nblocks), nullptr);
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_shape(g, kt), nullptr, &s));
+    return ensure_ws(g, query_ws_bytes(g, s, kt), nullptr);
 }
 
 extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item) {
@@ -256,8 +265,8 @@ extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per
     if (seed_tile != 0 && seed_tile != 1 && seed_tile != 2 && seed_tile != 4 && seed_tile != 8 &&
         seed_tile != 16 && seed_tile != 32 && seed_tile != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 0, 1, 2, 4, 8, 16, 32 or 64");
-    if (edges_per_item != 0 && (edges_per_item < 64 || edges_per_item > 4096 || edges_per_item % 64))
-        return fail(TPA_ERR_INVALID_ARG, "edges per item must be 0 or a multiple of 64 in 64..4096");
+    if (edges_per_item != 0 && (edges_per_item < 64 || edges_per_item > 512 || edges_per_item % 64))
+        return fail(TPA_ERR_INVALID_ARG, "edges per item must be 0 or a multiple of 64 in 64..512");
     g->seed_tile = seed_tile;
     g->edges_per_item = edges_per_item;
     return TPA_OK;

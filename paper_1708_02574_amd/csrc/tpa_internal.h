@@ -41,26 +41,49 @@ tpa_status dalloc(T **p, size_t count, hipStream_t stream) {
 void dfree(void *p);
 
 // ---------------------------------------------------------------- schedule
-// A wave work item over one CSR orientation.
-//   chunk == -1 : rows [row0, row1) (at most 64 rows, fewer than 2*EW edges)
-//   chunk == -2 : the single row row0, processed whole by one wave
-//   chunk >=  0 : chunk `chunk` (EL edges) of the long row row0; its partial
-//                 sum goes to slot `slot` and a finish pass adds the chunks
+// A wave work item over the rows of A~^T.
+//   kind 0 (group) : rows [row0, row0+nrows), nrows <= 63, with nnz <= EW
+//                    edges starting at e0
+//   kind 1 (row)   : the single row row0, nnz edges starting at e0
+//   kind 2 (chunk) : a chunk [e0, e0+nnz) of a long row; its sum goes to
+//                    partial slot <item index>; a finish pass adds each long
+//                    row's partials in chunk order
 struct Item {
-    int32_t row0, row1, chunk, slot;
+    int64_t e0;
+    int32_t row0;
+    uint32_t meta;  // nrows [0,7) | nnz [7,24) | kind [24,26)
 };
+constexpr uint32_t kItemGroup = 0, kItemRow = 1, kItemChunk = 2;
+__host__ __device__ inline uint32_t item_meta(uint32_t nrows, uint32_t nnz, uint32_t kind) {
+    return nrows | (nnz << 7) | (kind << 24);
+}
+__host__ __device__ inline uint32_t item_nrows(uint32_t m) { return m & 127u; }
+__host__ __device__ inline uint32_t item_nnz(uint32_t m) { return (m >> 7) & 0x1ffffu; }
+__host__ __device__ inline uint32_t item_kind(uint32_t m) { return (m >> 24) & 3u; }
+
 struct LongRow {
-    int32_t row, nchunks, slot0, pad;
+    int32_t row, nchunks, first_item, pad;
+};
+
+// Shape of a schedule: group items hold <= ew edges; rows of ew+1..el edges
+// are one item each; longer rows are cut into chunks of `chunk` edges.
+struct SchedShape {
+    int ew, el, chunk;
+    bool operator<(const SchedShape &o) const {
+        return ew != o.ew ? ew < o.ew : (el != o.el ? el < o.el : chunk < o.chunk);
+    }
 };
 
 struct Schedule {
-    int ew = 0, el = 0;
-    Item *items = nullptr;       // device
+    int ew = 0;                  // edge budget of a group item
+    int ds = 0;                  // group rows with <= ds edges are summed per lane
+    int el = 0;                  // rows with > el edges are chunked
+    int chunk = 0;               // chunk length
+    Item *items = nullptr;       // device; chunk items first
     int64_t n_items = 0;
+    int64_t n_chunk_items = 0;
     LongRow *longs = nullptr;    // device
     int64_t n_long = 0;
-    int64_t n_slots = 0;
-    int64_t max_chunks = 0;
     void release();
 };
 
@@ -95,8 +118,8 @@ struct tpa_graph {
     int64_t K = 0;
     float *str = nullptr;                   // r~_stranger, n
 
-    // schedules over A~^T keyed by edges-per-item
-    std::map<int, tpa::Schedule> sched_t;
+    // schedules over A~^T keyed by shape
+    std::map<tpa::SchedShape, tpa::Schedule> sched_t;
 
     // query workspace
     float *ws = nullptr;
@@ -111,7 +134,7 @@ struct tpa_graph {
 namespace tpa {
 
 tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);
-tpa_status get_schedule(tpa_graph *g, int ew, hipStream_t stream, const Schedule **out);
+tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out);
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);

@@ -138,8 +138,8 @@ def test_batched_queries(rmat13, torch, k, kt):
     assert np.all(l1_rows(R, expect) <= TOL)
 
 
-@pytest.mark.parametrize("ew", [64, 128, 1024])
-@pytest.mark.parametrize("kt", [1, 4])
+@pytest.mark.parametrize("ew", [64, 128, 512])
+@pytest.mark.parametrize("kt", [1, 4, 64])
 def test_schedules_with_long_rows(rmat13, torch, ew, kt):
     """Small edges-per-item makes the hub rows of A~^T long (chunks + finish)."""
     og, gg = rmat13
