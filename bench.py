@@ -1,0 +1,241 @@
+"""Benchmark of the TPA hot path on one MI355X.
+
+One step = the plain-TPA job on an R-MAT graph of 2^20 nodes and 2^24
+samples (the synthetic stand-in for the paper's social/web graphs):
+tpa_preprocess (PageRank stranger part, T = 10, K = 116 CPI steps), then
+1000 single-seed tpa_query calls (c = 0.15, S = 5), then the same 1000 seeds
+as one batched tpa_query (seed tiles of 64 columns).  The graph, the seeds
+and the output buffers are resident in HBM before timing starts.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line.  `value` is whole-step throughput in GTEPS: every CPI
+step traverses all m edges, so a step counts (K + 2 * 1000 * (S-1)) * m
+edge traversals (work unit of the paper's complexity analysis, Section
+3.4).  Seeds/s of the plain and batched forms are reported beside it, the
+roofline of the dominant kernel from HIP events taken in the timed region,
+and the FP64 oracle timed on host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+C_RESTART, S_FAM, T_STR = 0.15, 5, 10
+N_SEEDS = 1000
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "rmat20"
+PROFILE_PERIOD = 16
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_1_family_rmat20_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1708_02574_amd", "csrc", "cpi_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def algorithmic_bytes_family_step(n: int, m: int) -> int:
+    """Compulsory HBM bytes of one single-vector family CPI step with
+    1/outdeg weights (the dominant kernel): column ids 4m, row offsets of
+    the grouped rows 8(n+1), the gathered vector read once 4n, 1/outdeg 4n,
+    the next vector written 4n."""
+    return 4 * m + 8 * (n + 1) + 12 * n
+
+
+def traffic_from_profile(n_launch_bytes: int):
+    """HBM bytes per launch from the committed PMC summary, or None when it
+    is missing or was taken on a different version of the kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(scale: int, samples: int, seed: int, seeds, n_queries: int):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same
+    job: its preprocessing plus `n_queries` single-seed queries."""
+    import oracle
+    g = oracle.Graph.rmat(scale, samples, seed)
+    t0 = time.perf_counter()
+    g.preprocess(C_RESTART, T_STR, 1e-9)
+    for s in seeds[:n_queries]:
+        g.query(int(s), C_RESTART, S_FAM, T_STR)
+    dt = time.perf_counter() - t0
+    edges = (g.K + n_queries * (S_FAM - 1)) * g.m
+    return {
+        "value": round(edges / dt / 1e9, 4),
+        "unit": "GTEPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{WORKLOAD}: oracle preprocess (K={g.K} steps) + {n_queries} single-seed queries, "
+                  f"{dt:.1f} s on one host thread",
+        "seconds": round(dt, 3),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seeds", type=int, default=N_SEEDS)
+    ap.add_argument("--cpu-queries", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="after timing, run one device copy of this size (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the seed and block axes would shard with no communication; see DESIGN.md).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1708_02574_amd as tpa
+    import tpa_inputs as ti
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    scale, samples, gseed = ti.GRAPHS[WORKLOAD]
+    print(f"bench: building {WORKLOAD} (scale {scale}, {samples} samples)", file=sys.stderr, flush=True)
+    g = tpa.Graph.rmat(scale, samples, gseed)
+    n, m = g.n, g.m
+    eligible = (g.padded() == 0).cpu().numpy()
+    seeds_h = ti.draw_seeds(eligible, args.seeds, 1)
+    seeds = torch.from_numpy(seeds_h).cuda()
+    k = seeds.numel()
+    out_plain = torch.empty((k, n), dtype=torch.float32, device="cuda")
+    out_batch = torch.empty((k, n), dtype=torch.float32, device="cuda")
+    g.preprocess(C_RESTART, T_STR)
+    g.set_tuning(seed_tile=64)
+    g.reserve(k)
+    g.set_tuning(seed_tile=0)
+    torch.cuda.synchronize()
+
+    def step():
+        g.set_tuning(seed_tile=0)
+        g.preprocess(C_RESTART, T_STR)
+        e1.record()
+        for i in range(k):
+            g.query(seeds[i:i + 1], C_RESTART, S_FAM, T_STR, out=out_plain[i:i + 1])
+        e2.record()
+        g.set_tuning(seed_tile=64)
+        g.query(seeds, C_RESTART, S_FAM, T_STR, out=out_batch)
+        g.set_tuning(seed_tile=0)
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    e0, e1, e2, e3 = ev(), ev(), ev(), ev()
+    for _ in range(args.warmup):
+        e0.record()
+        step()
+        e3.record()
+    torch.cuda.synchronize()
+
+    # HIP events bracket one in PERIOD launches of each step-kernel variant
+    # in the timed region (the dominant kernel's average launch duration)
+    tpa.profile_enable(True, 65536, PROFILE_PERIOD)
+    tpa.profile_reset()
+    t_pre = t_plain = t_batch = 0.0
+    torch.cuda.synchronize()
+    start, stop = ev(), ev()
+    start.record()
+    for _ in range(args.steps):
+        e0.record()
+        step()
+        e3.record()
+        torch.cuda.synchronize()
+        t_pre += e0.elapsed_time(e1)
+        t_plain += e1.elapsed_time(e2)
+        t_batch += e2.elapsed_time(e3)
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_step = total_ms / args.steps
+    code = tpa.profile_code(1, 0, False, False)
+    launches, kms = tpa.profile_read(code)
+    tpa.profile_enable(False)
+
+    # sanity: every r_TPA has mass 1 - (1-c)^(K+1) (Lemma 2 + closed-form K)
+    mass = out_plain.double().sum(dim=1)
+    mass_b = out_batch.double().sum(dim=1)
+    expect = 1.0 - (1.0 - C_RESTART) ** 117
+    mass_err = float(max((mass - expect).abs().max().item(), (mass_b - expect).abs().max().item()))
+    max_diff = float((out_plain - out_batch).abs().max().item())
+
+    K = 116
+    edges_step = (K + 2 * k * (S_FAM - 1)) * m
+    t_pre /= args.steps
+    t_plain /= args.steps
+    t_batch /= args.steps
+    avg_launch_ms = kms / max(launches, 1)
+    alg = algorithmic_bytes_family_step(n, m)
+    achieved = alg / (avg_launch_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(alg)
+
+    rec = {
+        "metric": "TPA query GTEPS & seeds/s, batched vs 1-seed, at L1 <=1e-5 vs FP64 oracle",
+        "value": round(edges_step / (ms_step * 1e-3) / 1e9, 3),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{WORKLOAD}: R-MAT (0.57,0.19,0.19,0.05) 2^{scale} nodes, 2^{int(np.log2(samples))} samples, "
+                        f"deduped + dangling self-loops; tpa_preprocess + {k} single-seed tpa_query + "
+                        f"{k}-seed batched tpa_query (kt=64)",
+            "n": n, "m": m, "seeds": k, "c": C_RESTART, "S": S_FAM, "T": T_STR, "K": K,
+            "parallelism": "single GPU",
+        },
+        "seeds_per_s": {"plain": round(k / (t_plain * 1e-3), 1), "batched": round(k / (t_batch * 1e-3), 1)},
+        "gteps": {
+            "plain": round(k * (S_FAM - 1) * m / (t_plain * 1e-3) / 1e9, 2),
+            "batched": round(k * (S_FAM - 1) * m / (t_batch * 1e-3) / 1e9, 2),
+            "preprocess": round(K * m / (t_pre * 1e-3) / 1e9, 2),
+        },
+        "ms": {"preprocess": round(t_pre, 3), "plain_1000": round(t_plain, 3), "batched_1000": round(t_batch, 3)},
+        "roofline": {
+            "kernel": "step_kernel_1<family, non-first, 1/outdeg> (single-seed CPI step)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg,
+            "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+            "launches_timed": launches,
+        },
+        "checks": {"mass_max_err": mass_err, "plain_vs_batched_max_abs": max_diff},
+    }
+    if args.calibration_copy_mib > 0:
+        src = torch.empty(args.calibration_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if not args.no_cpu_baseline:
+        print("bench: timing the oracle on the host", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(scale, samples, gseed, seeds_h, args.cpu_queries)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -175,6 +175,22 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * Clears the flag. */
 tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing (a tracing aid, process-wide).  While enabled, HIP events
+ * bracket one in every `sample_period` launches of each CPI step-kernel
+ * variant, on the launch's stream; variants are numbered
+ *   code = 16*log2(kt) + 4*mode + 2*first + weighted
+ * (mode 0 = online family step, 1 = preprocessing stranger step; first =
+ * the gather-free first family step; weighted = explicit edge weights), and
+ * code 127 is the long-row finish pass.  tpa_profile_read synchronises the
+ * recorded events, adds their durations into per-code totals and returns
+ * them (launches timed, milliseconds).  tpa_profile_reset clears the
+ * totals.  Errors: INVALID_ARG (capacity outside 1..2^20, sample_period
+ * < 1, code outside 0..127), OOM, HIP. */
+tpa_status tpa_profile_enable(int enable, int capacity, int sample_period);
+tpa_status tpa_profile_read(int code, int64_t *launches, double *total_ms);
+tpa_status tpa_profile_reset(void);
+
 const char *tpa_status_string(tpa_status s);
 const char *tpa_last_error_message(void);
 

@@ -53,6 +53,9 @@ _SIGS = {
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
+    "tpa_profile_enable": (_i, [_i, _i, _i]),
+    "tpa_profile_read": (_i, [_i, _vp, _vp]),
+    "tpa_profile_reset": (_i, []),
     "tpa_status_string": (C.c_char_p, [_i]),
     "tpa_last_error_message": (C.c_char_p, []),
 }
@@ -123,6 +126,26 @@ def _stream(stream=None):
 
 def _ptr(t):
     return _vp(t.data_ptr())
+
+
+def profile_code(kt: int, mode: int, first: bool, weighted: bool) -> int:
+    """Variant code of a CPI step kernel for tpa_profile_read."""
+    return 16 * (int(kt).bit_length() - 1) + 4 * mode + 2 * int(first) + int(weighted)
+
+
+def profile_enable(enable: bool = True, capacity: int = 65536, sample_period: int = 1):
+    _call("tpa_profile_enable", int(enable), capacity, sample_period)
+
+
+def profile_reset():
+    _call("tpa_profile_reset")
+
+
+def profile_read(code: int):
+    """(launches, total milliseconds) recorded for a kernel variant."""
+    n, ms = C.c_int64(), C.c_double()
+    _call("tpa_profile_read", code, C.byref(n), C.byref(ms))
+    return n.value, ms.value
 
 
 class Graph:

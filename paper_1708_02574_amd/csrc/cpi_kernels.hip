@@ -31,6 +31,7 @@
 #include <cmath>
 
 #include "cpi_kernels.h"
+#include "profile.h"
 
 namespace tpa {
 namespace {
@@ -170,13 +171,7 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
 
 // ------------------------------------------------------------ kt == 1
 template <int MODE, bool FIRST, bool WEIGHTED>
-__global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict__ items, int64_t n_items,
-                                                          StepParams p) {
-    __shared__ float lds[kWaves][kGroupMax];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
-    if (wid >= n_items) return;
-    const Item it = items[wid];
+__device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64_t wid, int lane, float *my) {
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     const int32_t *col = p.col + it.e0;
@@ -197,7 +192,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             v[s] = u[s] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + s * 64 + lane, u[s], 0) : 0.0f;
-        float *my = lds[wv];
+        wave_sync();  // the previous item's LDS reads are done
 #pragma unroll
         for (int s = 0; s < NS; ++s)
             if (s * 64 < nnz) my[s * 64 + lane] = v[s];
@@ -254,6 +249,17 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     }
 }
 
+// One wave per work item (the hardware dispatcher balances the waves).
+template <int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict__ items, int64_t n_items,
+                                                          StepParams p) {
+    __shared__ float lds[kWaves][kGroupMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items) return;
+    item_1<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane, lds[wv]);
+}
+
 // ------------------------------------------------------------ kt == 64
 // Value of one edge for lane j; u and (for explicit weights) w are uniform.
 template <bool FIRST, bool WEIGHTED>
@@ -270,12 +276,7 @@ __device__ __forceinline__ float walk_value(const StepParams &p, int32_t u, floa
 }
 
 template <int MODE, bool FIRST, bool WEIGHTED>
-__global__ __launch_bounds__(kThreads) void step_kernel_64(const Item *__restrict__ items, int64_t n_items,
-                                                           StepParams p) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_items) return;
-    const Item it = items[wid];
+__device__ __forceinline__ void item_64(const StepParams &p, const Item it, int64_t wid, int lane) {
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     int32_t seed_plain = -1;
@@ -349,6 +350,15 @@ __global__ __launch_bounds__(kThreads) void step_kernel_64(const Item *__restric
         p.partials[wid * 64 + lane] = s;
 }
 
+template <int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_64(const Item *__restrict__ items, int64_t n_items,
+                                                           StepParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_items) return;
+    item_64<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane);
+}
+
 // ------------------------------------------------------------ kt = 2..32
 template <int KT, bool FIRST, bool WEIGHTED>
 __device__ __forceinline__ float range_sum_kt(const StepParams &p, int64_t e0, int64_t e1, int sub, int j) {
@@ -375,13 +385,8 @@ __device__ __forceinline__ float range_sum_kt(const StepParams &p, int64_t e0, i
 }
 
 template <int KT, int MODE, bool FIRST, bool WEIGHTED>
-__global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restrict__ items, int64_t n_items,
-                                                           StepParams p) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int64_t wid, int lane) {
     const int j = lane % KT, sub = lane / KT;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_items) return;
-    const Item it = items[wid];
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     if (kind == (int)kItemGroup) {
@@ -400,6 +405,15 @@ __global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restric
         else
             p.partials[wid * KT + j] = s;
     }
+}
+
+template <int KT, int MODE, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restrict__ items, int64_t n_items,
+                                                           StepParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_items) return;
+    item_kt<KT, MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane);
 }
 
 __global__ void stranger_init_kernel(int64_t n, float c, const float *restart_pr, float inv_n,
@@ -471,18 +485,24 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
     if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
     if (s.n_items > 0) {
+        int lg = 0;
+        while ((1 << lg) < p.kt) ++lg;
+        const int slot = profile_begin(16 * lg + 4 * mode + 2 * (first ? 1 : 0) + (p.w ? 1 : 0), st);
         if (mode == kFamily) {
             if (first) launch_w<kFamily, true>(s, p, st);
             else launch_w<kFamily, false>(s, p, st);
         } else {
             launch_w<kStranger, false>(s, p, st);
         }
+        profile_end(slot, st);
     }
     if (s.n_long > 0) {
+        const int slot = profile_begin(127, st);
         if (mode == kFamily)
             finish_kernel<kFamily><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
         else
             finish_kernel<kStranger><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
+        profile_end(slot, st);
     }
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;

@@ -70,3 +70,15 @@ def test_constructor_argument_checks():
     assert lib.tpa_graph_from_edges(10, 5, None, None, 0, None, C.byref(h)) == -1
     assert lib.tpa_graph_rmat(10, 0, 10, 1, 0.57, 0.19, 0.19, None, None) == -1
     assert not h.value
+
+
+def test_profile_argument_checks():
+    lib = tpa.load_library()
+    assert lib.tpa_profile_enable(1, 0, 1) == -1
+    assert lib.tpa_profile_enable(1, 1 << 21, 1) == -1
+    assert lib.tpa_profile_enable(1, 16, 0) == -1
+    assert lib.tpa_profile_read(128, None, None) == -1
+    assert lib.tpa_profile_read(-1, None, None) == -1
+    assert tpa.profile_code(1, 0, False, False) == 0
+    assert tpa.profile_code(64, 0, True, True) == 16 * 6 + 3
+    assert tpa.profile_code(1, 1, False, False) == 4
