@@ -159,6 +159,34 @@ tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, i
 tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, double c,
                             int S, int T, float *out, hipStream_t stream);
 
+/* Online phase for dense restart vectors: q[j*n + v] is restart vector j
+ * (seed-major float[k][n]; Algorithm 1's q, e.g. 1/|set| over a seed set).
+ * x(0) = c q_j, same steps and combine as tpa_query; out as tpa_query.  On a
+ * packed graph, column j holds every block's j-th restart vector.  Errors
+ * as tpa_query (no seed check). */
+tpa_status tpa_query_dense(tpa_graph_t g, const float *q, int64_t k, double c, int S, int T,
+                           float *out, hipStream_t stream);
+
+/* Reverse-mode derivative (an extension of the method) of
+ *   L = sum_j sum_v grad_out[j*n + v] * r_TPA_j[v]
+ * with r_TPA_j from seeds (k seed nodes; packed != 0: seeds[b*k + j] per
+ * block as tpa_query_packed) or from dense restart vectors q [k][n] (pass
+ * exactly one).  Both CPI chains are differentiated: the family chain per
+ * restart vector (x(0) = c q_j, S-1 steps) and the PageRank stranger chain
+ * (x'(0) = c/n_g per block, K steps, its iterates checkpointed every
+ * `checkpoint_every` steps and recomputed per segment; 0 = ceil(sqrt(K)),
+ * negative = one segment).  Outputs (device, either may be NULL):
+ *   grad_logits float[m], A~ order: dL/dtheta for row-softmax weights
+ *               A~_uv = softmax_u(theta); with 1/outdeg weights it is the
+ *               derivative at theta = 0;
+ *   grad_q      float[k][n]: dL/dq_j = c * lambda_j(0).
+ * Requires tpa_preprocess with the same (c, T) (K comes from its eps).
+ * Allocates scratch and synchronises `stream` before returning.
+ * Errors: INVALID_ARG, NOT_PREPROCESSED, PARAM_MISMATCH, OOM, HIP. */
+tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k, int packed,
+                        double c, int S, int T, const float *grad_out, float *grad_logits,
+                        float *grad_q, int checkpoint_every, hipStream_t stream);
+
 /* Pre-allocate the query workspace for up to k seeds (or per_block slots),
  * so that later queries allocate nothing (e.g. under stream capture). */
 tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
@@ -180,9 +208,11 @@ tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
  * bracket one in every `sample_period` launches of each CPI step-kernel
  * variant, on the launch's stream; variants are numbered
  *   code = 16*log2(kt) + 4*mode + 2*first + weighted
- * (mode 0 = online family step, 1 = preprocessing stranger step; first =
- * the gather-free first family step; weighted = explicit edge weights), and
- * code 127 is the long-row finish pass.  tpa_profile_read synchronises the
+ * (mode 0 = online family step, 1 = preprocessing stranger step, 2 =
+ * plain step keeping its iterate, 3 = adjoint step; first = the gather-free
+ * first step from one-hot seeds, or for mode 3 = with the edge gradient;
+ * weighted = explicit edge weights), and code 127 is the long-row finish
+ * pass.  tpa_profile_read synchronises the
  * recorded events, adds their durations into per-code totals and returns
  * them (launches timed, milliseconds).  tpa_profile_reset clears the
  * totals.  Errors: INVALID_ARG (capacity outside 1..2^20, sample_period

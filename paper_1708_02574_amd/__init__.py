@@ -49,6 +49,8 @@ _SIGS = {
     "tpa_stranger": (_i, [_vp, _vp, _vp]),
     "tpa_query": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_query_packed": (_i, [_vp, _vp, _i, _d, _i, _i, _vp, _vp]),
+    "tpa_query_dense": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
+    "tpa_backward": (_i, [_vp, _vp, _vp, _i64, _i, _d, _i, _i, _vp, _vp, _vp, _i, _vp]),
     "tpa_reserve": (_i, [_vp, _i64]),
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
@@ -274,6 +276,43 @@ class Graph:
         _call("tpa_query_packed", self._h, _ptr(sd), P, c, S, T, _ptr(out), _stream(stream))
         return out
 
+    def query_dense(self, q, c: float, S: int, T: int, out=None, stream=None):
+        """r_TPA for dense restart vectors q [k, n] (float32): returns [k, n]."""
+        torch = _torch()
+        qd = q.to(device="cuda", dtype=torch.float32).contiguous()
+        if qd.dim() != 2 or qd.shape[1] != self.n:
+            raise ValueError("q must be [k, n]")
+        k = qd.shape[0]
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.float32, device="cuda")
+        _call("tpa_query_dense", self._h, _ptr(qd), k, c, S, T, _ptr(out), _stream(stream))
+        return out
+
+    def backward(self, grad_out, c: float, S: int, T: int, seeds=None, q=None, packed: bool = False,
+                 want_logits: bool = True, want_q: bool = True, checkpoint_every: int = 0, stream=None):
+        """Gradients of L = sum(grad_out * r_TPA) w.r.t. the edge logits (A~
+        order, [m]) and the restart vectors ([k, n]); returns (dtheta, dq)."""
+        torch = _torch()
+        go = grad_out.to(device="cuda", dtype=torch.float32).contiguous()
+        k = go.shape[0]
+        if go.dim() != 2 or go.shape[1] != self.n:
+            raise ValueError("grad_out must be [k, n]")
+        sp = qp = None
+        if seeds is not None:
+            sd = seeds.to(device="cuda", dtype=torch.int32).contiguous()
+            sp = _ptr(sd)
+        if q is not None:
+            qd = q.to(device="cuda", dtype=torch.float32).contiguous()
+            if qd.shape != go.shape:
+                raise ValueError("q must match grad_out's shape")
+            qp = _ptr(qd)
+        dth = torch.empty(self.m, dtype=torch.float32, device="cuda") if want_logits else None
+        dq = torch.empty((k, self.n), dtype=torch.float32, device="cuda") if want_q else None
+        _call("tpa_backward", self._h, sp, qp, k, int(packed), c, S, T, _ptr(go),
+              _ptr(dth) if dth is not None else None, _ptr(dq) if dq is not None else None,
+              checkpoint_every, _stream(stream))
+        return dth, dq
+
     def reserve(self, k: int):
         _call("tpa_reserve", self._h, k)
 
@@ -288,3 +327,48 @@ class Graph:
     def device_error(self, stream=None):
         """Raise TPAError if a query since the last check saw a bad seed."""
         _call("tpa_get_device_error", self._h, _stream(stream))
+
+
+def _autograd_function():
+    import torch
+
+    class TPAFunction(torch.autograd.Function):
+        """r_TPA = TPAFunction.apply(theta, Q, graph, c, S, T[, checkpoint_every]).
+
+        theta: per-edge logits [m] in A~ order (row-softmax weights), Q: dense
+        restart vectors [k, n].  The forward sets the graph's weights from
+        theta and re-runs preprocessing (the stranger part depends on the
+        weights); the backward differentiates both CPI chains on the device.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, Q, graph, c, S, T, checkpoint_every=0):
+            graph.set_logits(theta.detach())
+            graph.preprocess(c, T)
+            R = graph.query_dense(Q.detach(), c, S, T)
+            ctx.graph, ctx.args = graph, (c, S, T, checkpoint_every)
+            ctx.save_for_backward(Q)
+            return R
+
+        @staticmethod
+        def backward(ctx, gR):
+            (Q,) = ctx.saved_tensors
+            c, S, T, ck = ctx.args
+            dth, dq = ctx.graph.backward(gR, c, S, T, q=Q, want_logits=ctx.needs_input_grad[0],
+                                         want_q=ctx.needs_input_grad[1], checkpoint_every=ck)
+            return dth, dq, None, None, None, None, None
+
+    return TPAFunction
+
+
+class _LazyFunction:
+    _f = None
+
+    def __getattr__(self, name):
+        if _LazyFunction._f is None:
+            _LazyFunction._f = _autograd_function()
+        return getattr(_LazyFunction._f, name)
+
+
+TPAFunction = _LazyFunction()
+

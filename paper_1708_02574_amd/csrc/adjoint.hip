@@ -1,0 +1,561 @@
+// Reverse-mode derivative of the TPA hot path (an extension of the paper:
+// its CPI recursions of Section 2.3 / Algorithms 2-3, differentiated).
+//
+// For one CPI chain x(i) = (1-c) A~^T x(i-1), i = 1..N, with loss
+// L = sum_i beta_i <g, x(i)>, the adjoint lambda(i) = dL/dx(i) obeys
+//     lambda(N) = beta_N g,   lambda(i-1) = beta_{i-1} g + (1-c) A~ lambda(i),
+// and dL/dA~_uv = (1-c) sum_{i=1..N} x(i-1)[u] lambda(i)[v].  TPA has two
+// such chains per loss L = sum_j <grad_out_j, r_TPA_j>:
+//   family   (per restart vector q_j): x(0) = c q_j, N = S-1, beta = 1 + scale;
+//            dL/dq_j = c lambda(0)
+//   stranger (PageRank, once for g = sum_j grad_out_j): x'(0) = c/n_g per
+//            block, N = K, beta_i = [i >= T]
+// The row-softmax backward then gives dL/dtheta_uv = A~_uv (G_uv - sum_w A~_uw G_uw).
+//
+// One adjoint step is a pull over the rows of A~ (out-edges): the gather of
+// lambda(i)[v] serves both the row sum for lambda(i-1)[u] and the per-edge
+// gradient term, fused in one pass.  Work items are the wave items of the
+// forward kernels, built over A~'s rows.  The stranger chain's iterates are
+// checkpointed every C steps and recomputed per segment (memory (K/C + C)
+// vectors instead of K).
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "cpi_kernels.h"
+#include "profile.h"
+
+namespace tpa {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kGroupMax = 512;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct AdjParams {
+    const int64_t *rowptr = nullptr;   // A~ (rows = sources u)
+    const int32_t *col = nullptr;      // destinations v
+    const float *w = nullptr;          // A~ weights in A~ order, or null (1/outdeg)
+    const float *inv = nullptr;        // 1/outdeg
+    const LongRow *longs = nullptr;
+    const float *lam_in = nullptr;     // lambda(i), [n][kt]
+    float *lam_out = nullptr;          // lambda(i-1), [n][kt]
+    const float *xprev = nullptr;      // x(i-1), [n][kt] (null: no edge gradient)
+    float *G = nullptr;                // dL/dA~, [m] in A~ order
+    const float *gvec = nullptr;       // kt == 1: g [n]; kt > 1: grad_out tile, seed-major
+    int64_t g_stride = 0;              // seed-major row stride (n) for kt > 1
+    float beta = 0.f;                  // beta_{i-1}
+    float omc = 0.f;                   // 1 - c
+    int kt = 1;
+    int ncols = 1;
+    int64_t n = 0;
+    float *partials = nullptr;         // chunk partials [chunk items][kt]
+};
+
+__device__ __forceinline__ float g_of(const AdjParams &p, int64_t u, int j) {
+    if (p.kt == 1) return p.gvec[u];
+    return j < p.ncols ? p.gvec[(int64_t)j * p.g_stride + u] : 0.0f;
+}
+
+// lambda(i-1)[u][j] = beta g + (1-c) * (explicit weights ? sum : sum / outdeg(u))
+__device__ __forceinline__ void adj_epilogue(const AdjParams &p, int64_t u, int j, float sum) {
+    const float s = p.w ? sum : sum * p.inv[u];
+    p.lam_out[u * p.kt + j] = fmaf(p.beta, g_of(p, u, j), p.omc * s);
+}
+
+// ------------------------------------------------------------ kt == 1
+template <bool WEIGHTED, bool WITHG>
+__global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict__ items, int64_t n_items,
+                                                         AdjParams p) {
+    __shared__ float lds_v[kWaves][kGroupMax];
+    __shared__ float lds_x[kWaves][kGroupMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items) return;
+    const Item it = items[wid];
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    const int32_t *col = p.col + it.e0;
+    if (kind == (int)kItemGroup) {
+        constexpr int NS = kGroupMax / 64;
+        const int nrows = (int)item_nrows(it.meta);
+        const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        int32_t v[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = s * 64 + lane;
+            v[s] = e < nnz ? col[e] : -1;
+        }
+        const float xr = (WITHG && lane < nrows) ? p.omc * p.xprev[it.row0 + lane] : 0.0f;
+        float l[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) l[s] = v[s] >= 0 ? p.lam_in[v[s]] : 0.0f;
+        const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
+        const int len = rel_next - rel;
+        float *my = lds_v[wv];
+        float *mx = lds_x[wv];
+        if (WITHG) {
+            // expand (1-c) x(i-1)[row] over the row's edges
+            if (lane < nrows && len <= 32)
+                for (int k = rel; k < rel_next; ++k) mx[k] = xr;
+            uint64_t big = __ballot(lane < nrows && len > 32);
+            while (big) {
+                const int r = __builtin_ctzll(big);
+                big &= big - 1;
+                const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel_next, r);
+                const float xv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xr), r));
+                for (int k = b + lane; k < en; k += 64) mx[k] = xv;
+            }
+            wave_sync();
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int e = s * 64 + lane;
+            if (s * 64 < nnz) {
+                if (WITHG && e < nnz) p.G[it.e0 + e] += mx[e] * l[s];
+                my[e] = (WEIGHTED && e < nnz) ? p.w[it.e0 + e] * l[s] : l[s];
+            }
+        }
+        wave_sync();
+        if (lane < nrows && len <= 32) {
+            float acc = 0.0f;
+            for (int k = rel; k < rel_next; ++k) acc += my[k];
+            adj_epilogue(p, it.row0 + lane, 0, acc);
+        }
+        uint64_t big = __ballot(lane < nrows && len > 32);
+        while (big) {
+            const int r = __builtin_ctzll(big);
+            big &= big - 1;
+            const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel_next, r);
+            float t = 0.0f;
+            for (int k = b + lane; k < en; k += 64) t += my[k];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) adj_epilogue(p, it.row0 + r, 0, t);
+        }
+        return;
+    }
+    // one row or one chunk of a long row
+    const int64_t row = kind == (int)kItemRow ? (int64_t)it.row0 : (int64_t)p.longs[it.row0].row;
+    const float xr = WITHG ? p.omc * p.xprev[row] : 0.0f;
+    constexpr int UNR = 16;
+    float s = 0.0f;
+    for (int base = 0; base < nnz; base += 64 * UNR) {
+        int32_t v[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int e = base + k * 64 + lane;
+            v[k] = e < nnz ? col[e] : -1;
+        }
+        float l[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) l[k] = v[k] >= 0 ? p.lam_in[v[k]] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int e = base + k * 64 + lane;
+            if (v[k] >= 0) {
+                if (WITHG) p.G[it.e0 + e] += xr * l[k];
+                s += WEIGHTED ? p.w[it.e0 + e] * l[k] : l[k];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        if (kind == (int)kItemRow)
+            adj_epilogue(p, row, 0, s);
+        else
+            p.partials[wid] = s;
+    }
+}
+
+// ------------------------------------------------------------ kt >= 2
+// Lanes (sub, j): 64/KT sub-groups stride over a row's edges, lane j holds
+// column j.  The edge gradient term sum_j x_j(i-1)[u] lambda_j(i)[v] is a
+// xor-reduction over the KT lanes of a sub-group.
+template <int KT, bool WEIGHTED, bool WITHG>
+__device__ __forceinline__ float adj_range_kt(const AdjParams &p, int64_t row, int64_t e0, int64_t e1, int sub,
+                                              int j) {
+    constexpr int SUBS = 64 / KT;
+    const float xr = WITHG ? p.omc * p.xprev[row * KT + j] : 0.0f;
+    float s = 0.0f;
+    // every lane runs the same trip count (the shuffles below need all 64)
+    for (int64_t base = e0; base < e1; base += SUBS) {
+        const int64_t e = base + sub;
+        const bool ok = e < e1;
+        const int32_t v = ok ? p.col[e] : 0;
+        const float l = ok ? p.lam_in[(int64_t)v * KT + j] : 0.0f;
+        if (WITHG) {
+            float d = xr * l;
+#pragma unroll
+            for (int off = 1; off < KT; off <<= 1) d += __shfl_xor(d, off, 64);
+            if (ok && j == 0) p.G[e] += d;
+        }
+        if (ok) s += WEIGHTED ? p.w[e] * l : l;
+    }
+#pragma unroll
+    for (int off = KT; off < 64; off <<= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+template <int KT, bool WEIGHTED, bool WITHG>
+__global__ __launch_bounds__(kThreads) void adj_kernel_kt(const Item *__restrict__ items, int64_t n_items,
+                                                          AdjParams p) {
+    const int lane = threadIdx.x & 63;
+    const int j = lane % KT, sub = lane / KT;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_items) return;
+    const Item it = items[wid];
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    if (kind == (int)kItemGroup) {
+        const int nrows = (int)item_nrows(it.meta);
+        for (int r = 0; r < nrows; ++r) {
+            const int64_t row = it.row0 + r;
+            const float s = adj_range_kt<KT, WEIGHTED, WITHG>(p, row, p.rowptr[row], p.rowptr[row + 1], sub, j);
+            if (sub == 0) adj_epilogue(p, row, j, s);
+        }
+        return;
+    }
+    const int64_t row = kind == (int)kItemRow ? (int64_t)it.row0 : (int64_t)p.longs[it.row0].row;
+    const float s = adj_range_kt<KT, WEIGHTED, WITHG>(p, row, it.e0, it.e0 + nnz, sub, j);
+    if (sub == 0) {
+        if (kind == (int)kItemRow)
+            adj_epilogue(p, row, j, s);
+        else
+            p.partials[wid * KT + j] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void adj_finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
+                                                              AdjParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_long) return;
+    const LongRow lr = longs[wid];
+    if (p.kt == 1) {
+        float t = 0.0f;
+        for (int i = lane; i < lr.nchunks; i += 64) t += p.partials[(int64_t)lr.first_item + i];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0) adj_epilogue(p, lr.row, 0, t);
+    } else {
+        for (int j = lane; j < p.kt; j += 64) {
+            float t = 0.0f;
+            for (int i = 0; i < lr.nchunks; ++i) t += p.partials[((int64_t)lr.first_item + i) * p.kt + j];
+            adj_epilogue(p, lr.row, j, t);
+        }
+    }
+}
+
+// g_sum[v] = sum_j grad_out[j][v]
+__global__ void gsum_kernel(const float *grad_out, int64_t k, int64_t n, float *gs) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int64_t j = 0; j < k; ++j) s += grad_out[j * n + v];
+        gs[v] = s;
+    }
+}
+
+// lambda(N) tile: lam[v][j] = beta * g(v, j)
+__global__ void lam_init_kernel(AdjParams p, float *lam) {
+    const int64_t total = p.n * (int64_t)p.kt;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / p.kt;
+        const int j = (int)(i - v * p.kt);
+        lam[i] = p.beta * g_of(p, v, j);
+    }
+}
+
+// grad_q[col0 + j][v] = c * lambda(0)[v][j]
+__global__ void gradq_kernel(const float *lam, int64_t n, int kt, int ncols, float c, int64_t col0, float *gq) {
+    const int64_t total = n * (int64_t)ncols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(i / n);
+        const int64_t v = i - (int64_t)j * n;
+        gq[(col0 + j) * n + v] = c * lam[v * kt + j];
+    }
+}
+
+// z = x (explicit weights) or x / outdeg (uniform)
+__global__ void scale_kernel(const float *x, const float *inv, int use_inv, int64_t n, float *z) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        z[v] = use_inv ? x[v] * inv[v] : x[v];
+}
+
+// Row softmax backward, in place on G: one wave per row of A~.
+__global__ void softmax_bwd_kernel(const int64_t *rowptr, const float *w, const float *inv, int64_t n, float *G) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (row >= n) return;
+    const int64_t b = rowptr[row], e = rowptr[row + 1];
+    const float iu = w ? 0.0f : inv[row];
+    float s = 0.0f;
+    for (int64_t i = b + lane; i < e; i += 64) s += (w ? w[i] : iu) * G[i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    for (int64_t i = b + lane; i < e; i += 64) {
+        const float a = w ? w[i] : iu;
+        G[i] = a * (G[i] - s);
+    }
+}
+
+inline unsigned grid_1d(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
+}
+inline unsigned blocks_for(int64_t waves) { return (unsigned)((waves + kWaves - 1) / kWaves); }
+
+template <bool WG>
+void launch_adj_kt(const Schedule &s, const AdjParams &p, hipStream_t st) {
+    const unsigned grid = blocks_for(s.n_items);
+    const Item *it = s.items;
+    const int64_t ni = s.n_items;
+    const bool w = p.w != nullptr;
+#define TPA_ADJ_CASE(KT)                                                                                  \
+    if (w) adj_kernel_kt<KT, true, WG><<<grid, kThreads, 0, st>>>(it, ni, p);                             \
+    else adj_kernel_kt<KT, false, WG><<<grid, kThreads, 0, st>>>(it, ni, p);
+    switch (p.kt) {
+        case 1:
+            if (w) adj_kernel_1<true, WG><<<grid, kThreads, 0, st>>>(it, ni, p);
+            else adj_kernel_1<false, WG><<<grid, kThreads, 0, st>>>(it, ni, p);
+            break;
+        case 2: TPA_ADJ_CASE(2) break;
+        case 4: TPA_ADJ_CASE(4) break;
+        case 8: TPA_ADJ_CASE(8) break;
+        case 16: TPA_ADJ_CASE(16) break;
+        case 32: TPA_ADJ_CASE(32) break;
+        case 64: TPA_ADJ_CASE(64) break;
+        default: break;
+    }
+#undef TPA_ADJ_CASE
+}
+
+tpa_status adj_step(const Schedule &s, const AdjParams &p, hipStream_t st) {
+    if (s.n_items > 0) {
+        int lg = 0;
+        while ((1 << lg) < p.kt) ++lg;
+        const int slot = profile_begin(16 * lg + 12 + (p.G ? 2 : 0) + (p.w ? 1 : 0), st);
+        if (p.G) launch_adj_kt<true>(s, p, st);
+        else launch_adj_kt<false>(s, p, st);
+        profile_end(slot, st);
+    }
+    if (s.n_long > 0) adj_finish_kernel<<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+// Scoped device buffers freed on every exit path.
+struct Scratch {
+    std::vector<void *> bufs;
+    ~Scratch() {
+        for (void *b : bufs) dfree(b);
+    }
+    template <class T>
+    tpa_status get(T **p, size_t count, hipStream_t st) {
+        TPA_TRY(dalloc(p, std::max<size_t>(count, 1), st));
+        bufs.push_back(*p);
+        return TPA_OK;
+    }
+};
+
+}  // namespace
+}  // namespace tpa
+
+using namespace tpa;
+
+extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k, int packed,
+                                   double c, int S, int T, const float *grad_out, float *grad_logits,
+                                   float *grad_q, int checkpoint_every, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (!g->preprocessed) return fail(TPA_ERR_NOT_PREPROCESSED, "tpa_preprocess has not run on this graph");
+    if (!(c > 0.0 && c < 1.0) || S < 1 || T < S) return fail(TPA_ERR_INVALID_ARG, "need 0 < c < 1, S >= 1, T >= S");
+    if (c != g->c || T != g->T) return fail(TPA_ERR_PARAM_MISMATCH, "(c, T) differs from the preprocessed (c, T)");
+    if (k < 1) return fail(TPA_ERR_INVALID_ARG, "k must be >= 1");
+    if ((seeds == nullptr) == (q == nullptr)) return fail(TPA_ERR_INVALID_ARG, "pass exactly one of seeds and q");
+    if (!grad_out) return fail(TPA_ERR_INVALID_ARG, "grad_out is NULL");
+    if (!grad_logits && !grad_q) return TPA_OK;
+    if (packed && (!seeds || !g->node_block)) return fail(TPA_ERR_INVALID_ARG, "packed needs seeds and a packed graph");
+    const int64_t n = g->n, m = g->m, K = g->K;
+    const float omc = (float)(1.0 - c);
+    const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
+    const float alpha = (float)((1.0 - pT) / (1.0 - pS));
+    Scratch sc;
+
+    const Schedule *sf1 = nullptr, *sa1 = nullptr;
+    TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
+    TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sa1, true));
+
+    if (grad_logits) {
+        TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
+        // ---- stranger chain, checkpointed ----
+        int64_t C = checkpoint_every;
+        if (C == 0) C = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)K)));
+        if (C < 0 || C > K) C = K;
+        const int64_t nck = (K + C - 1) / C;
+        float *gs, *ck, *seg, *z0, *z1, *lam0, *lam1, *comp, *part_f, *part_a;
+        TPA_TRY(sc.get(&gs, n, st));
+        TPA_TRY(sc.get(&ck, (size_t)nck * n, st));
+        TPA_TRY(sc.get(&seg, (size_t)C * n, st));
+        TPA_TRY(sc.get(&z0, n, st));
+        TPA_TRY(sc.get(&z1, n, st));
+        TPA_TRY(sc.get(&lam0, n, st));
+        TPA_TRY(sc.get(&lam1, n, st));
+        TPA_TRY(sc.get(&comp, n, st));
+        TPA_TRY(sc.get(&part_f, sf1->n_chunk_items, st));
+        TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
+        gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
+        // forward pass: checkpoints x'(0), x'(C), ...
+        TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, st));
+        StepParams fp;
+        fp.rowptr = g->t.rowptr;
+        fp.col = g->t.col;
+        fp.w = g->weighted ? g->t.w : nullptr;
+        fp.inv = g->inv_deg;
+        fp.partials = part_f;
+        fp.omc = omc;
+        fp.c = (float)c;
+        fp.kt = 1;
+        fp.ncols = 1;
+        fp.n = n;
+        float *zc = z0, *zn = z1;
+        for (int64_t i = 1; i < (nck - 1) * C + 1 && i < K; ++i) {
+            fp.zin = zc;
+            fp.zout = zn;
+            fp.xs_out = (i % C == 0) ? ck + (size_t)(i / C) * n : nullptr;
+            TPA_TRY(launch_step(*sf1, kPlain, false, fp, st));
+            std::swap(zc, zn);
+        }
+        // backward over segments
+        AdjParams ap;
+        ap.rowptr = g->a.rowptr;
+        ap.col = g->a.col;
+        ap.w = g->weighted ? g->a.w : nullptr;
+        ap.inv = g->inv_deg;
+        ap.longs = sa1->longs;
+        ap.G = grad_logits;
+        ap.gvec = gs;
+        ap.omc = omc;
+        ap.kt = 1;
+        ap.ncols = 1;
+        ap.n = n;
+        ap.partials = part_a;
+        ap.beta = (K >= T) ? 1.0f : 0.0f;
+        lam_init_kernel<<<grid_1d(n), 256, 0, st>>>(ap, lam0);
+        float *lc = lam0, *ln = lam1;
+        for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
+            const int64_t lo = sgi * C, hi = std::min<int64_t>(lo + C, K);
+            // recompute x'(lo+1 .. hi-1) into seg[1..]; seg slot 0 is the checkpoint
+            float *x_lo = ck + (size_t)sgi * n;
+            if (hi - lo > 1) {
+                scale_kernel<<<grid_1d(n), 256, 0, st>>>(x_lo, g->inv_deg, g->weighted ? 0 : 1, n, z0);
+                float *a = z0, *b = z1;
+                for (int64_t i = lo + 1; i < hi; ++i) {
+                    fp.zin = a;
+                    fp.zout = b;
+                    fp.xs_out = seg + (size_t)(i - lo) * n;
+                    TPA_TRY(launch_step(*sf1, kPlain, false, fp, st));
+                    std::swap(a, b);
+                }
+            }
+            for (int64_t i = hi; i > lo; --i) {
+                ap.xprev = (i - 1 == lo) ? x_lo : seg + (size_t)(i - 1 - lo) * n;
+                ap.lam_in = lc;
+                ap.lam_out = ln;
+                ap.beta = (i - 1 >= T) ? 1.0f : 0.0f;
+                TPA_TRY(adj_step(*sa1, ap, st));
+                std::swap(lc, ln);
+            }
+        }
+    }
+
+    // ---- family chains per seed tile ----
+    const int kt = choose_kt(g, k);
+    const Schedule *sfk = nullptr, *sak = nullptr;
+    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &sfk, false));
+    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &sak, true));
+    const int nit = std::max(S - 1, 1);  // stored iterates x(0..S-2)
+    float *xf, *z0, *z1, *lam0, *lam1, *part_f, *part_a;
+    TPA_TRY(sc.get(&xf, (size_t)nit * n * kt, st));
+    TPA_TRY(sc.get(&z0, (size_t)n * kt, st));
+    TPA_TRY(sc.get(&z1, (size_t)n * kt, st));
+    TPA_TRY(sc.get(&lam0, (size_t)n * kt, st));
+    TPA_TRY(sc.get(&lam1, (size_t)n * kt, st));
+    TPA_TRY(sc.get(&part_f, (size_t)sfk->n_chunk_items * kt, st));
+    TPA_TRY(sc.get(&part_a, (size_t)sak->n_chunk_items * kt, st));
+    StepParams fp;
+    fp.rowptr = g->t.rowptr;
+    fp.col = g->t.col;
+    fp.w = g->weighted ? g->t.w : nullptr;
+    fp.inv = g->inv_deg;
+    fp.partials = part_f;
+    fp.omc = omc;
+    fp.c = (float)c;
+    fp.kt = kt;
+    fp.n = n;
+    fp.node_block = packed ? g->node_block : nullptr;
+    fp.seed_stride = packed ? (int)k : 0;
+    AdjParams ap;
+    ap.rowptr = g->a.rowptr;
+    ap.col = g->a.col;
+    ap.w = g->weighted ? g->a.w : nullptr;
+    ap.inv = g->inv_deg;
+    ap.longs = sak->longs;
+    ap.G = grad_logits;
+    ap.g_stride = n;
+    ap.omc = omc;
+    ap.kt = kt;
+    ap.n = n;
+    ap.partials = part_a;
+    for (int64_t base = 0; base < k; base += kt) {
+        const int ncols = (int)std::min<int64_t>(kt, k - base);
+        fp.seeds = seeds ? seeds + base : nullptr;
+        fp.qdense = q ? q + base * n : nullptr;
+        fp.ncols = ncols;
+        // x(0) and the scaled vector for step 1
+        if (q) {
+            TPA_TRY(launch_dense_init(fp, z0, xf, st));
+        } else {
+            TPA_TRY(launch_onehot_init(fp, xf, st));
+        }
+        float *zc = z0, *zn = z1;
+        for (int i = 1; i <= S - 2; ++i) {
+            fp.zin = zc;
+            fp.zout = zn;
+            fp.xs_out = xf + (size_t)i * n * kt;
+            TPA_TRY(launch_step(*sfk, kPlain, i == 1 && !q, fp, st));
+            std::swap(zc, zn);
+        }
+        ap.gvec = grad_out + base * n;
+        ap.ncols = ncols;
+        ap.beta = alpha;
+        lam_init_kernel<<<grid_1d(n * kt), 256, 0, st>>>(ap, lam0);
+        float *lc = lam0, *ln = lam1;
+        for (int i = S - 1; i >= 1; --i) {
+            ap.xprev = grad_logits ? xf + (size_t)(i - 1) * n * kt : nullptr;
+            ap.G = grad_logits;
+            ap.lam_in = lc;
+            ap.lam_out = ln;
+            ap.beta = alpha;
+            TPA_TRY(adj_step(*sak, ap, st));
+            std::swap(lc, ln);
+        }
+        if (grad_q) gradq_kernel<<<grid_1d(n * ncols), 256, 0, st>>>(lc, n, kt, ncols, (float)c, base, grad_q);
+    }
+    if (grad_logits) {
+        softmax_bwd_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, st>>>(g->a.rowptr, g->weighted ? g->a.w : nullptr,
+                                                                          g->inv_deg, n, grad_logits);
+    }
+    TPA_TRY_HIP(hipGetLastError());
+    TPA_TRY_HIP(hipStreamSynchronize(st));  // scratch buffers are freed on return
+    return TPA_OK;
+}

@@ -5,7 +5,7 @@
 
 namespace tpa {
 
-enum StepMode : int { kFamily = 0, kStranger = 1 };
+enum StepMode : int { kFamily = 0, kStranger = 1, kPlain = 2 };
 
 // One CPI step y = (1-c) A~^T x over a seed tile of kt columns (node-major
 // [n][kt] vectors), pulled over the rows of A~^T, plus the step's epilogue:
@@ -14,6 +14,10 @@ enum StepMode : int { kFamily = 0, kStranger = 1 };
 //            weights); on the last step out = alpha*y + r~_stranger instead.
 //   stranger : x = (1-c)*sum; next gathered vector as above; when
 //            `accumulate` is set r~_stranger += x (Kahan-compensated).
+//   plain    : x = (1-c)*sum, stored in xs_out when set (the iterates the
+//            adjoint needs), next gathered vector as above.
+// The family restart c*q is c*[v == seed] for seed lists, or c*Q[j][v] for
+// dense restart vectors (seed-major Q, qdense set).
 struct StepParams {
     const int64_t *rowptr = nullptr;
     const int32_t *col = nullptr;
@@ -37,6 +41,8 @@ struct StepParams {
     int64_t n = 0;
     int64_t out_col0 = 0;
     int32_t *err = nullptr;            // sticky error flag (invalid seed)
+    const float *qdense = nullptr;     // dense restart vectors, seed-major [*, n] (tile offset applied)
+    float *xs_out = nullptr;           // plain mode: iterate store [n][kt]
     // stranger
     float *acc = nullptr;
     float *comp = nullptr;
@@ -49,6 +55,13 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
 // T == 0 else 0, comp = 0, where r0 = 1/n or 1/n_block(v).
 tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, float *zout, float *acc,
                                 float *comp, hipStream_t st);
+
+// z0 = c*Q^T tile (node-major, scaled by 1/outdeg for uniform weights) and,
+// when x0 is set, the unscaled x(0) = c*Q tile; columns >= ncols are zero.
+tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStream_t st);
+
+// x(0) = c*e_seed tile for seed lists (node-major), columns >= ncols zero.
+tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
 // A seed outside [0, n) (or outside its block on a packed graph) gives a

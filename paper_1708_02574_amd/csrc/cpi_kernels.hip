@@ -73,6 +73,8 @@ __device__ __forceinline__ EpiPre epi_load(const StepParams &p, int64_t v) {
     if (MODE == kFamily) {
         if (p.last) q.a = p.str[v];
         else if (!p.w) q.a = p.inv[v];
+    } else if (MODE == kPlain) {
+        if (!p.w) q.a = p.inv[v];
     } else {
         if (!p.w) q.a = p.inv[v];
         if (p.accumulate) {
@@ -96,11 +98,18 @@ template <int MODE>
 __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j, float sum, const EpiPre &q) {
     if (MODE == kFamily) {
         if (j >= p.ncols) return;
-        const int32_t seed = seed_of(p, v, j);
-        const float y = fmaf(p.omc, sum, (v == (int64_t)seed) ? p.c : 0.0f);
+        int32_t seed = -1;
+        float restart;
+        if (p.qdense) {
+            restart = p.c * p.qdense[(int64_t)j * p.n + v];
+        } else {
+            seed = seed_of(p, v, j);
+            restart = (v == (int64_t)seed) ? p.c : 0.0f;
+        }
+        const float y = fmaf(p.omc, sum, restart);
         if (p.last) {
             float o;
-            if (seed_valid(p, v, seed)) {
+            if (p.qdense || seed_valid(p, v, seed)) {
                 o = fmaf(p.alpha, y, q.a);
             } else {
                 o = qnan();
@@ -110,6 +119,10 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
         } else {
             p.zout[v * p.kt + j] = p.w ? y : y * q.a;
         }
+    } else if (MODE == kPlain) {
+        const float x = p.omc * sum;
+        if (p.xs_out) p.xs_out[v * p.kt + j] = x;
+        p.zout[v * p.kt + j] = p.w ? x : x * q.a;
     } else {
         const float x = p.omc * sum;
         p.zout[v] = p.w ? x : x * q.a;
@@ -428,16 +441,44 @@ __global__ void stranger_init_kernel(int64_t n, float c, const float *restart_pr
     }
 }
 
+__global__ void dense_init_kernel(StepParams p, float *z0, float *x0) {
+    const int64_t total = p.n * (int64_t)p.kt;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / p.kt;
+        const int j = (int)(i - v * p.kt);
+        const float x = j < p.ncols ? p.c * p.qdense[(int64_t)j * p.n + v] : 0.0f;
+        z0[i] = p.w ? x : x * p.inv[v];
+        if (x0) x0[i] = x;
+    }
+}
+
+__global__ void onehot_init_kernel(StepParams p, float *x0) {
+    const int64_t total = p.n * (int64_t)p.kt;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i / p.kt;
+        const int j = (int)(i - v * p.kt);
+        x0[i] = (v == (int64_t)seed_of(p, v, j)) ? p.c : 0.0f;
+    }
+}
+
 __global__ void combine_only_kernel(StepParams p) {
     const int64_t total = p.n * (int64_t)p.ncols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int j = (int)(i / p.n);
         const int64_t v = i - (int64_t)j * p.n;
-        const int32_t seed = seed_of(p, v, j);
-        const float y = (v == (int64_t)seed) ? p.c : 0.0f;
+        int32_t seed = -1;
+        float y;
+        if (p.qdense) {
+            y = p.c * p.qdense[(int64_t)j * p.n + v];
+        } else {
+            seed = seed_of(p, v, j);
+            y = (v == (int64_t)seed) ? p.c : 0.0f;
+        }
         float o;
-        if (seed_valid(p, v, seed)) {
+        if (p.qdense || seed_valid(p, v, seed)) {
             o = fmaf(p.alpha, y, p.str[v]);
         } else {
             o = qnan();
@@ -491,6 +532,9 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
         if (mode == kFamily) {
             if (first) launch_w<kFamily, true>(s, p, st);
             else launch_w<kFamily, false>(s, p, st);
+        } else if (mode == kPlain) {
+            if (first) launch_w<kPlain, true>(s, p, st);
+            else launch_w<kPlain, false>(s, p, st);
         } else {
             launch_w<kStranger, false>(s, p, st);
         }
@@ -500,6 +544,8 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
         const int slot = profile_begin(127, st);
         if (mode == kFamily)
             finish_kernel<kFamily><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
+        else if (mode == kPlain)
+            finish_kernel<kPlain><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
         else
             finish_kernel<kStranger><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
         profile_end(slot, st);
@@ -512,6 +558,18 @@ tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, flo
                                 float *comp, hipStream_t st) {
     stranger_init_kernel<<<grid_1d(g->n), 256, 0, st>>>(g->n, c, g->restart_pr, (float)(1.0 / (double)g->n),
                                                          g->inv_deg, g->t.w, include_x0, zout, acc, comp);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStream_t st) {
+    dense_init_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p, z0, x0);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st) {
+    onehot_init_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p, x0);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

@@ -399,16 +399,18 @@ void Schedule::release() {
 //   * runs of rows with <= EW edges: greedy groups of at most 63 rows and
 //     EW edges (rows of <= DS = 32 edges are summed one lane per row, longer
 //     ones by the whole wave).
-tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Schedule **out) {
-    auto it = g->sched_t.find(shape);
-    if (it != g->sched_t.end()) { *out = &it->second; return TPA_OK; }
+tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Schedule **out, bool over_a) {
+    auto &cache = over_a ? g->sched_a : g->sched_t;
+    const int64_t *rowptr_dev = over_a ? g->a.rowptr : g->t.rowptr;
+    auto it = cache.find(shape);
+    if (it != cache.end()) { *out = &it->second; return TPA_OK; }
     const int64_t n = g->n;
     const int ew = shape.ew, el = shape.el, chunk = shape.chunk;
     if (ew < 1 || el < ew || chunk < 1 || el > (1 << 16) || chunk > (1 << 16))
         return fail(TPA_ERR_INVALID_ARG, "bad schedule shape");
     const int ds = std::min(32, ew);
     std::vector<int64_t> rp(n + 1);
-    TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->t.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    TPA_TRY_HIP(hipMemcpyAsync(rp.data(), rowptr_dev, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
     TPA_TRY_HIP(hipStreamSynchronize(st));
     std::vector<Item> chunks, rows, groups;
     std::vector<LongRow> longs;
@@ -463,7 +465,7 @@ tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Sc
         TPA_TRY_HIP(hipMemcpyAsync(s.longs, longs.data(), sizeof(LongRow) * s.n_long, hipMemcpyHostToDevice, st));
     }
     TPA_TRY_HIP(hipStreamSynchronize(st));
-    auto ins = g->sched_t.emplace(shape, s);
+    auto ins = cache.emplace(shape, s);
     *out = &ins.first->second;
     return TPA_OK;
 }
@@ -475,7 +477,9 @@ void graph_release(tpa_graph *g) {
     dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
     dfree(g->str); dfree(g->ws); dfree(g->dev_err);
     for (auto &kv : g->sched_t) kv.second.release();
+    for (auto &kv : g->sched_a) kv.second.release();
     g->sched_t.clear();
+    g->sched_a.clear();
 }
 
 }  // namespace tpa

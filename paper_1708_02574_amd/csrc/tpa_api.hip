@@ -47,6 +47,8 @@ namespace {
 constexpr int kDefaultEW1 = 512;   // group edge budget, single vector
 constexpr int kDefaultEW64 = 256;  // group edge budget, seed tiles
 
+}  // namespace
+
 // First i >= 1 with c (1-c)^i < eps: Algorithm 1's L1 break, with the
 // per-block norm ||x'(i)||_1 = c (1-c)^i of Lemma 2.
 int64_t stranger_last_iteration(double c, double eps) {
@@ -77,6 +79,8 @@ int choose_kt(const tpa_graph *g, int64_t k) {
     while (kt < k && kt < 16) kt <<= 1;
     return kt;
 }
+
+namespace {
 
 // Workspace layout (floats): z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt]
 size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt) {
@@ -112,13 +116,16 @@ tpa_status check_query_args(tpa_graph *g, double c, int S, int T) {
     return TPA_OK;
 }
 
-// Shared driver: `k` columns, seeds [k] (plain) or [nblocks][k] (packed).
-tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed, double c, int S, int T,
-                     float *out, hipStream_t st) {
+}  // namespace
+
+// Shared driver: `k` columns; restart from seeds [k] (plain) or
+// [nblocks][k] (packed), or from dense seed-major vectors q [k][n].
+tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
+                     int S, int T, float *out, hipStream_t st) {
     TPA_TRY(check_query_args(g, c, S, T));
     if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
     if (k == 0) return TPA_OK;
-    if (!seeds || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/out is NULL");
+    if ((!seeds && !q) || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/q/out is NULL");
     if (packed && !g->node_block) return fail(TPA_ERR_INVALID_ARG, "graph is not packed");
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
@@ -146,7 +153,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed,
     p.out = out;
     p.n = g->n;
     for (int64_t base = 0; base < k; base += kt) {
-        p.seeds = seeds + base;
+        p.seeds = seeds ? seeds + base : nullptr;
+        p.qdense = q ? q + base * g->n : nullptr;
         p.ncols = (int)std::min<int64_t>(kt, k - base);
         p.out_col0 = base;
         if (S == 1) {
@@ -154,17 +162,18 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, int64_t k, bool packed,
             TPA_TRY(launch_combine_only(p, st));
             continue;
         }
+        if (q) TPA_TRY(launch_dense_init(p, z0, nullptr, st));
         for (int step = 1; step <= S - 1; ++step) {
             p.zin = (step & 1) ? z0 : z1;
             p.zout = (step & 1) ? z1 : z0;
             p.last = step == S - 1;
-            TPA_TRY(launch_step(*s, kFamily, step == 1, p, st));
+            // one-hot restart: the first step needs no gather
+            TPA_TRY(launch_step(*s, kFamily, step == 1 && !q, p, st));
         }
     }
     return TPA_OK;
 }
 
-}  // namespace
 }  // namespace tpa
 
 using namespace tpa;
@@ -243,13 +252,19 @@ extern "C" tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t st) {
 
 extern "C" tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
                                 float *out, hipStream_t st) {
-    return run_query(g, seeds, k, false, c, S, T, out, st);
+    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st);
+}
+
+extern "C" tpa_status tpa_query_dense(tpa_graph_t g, const float *q, int64_t k, double c, int S, int T,
+                                      float *out, hipStream_t st) {
+    if (k > 0 && !q) return fail(TPA_ERR_INVALID_ARG, "q is NULL");
+    return run_query(g, nullptr, q, k, false, c, S, T, out, st);
 }
 
 extern "C" tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, double c, int S,
                                        int T, float *out, hipStream_t st) {
     if (per_block < 1) return fail(TPA_ERR_INVALID_ARG, "per_block must be >= 1");
-    return run_query(g, seeds, per_block, true, c, S, T, out, st);
+    return run_query(g, seeds, nullptr, per_block, true, c, S, T, out, st);
 }
 
 extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {

@@ -118,8 +118,9 @@ struct tpa_graph {
     int64_t K = 0;
     float *str = nullptr;                   // r~_stranger, n
 
-    // schedules over A~^T keyed by shape
+    // schedules over the rows of A~^T (forward) and of A~ (adjoint), by shape
     std::map<tpa::SchedShape, tpa::Schedule> sched_t;
+    std::map<tpa::SchedShape, tpa::Schedule> sched_a;
 
     // query workspace
     float *ws = nullptr;
@@ -133,8 +134,15 @@ struct tpa_graph {
 
 namespace tpa {
 
+int64_t stranger_last_iteration(double c, double eps);
+int choose_kt(const tpa_graph *g, int64_t k);
+SchedShape choose_shape(const tpa_graph *g, int kt);
+tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
+                     int S, int T, float *out, hipStream_t st);
 tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);
-tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out);
+// Work schedule over the rows of A~^T (over_a = false) or of A~ (true).
+tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out,
+                        bool over_a = false);
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);

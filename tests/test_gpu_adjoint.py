@@ -1,0 +1,206 @@
+"""Adjoint CPI and dense restart vectors on the GPU vs the FP64 oracle.
+
+Gradients have no unit mass, so they are compared by normalised L1,
+||g - g*||_1 / ||g*||_1 <= 1e-5 (the oracle's gradient is itself pinned by
+central finite differences in test_oracle.py).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tpa_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+c, S, T, EPS = ti.C, ti.S, ti.T, ti.EPS
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def tpa(torch):
+    import paper_1708_02574_amd as _tpa
+    _tpa.load_library()
+    return _tpa
+
+
+def nl1(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300)
+
+
+def l1_rows(a, b):
+    return np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum(axis=-1)
+
+
+def onehot(n, seeds):
+    q = np.zeros((len(seeds), n))
+    q[np.arange(len(seeds)), seeds] = 1.0
+    return q
+
+
+@pytest.fixture(scope="module")
+def g10(tpa):
+    scale, samples, seed = 10, 12000, 77
+    og = oracle.Graph.rmat(scale, samples, seed)
+    gg = tpa.Graph.rmat(scale, samples, seed)
+    return og, gg
+
+
+def test_query_dense_parity(g10, torch):
+    og, gg = g10
+    og.set_logits(None)
+    gg.set_logits(None)
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    rng = np.random.default_rng(3)
+    Q = rng.random((5, og.n))
+    Q /= Q.sum(axis=1, keepdims=True)
+    Q[0] = 0.0
+    Q[0, 17] = 1.0                      # one-hot column
+    Q[1] = 0.0
+    Q[1, [3, 9, 400]] = 1.0 / 3.0       # seed set
+    for kt in (1, 4, 64):
+        gg.set_tuning(seed_tile=kt)
+        R = gg.query_dense(torch.from_numpy(Q.astype(np.float32)), c, S, T).cpu().numpy()
+        expect = np.stack([og.query_q(q, c, S, T) for q in Q])
+        assert np.all(l1_rows(R, expect) <= TOL), l1_rows(R, expect)
+    gg.set_tuning(0, 0)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("kt", [1, 4, 64])
+def test_backward_seeds_vs_oracle(g10, tpa, torch, weighted, kt):
+    og, gg = g10
+    theta = ti.draw_logits(og.m, 5) if weighted else np.zeros(og.m, np.float32)
+    og.set_logits(theta.astype(np.float64) if weighted else None)
+    gg.set_logits(torch.from_numpy(theta).cuda() if weighted else None)
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, 6, 11)
+    W = ti.draw_loss_weights((6, og.n), 12)
+    gg.set_tuning(seed_tile=kt)
+    try:
+        dth, dq = gg.backward(torch.from_numpy(W), c, S, T, seeds=torch.from_numpy(seeds))
+    finally:
+        gg.set_tuning(0, 0)
+    odth, _, odq = og.backward(onehot(og.n, seeds), W.astype(np.float64), c, S, T, og.K)
+    assert nl1(dth.cpu().numpy(), odth) <= TOL, nl1(dth.cpu().numpy(), odth)
+    assert nl1(dq.cpu().numpy(), odq) <= TOL, nl1(dq.cpu().numpy(), odq)
+
+
+def test_backward_dense_q_and_checkpoints(g10, tpa, torch):
+    og, gg = g10
+    theta = ti.draw_logits(og.m, 6)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    rng = np.random.default_rng(8)
+    Q = rng.random((3, og.n))
+    Q /= Q.sum(axis=1, keepdims=True)
+    W = ti.draw_loss_weights((3, og.n), 9)
+    odth, _, odq = og.backward(Q, W.astype(np.float64), c, S, T, og.K)
+    ref = None
+    for ck in (0, 1, 7, 116, -1):
+        dth, dq = gg.backward(torch.from_numpy(W), c, S, T, q=torch.from_numpy(Q.astype(np.float32)),
+                              checkpoint_every=ck)
+        dth = dth.cpu().numpy()
+        assert nl1(dth, odth) <= TOL
+        assert nl1(dq.cpu().numpy(), odq) <= TOL
+        if ref is None:
+            ref = dth
+        else:
+            assert np.array_equal(dth, ref)  # recomputed iterates are bit-identical
+
+
+@pytest.mark.parametrize("Sq,Tq", [(1, 10), (2, 10), (5, 5), (3, 20)])
+def test_backward_S_T_cases(tpa, torch, Sq, Tq):
+    og = oracle.Graph.rmat(9, 5000, 21)
+    gg = tpa.Graph.rmat(9, 5000, 21)
+    theta = ti.draw_logits(og.m, 2)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, Tq, EPS)
+    gg.preprocess(c, Tq)
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, 3, 4)
+    W = ti.draw_loss_weights((3, og.n), 5)
+    dth, dq = gg.backward(torch.from_numpy(W), c, Sq, Tq, seeds=torch.from_numpy(seeds))
+    odth, _, odq = og.backward(onehot(og.n, seeds), W.astype(np.float64), c, Sq, Tq, og.K)
+    assert nl1(dth.cpu().numpy(), odth) <= TOL
+    assert nl1(dq.cpu().numpy(), odq) <= TOL
+
+
+def test_backward_long_rows(g10, tpa, torch):
+    """Small items force chunked long rows in both orientations."""
+    og, gg = g10
+    og.set_logits(None)
+    gg.set_logits(None)
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, 5, 1)
+    W = ti.draw_loss_weights((5, og.n), 2)
+    odth, _, odq = og.backward(onehot(og.n, seeds), W.astype(np.float64), c, S, T, og.K)
+    for kt in (1, 4):
+        gg.set_tuning(seed_tile=kt, edges_per_item=64)
+        try:
+            dth, dq = gg.backward(torch.from_numpy(W), c, S, T, seeds=torch.from_numpy(seeds))
+        finally:
+            gg.set_tuning(0, 0)
+        assert nl1(dth.cpu().numpy(), odth) <= TOL
+        assert nl1(dq.cpu().numpy(), odq) <= TOL
+
+
+def test_backward_packed_blocks(tpa, torch):
+    params = [(9, 4000, 1, 400), (10, 9000, 2, 0), (8, 1500, 3, 200)]
+    ogs, ggs = [], []
+    for scale, samples, seed, nn in params:
+        n_nodes = nn or (1 << scale)
+        ogs.append(oracle.Graph.rmat(scale, samples, seed, n_nodes=n_nodes))
+        ggs.append(tpa.Graph.rmat(scale, samples, seed, n_nodes=n_nodes))
+    pk = tpa.Graph.pack(ggs)
+    pk.preprocess(c, T)
+    off = pk.block_offsets()
+    P = 2
+    loc = [ti.draw_seeds(og.export()["padded"] == 0, P, 30 + b) for b, og in enumerate(ogs)]
+    seeds = np.stack([off[b] + loc[b] for b in range(3)]).astype(np.int32)
+    W = ti.draw_loss_weights((P, pk.n), 31)
+    dth, dq = pk.backward(torch.from_numpy(W), c, S, T, seeds=torch.from_numpy(seeds), packed=True)
+    dth = dth.cpu().numpy()
+    dq = dq.cpu().numpy()
+    eoff = 0
+    for b, og in enumerate(ogs):
+        og.preprocess(c, T, EPS)
+        lo, hi = off[b], off[b + 1]
+        odth, _, odq = og.backward(onehot(og.n, loc[b]), W[:, lo:hi].astype(np.float64), c, S, T, og.K)
+        assert nl1(dth[eoff:eoff + og.m], odth) <= TOL
+        assert nl1(dq[:, lo:hi], odq) <= TOL
+        eoff += og.m
+
+
+def test_autograd_function(g10, tpa, torch):
+    og, gg = g10
+    theta = torch.from_numpy(ti.draw_logits(og.m, 13)).cuda().requires_grad_(True)
+    rng = np.random.default_rng(14)
+    Qn = rng.random((2, og.n))
+    Qn /= Qn.sum(axis=1, keepdims=True)
+    Q = torch.from_numpy(Qn.astype(np.float32)).cuda().requires_grad_(True)
+    W = torch.from_numpy(ti.draw_loss_weights((2, og.n), 15)).cuda()
+    R = tpa.TPAFunction.apply(theta, Q, gg, c, S, T)
+    loss = (R * W).sum()
+    loss.backward()
+    og.set_logits(theta.detach().cpu().numpy().astype(np.float64))
+    _, K = og.tpa_forward(Qn, c, S, T, EPS)
+    odth, _, odq = og.backward(Qn, W.cpu().numpy().astype(np.float64), c, S, T, K)
+    assert nl1(theta.grad.cpu().numpy(), odth) <= TOL
+    assert nl1(Q.grad.cpu().numpy(), odq) <= TOL
+    og.preprocess(c, T, EPS)
+    expect = np.stack([og.query_q(q, c, S, T) for q in Qn])
+    assert np.all(l1_rows(R.detach().cpu().numpy(), expect) <= TOL)
