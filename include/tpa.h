@@ -187,6 +187,36 @@ tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const float *q, int
                         double c, int S, int T, const float *grad_out, float *grad_logits,
                         float *grad_q, int checkpoint_every, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Captured queries (HIP graphs).  tpa_query_graph_create records the whole
+ * launch sequence of a query (seeds: as tpa_query / tpa_query_packed when
+ * packed != 0; or dense q as tpa_query_dense) into a HIP graph with its own
+ * workspace (allocated here, synchronously); tpa_query_graph_launch replays
+ * it on `stream`.  The seeds / q / out buffers are fixed at capture; their
+ * contents may change between replays.  Re-create after
+ * tpa_graph_set_logits, tpa_preprocess with other parameters or
+ * tpa_set_tuning.  The graph handle must outlive the capture, and a replay
+ * must not overlap other queries on the same handle.  Errors: INVALID_ARG,
+ * NOT_PREPROCESSED, PARAM_MISMATCH, OOM, HIP. */
+typedef struct tpa_query_graph *tpa_query_graph_t;
+tpa_status tpa_query_graph_create(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k,
+                                  int packed, double c, int S, int T, float *out, hipStream_t stream,
+                                  tpa_query_graph_t *out_graph);
+tpa_status tpa_query_graph_launch(tpa_query_graph_t qg, hipStream_t stream);
+tpa_status tpa_query_graph_destroy(tpa_query_graph_t qg);
+
+/* Autotuner: times tpa_query on the caller's k seeds (device) for every
+ * candidate seed tile (8..64, and 1 when k <= 4) and group edge budget
+ * (128, 256, 512), keeps candidates whose first min(k, 8) outputs agree
+ * with the single-vector path within L1 <= 1e-5 per seed, and stores the
+ * fastest with tpa_set_tuning.  scratch_out is a float[k][n] device buffer
+ * it may overwrite.  Outputs (host, nullable): best seed tile, edge budget,
+ * milliseconds per query call.  Synchronous.  Errors: INVALID_ARG,
+ * NOT_PREPROCESSED, OOM, HIP. */
+tpa_status tpa_autotune(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
+                        float *scratch_out, int *best_tile, int *best_edges_per_item, double *best_ms,
+                        hipStream_t stream);
+
 /* Pre-allocate the query workspace for up to k seeds (or per_block slots),
  * so that later queries allocate nothing (e.g. under stream capture). */
 tpa_status tpa_reserve(tpa_graph_t g, int64_t k);

@@ -51,6 +51,10 @@ _SIGS = {
     "tpa_query_packed": (_i, [_vp, _vp, _i, _d, _i, _i, _vp, _vp]),
     "tpa_query_dense": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_backward": (_i, [_vp, _vp, _vp, _i64, _i, _d, _i, _i, _vp, _vp, _vp, _i, _vp]),
+    "tpa_query_graph_create": (_i, [_vp, _vp, _vp, _i64, _i, _d, _i, _i, _vp, _vp, _vp]),
+    "tpa_query_graph_launch": (_i, [_vp, _vp]),
+    "tpa_query_graph_destroy": (_i, [_vp]),
+    "tpa_autotune": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "tpa_reserve": (_i, [_vp, _i64]),
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
@@ -313,6 +317,40 @@ class Graph:
               checkpoint_every, _stream(stream))
         return dth, dq
 
+    def capture_query(self, c: float, S: int, T: int, out, seeds=None, q=None, packed: bool = False,
+                      stream=None) -> "QueryGraph":
+        """Record a query into a HIP graph; seeds / q / out must stay alive and
+        keep their addresses (their contents may change between replays)."""
+        torch = _torch()
+        sp = qp = None
+        if seeds is not None:
+            if seeds.dtype != torch.int32 or not seeds.is_cuda or not seeds.is_contiguous():
+                raise ValueError("seeds must be a contiguous int32 device tensor")
+            sp, keep, k = _ptr(seeds), seeds, (seeds.shape[1] if packed else seeds.numel())
+        elif q is not None:
+            if q.dtype != torch.float32 or not q.is_cuda or not q.is_contiguous():
+                raise ValueError("q must be a contiguous float32 device tensor")
+            qp, keep, k = _ptr(q), q, q.shape[0]
+        else:
+            raise ValueError("pass seeds or q")
+        h = _vp()
+        _call("tpa_query_graph_create", self._h, sp, qp, k, int(packed), c, S, T, _ptr(out),
+              _stream(stream), C.byref(h))
+        return QueryGraph(h.value, (self, keep, out))
+
+    def autotune(self, seeds, c: float, S: int, T: int, scratch_out=None, stream=None):
+        """Pick the fastest parity-checked (seed tile, edge budget) for these
+        seeds; returns (seed_tile, edges_per_item, ms)."""
+        torch = _torch()
+        sd = seeds.to(device="cuda", dtype=torch.int32).contiguous()
+        k = sd.numel()
+        if scratch_out is None:
+            scratch_out = torch.empty((k, self.n), dtype=torch.float32, device="cuda")
+        t, e, ms = C.c_int(), C.c_int(), C.c_double()
+        _call("tpa_autotune", self._h, _ptr(sd), k, c, S, T, _ptr(scratch_out), C.byref(t), C.byref(e),
+              C.byref(ms), _stream(stream))
+        return t.value, e.value, ms.value
+
     def reserve(self, k: int):
         _call("tpa_reserve", self._h, k)
 
@@ -327,6 +365,28 @@ class Graph:
     def device_error(self, stream=None):
         """Raise TPAError if a query since the last check saw a bad seed."""
         _call("tpa_get_device_error", self._h, _stream(stream))
+
+
+class QueryGraph:
+    """A captured query (tpa_query_graph_t); launch() replays it."""
+
+    def __init__(self, handle: int, keep):
+        self._h = _vp(handle)
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _call("tpa_query_graph_launch", self._h, _stream(stream))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().tpa_query_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd_function():

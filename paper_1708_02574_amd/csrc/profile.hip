@@ -43,6 +43,8 @@ tpa_status drain(Profiler &p) {
 int profile_begin(int code, hipStream_t st) {
     Profiler &p = prof();
     if (!p.on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return -1;
     std::lock_guard<std::mutex> lk(p.mu);
     if (p.seen[code]++ % p.period != 0) return -1;
     if (p.used == p.begin.size() && drain(p) != TPA_OK) return -1;

@@ -120,8 +120,15 @@ tpa_status check_query_args(tpa_graph *g, double c, int S, int T) {
 
 // Shared driver: `k` columns; restart from seeds [k] (plain) or
 // [nblocks][k] (packed), or from dense seed-major vectors q [k][n].
+size_t query_workspace_bytes(tpa_graph *g, int64_t k, hipStream_t st) {
+    const int kt = choose_kt(g, k);
+    const Schedule *s = nullptr;
+    if (get_schedule(g, choose_shape(g, kt), st, &s) != TPA_OK) return 0;
+    return query_ws_bytes(g, s, kt);
+}
+
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st) {
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes) {
     TPA_TRY(check_query_args(g, c, S, T));
     if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
     if (k == 0) return TPA_OK;
@@ -130,8 +137,13 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
-    TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt), st));
-    float *z0 = g->ws;
+    if (ws) {
+        if (ws_bytes < query_ws_bytes(g, s, kt)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
+    } else {
+        TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt), st));
+        ws = g->ws;
+    }
+    float *z0 = ws;
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
 
@@ -252,19 +264,19 @@ extern "C" tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t st) {
 
 extern "C" tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
                                 float *out, hipStream_t st) {
-    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st);
+    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st, nullptr, 0);
 }
 
 extern "C" tpa_status tpa_query_dense(tpa_graph_t g, const float *q, int64_t k, double c, int S, int T,
                                       float *out, hipStream_t st) {
     if (k > 0 && !q) return fail(TPA_ERR_INVALID_ARG, "q is NULL");
-    return run_query(g, nullptr, q, k, false, c, S, T, out, st);
+    return run_query(g, nullptr, q, k, false, c, S, T, out, st, nullptr, 0);
 }
 
 extern "C" tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int per_block, double c, int S,
                                        int T, float *out, hipStream_t st) {
     if (per_block < 1) return fail(TPA_ERR_INVALID_ARG, "per_block must be >= 1");
-    return run_query(g, seeds, nullptr, per_block, true, c, S, T, out, st);
+    return run_query(g, seeds, nullptr, per_block, true, c, S, T, out, st, nullptr, 0);
 }
 
 extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {

@@ -137,8 +137,10 @@ namespace tpa {
 int64_t stranger_last_iteration(double c, double eps);
 int choose_kt(const tpa_graph *g, int64_t k);
 SchedShape choose_shape(const tpa_graph *g, int kt);
+// Query driver; ws == nullptr uses (and grows) the handle's workspace.
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st);
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes);
+size_t query_workspace_bytes(tpa_graph *g, int64_t k, hipStream_t st);
 tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);
 // Work schedule over the rows of A~^T (over_a = false) or of A~ (true).
 tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out,

@@ -50,6 +50,11 @@ def test_header_status_codes_match_binding():
     lambda L: L.tpa_reserve(None, 1),
     lambda L: L.tpa_get_device_error(None, None),
     lambda L: L.tpa_graph_pack(None, 0, None, None),
+    lambda L: L.tpa_query_dense(None, None, 1, 0.15, 5, 10, None, None),
+    lambda L: L.tpa_backward(None, None, None, 1, 0, 0.15, 5, 10, None, None, None, 0, None),
+    lambda L: L.tpa_query_graph_create(None, None, None, 1, 0, 0.15, 5, 10, None, None, C.byref(C.c_void_p())),
+    lambda L: L.tpa_query_graph_launch(None, None),
+    lambda L: L.tpa_autotune(None, None, 1, 0.15, 5, 10, None, None, None, None, None),
 ])
 def test_null_handles_are_invalid_arg(call):
     lib = tpa.load_library()
