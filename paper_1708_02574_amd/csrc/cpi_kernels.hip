@@ -463,6 +463,35 @@ __global__ void onehot_init_kernel(StepParams p, float *x0) {
     }
 }
 
+__global__ void fill_zero_kernel(float *z, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = 0.0f;
+}
+
+// First family step from one-hot seeds, pushed over the seed's out-edges:
+// y1 = c e_s + (1-c) c A~^T e_s is non-zero only at s and its out-neighbors
+// (one wave per block's seed; the rest of z1 was zero-filled).
+__global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
+                                  int64_t nseeds) {
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (b >= nseeds) return;
+    const int32_t s = p.seeds[b * (p.node_block ? p.seed_stride : 0)];
+    if (s < 0 || (int64_t)s >= p.n) return;
+    if (p.node_block && p.node_block[s] != b) return;
+    const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
+    const float cw = p.c * p.omc;
+    bool self = false;
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
+        const int32_t v = a_col[e];
+        const float w = a_w ? a_w[e] : p.inv[s];
+        const float y = fmaf(cw, w, v == s ? p.c : 0.0f);
+        p.zout[v] = a_w ? y : y * p.inv[v];
+        self |= (v == s);
+    }
+    if (!__any(self) && lane == 0) p.zout[s] = a_w ? p.c : p.c * p.inv[s];
+}
+
 __global__ void combine_only_kernel(StepParams p) {
     const int64_t total = p.n * (int64_t)p.ncols;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
@@ -570,6 +599,14 @@ tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStrea
 
 tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st) {
     onehot_init_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p, x0);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nseeds, hipStream_t st) {
+    fill_zero_kernel<<<grid_1d(p.n), 256, 0, st>>>(p.zout, p.n);
+    push_first_kernel<<<(unsigned)((nseeds * 64 + 255) / 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col,
+                                                                            g->weighted ? g->a.w : nullptr, nseeds);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
