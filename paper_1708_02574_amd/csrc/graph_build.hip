@@ -125,6 +125,13 @@ __global__ void degree_kernel(const int32_t *deg, int64_t n, int64_t *deg64, int
     }
 }
 
+__global__ void max_deg_kernel(const int64_t *deg, int64_t n, unsigned long long *out) {
+    unsigned long long mx = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mx = max(mx, (unsigned long long)deg[i]);
+    atomicMax(out, mx);
+}
+
 __global__ void widen_kernel(const int32_t *in, int64_t n, int64_t *out) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -329,6 +336,14 @@ tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStrea
     TPA_TRY(exclusive_scan_i64(deg64, ustart, n + 1, st));
     TPA_TRY(exclusive_scan_i64(deg2, g->a.rowptr, n + 1, st));
     g->m = read_back(g->a.rowptr + n, st);
+    {
+        unsigned long long *mx = nullptr;
+        TPA_TRY(dalloc(&mx, 1, st));
+        TPA_TRY_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long), st));
+        max_deg_kernel<<<grid_for(n), kBlock, 0, st>>>(deg2, n, mx);
+        g->max_outdeg = (int64_t)read_back(mx, st);
+        dfree(mx);
+    }
     const int64_t m = g->m;
     // A~ columns + transposed keys
     uint64_t *tkeys = nullptr;
@@ -604,16 +619,19 @@ extern "C" tpa_status tpa_graph_pack(const tpa_graph_t *gs, int count, hipStream
     *out = nullptr;
     if (!gs || count < 1) return fail(TPA_ERR_INVALID_ARG, "need at least one graph");
     int64_t n = 0, m = 0;
+    int64_t maxd = 0;
     for (int i = 0; i < count; ++i) {
         if (!gs[i]) return fail(TPA_ERR_INVALID_ARG, "NULL graph handle");
         n += gs[i]->n;
         m += gs[i]->m;
+        maxd = std::max(maxd, gs[i]->max_outdeg);
     }
     if (n > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "packed node ids must fit int32");
     tpa_graph *g = new tpa_graph();
     TPA_TRY_HIP(hipGetDevice(&g->device));
     g->n = n;
     g->m = m;
+    g->max_outdeg = maxd;
     g->bits = key_bits(n);
     tpa_status s;
     auto bail = [&](tpa_status e) { graph_release(g); delete g; return e; };

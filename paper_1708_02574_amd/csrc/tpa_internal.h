@@ -98,6 +98,7 @@ struct Csr {
 struct tpa_graph {
     int device = 0;
     int64_t n = 0, m = 0;
+    int64_t max_outdeg = 0;                 // largest row of A~
     int bits = 1;                           // bits of a node id (key packing)
     int64_t nblocks = 1;
     std::vector<int64_t> block_off;         // host, nblocks+1
