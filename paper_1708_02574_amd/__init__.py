@@ -220,13 +220,15 @@ class Graph:
         _call("tpa_graph_blocks", self._h, out.ctypes.data_as(_vp))
         return out
 
-    def export(self, transpose: bool = False, stream=None):
+    def export(self, transpose: bool = False, col: bool = True, weights: bool = True, stream=None):
+        """(row_ptr, col, w) of A~ (or A~^T); col / w are None when not asked for."""
         torch = _torch()
         rp = torch.empty(self.n + 1, dtype=torch.int64, device="cuda")
-        col = torch.empty(self.m, dtype=torch.int32, device="cuda")
-        w = torch.empty(self.m, dtype=torch.float32, device="cuda")
-        _call("tpa_graph_export", self._h, int(transpose), _ptr(rp), _ptr(col), _ptr(w), _stream(stream))
-        return rp, col, w
+        cl = torch.empty(self.m, dtype=torch.int32, device="cuda") if col else None
+        w = torch.empty(self.m, dtype=torch.float32, device="cuda") if weights else None
+        _call("tpa_graph_export", self._h, int(transpose), _ptr(rp), _ptr(cl) if cl is not None else None,
+              _ptr(w) if w is not None else None, _stream(stream))
+        return rp, cl, w
 
     def padded(self, stream=None):
         torch = _torch()

@@ -292,20 +292,21 @@ __global__ void scale_kernel(const float *x, const float *inv, int use_inv, int6
         z[v] = use_inv ? x[v] * inv[v] : x[v];
 }
 
-// Row softmax backward, in place on G: one wave per row of A~.
+// Row softmax backward, in place on G: waves stride over the rows of A~.
 __global__ void softmax_bwd_kernel(const int64_t *rowptr, const float *w, const float *inv, int64_t n, float *G) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const int64_t b = rowptr[row], e = rowptr[row + 1];
-    const float iu = w ? 0.0f : inv[row];
-    float s = 0.0f;
-    for (int64_t i = b + lane; i < e; i += 64) s += (w ? w[i] : iu) * G[i];
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; row < n; row += nwaves) {
+        const int64_t b = rowptr[row], e = rowptr[row + 1];
+        const float iu = w ? 0.0f : inv[row];
+        float s = 0.0f;
+        for (int64_t i = b + lane; i < e; i += 64) s += (w ? w[i] : iu) * G[i];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    for (int64_t i = b + lane; i < e; i += 64) {
-        const float a = w ? w[i] : iu;
-        G[i] = a * (G[i] - s);
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        for (int64_t i = b + lane; i < e; i += 64) {
+            const float a = w ? w[i] : iu;
+            G[i] = a * (G[i] - s);
+        }
     }
 }
 
@@ -341,6 +342,8 @@ void launch_adj_kt(const Schedule &s, const AdjParams &p, hipStream_t st) {
 }
 
 tpa_status adj_step(const Schedule &s, const AdjParams &p, hipStream_t st) {
+    if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
+        return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
     if (s.n_items > 0) {
         int lg = 0;
         while ((1 << lg) < p.kt) ++lg;
@@ -552,8 +555,9 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         if (grad_q) gradq_kernel<<<grid_1d(n * ncols), 256, 0, st>>>(lc, n, kt, ncols, (float)c, base, grad_q);
     }
     if (grad_logits) {
-        softmax_bwd_kernel<<<(unsigned)((n * 64 + 255) / 256), 256, 0, st>>>(g->a.rowptr, g->weighted ? g->a.w : nullptr,
-                                                                          g->inv_deg, n, grad_logits);
+        const unsigned sgrid = (unsigned)std::min<int64_t>((n * 64 + 255) / 256, 1 << 20);
+        softmax_bwd_kernel<<<sgrid, 256, 0, st>>>(g->a.rowptr, g->weighted ? g->a.w : nullptr, g->inv_deg, n,
+                                                  grad_logits);
     }
     TPA_TRY_HIP(hipGetLastError());
     TPA_TRY_HIP(hipStreamSynchronize(st));  // scratch buffers are freed on return

@@ -554,6 +554,8 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
     if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
+    if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
+        return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
     if (s.n_items > 0) {
         int lg = 0;
         while ((1 << lg) < p.kt) ++lg;

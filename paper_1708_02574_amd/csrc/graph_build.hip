@@ -31,7 +31,7 @@ constexpr int kBlock = 256;
 
 inline unsigned grid_for(int64_t n, int block = kBlock) {
     int64_t g = (n + block - 1) / block;
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 30));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 22));  // grid-stride kernels
 }
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output j of the generator
@@ -183,21 +183,22 @@ __global__ void tkeys_with_ids_kernel(const int64_t *a_rowptr, const int32_t *a_
     }
 }
 
-// Row softmax of the logits over A~'s rows, one wave per row (fixed-order
-// reductions, so the weights are deterministic).
+// Row softmax of the logits over A~'s rows, waves striding over the rows
+// (fixed-order reductions, so the weights are deterministic).
 __global__ void softmax_rows_kernel(const int64_t *rowptr, int64_t n, const float *theta,
                                     float *w) {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    if (row >= n) return;
-    const int64_t b = rowptr[row], e = rowptr[row + 1];
-    float mx = -INFINITY;
-    for (int64_t i = b + lane; i < e; i += 64) mx = fmaxf(mx, theta[i]);
-    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    float s = 0.0f;
-    for (int64_t i = b + lane; i < e; i += 64) s += expf(theta[i] - mx);
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    for (int64_t i = b + lane; i < e; i += 64) w[i] = expf(theta[i] - mx) / s;
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; row < n; row += nwaves) {
+        const int64_t b = rowptr[row], e = rowptr[row + 1];
+        float mx = -INFINITY;
+        for (int64_t i = b + lane; i < e; i += 64) mx = fmaxf(mx, theta[i]);
+        for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        float s = 0.0f;
+        for (int64_t i = b + lane; i < e; i += 64) s += expf(theta[i] - mx);
+        for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+        for (int64_t i = b + lane; i < e; i += 64) w[i] = expf(theta[i] - mx) / s;
+    }
 }
 
 __global__ void gather_w_kernel(const float *aw, const int64_t *t2a, int64_t m, float *tw) {

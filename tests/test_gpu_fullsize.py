@@ -95,3 +95,100 @@ def test_rmat22_batched_sampled(tpa, torch):
     assert l1_rows(st, og.str) <= TOL
     for r, i in enumerate(sample):
         assert l1_rows(Rs[r], og.query(int(seeds[i]), c, S, T)) <= TOL
+
+
+def nl1(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b).sum() / max(np.abs(b).sum(), 1e-300)
+
+
+def test_uneven_graph_batch_with_adjoint(tpa, torch):
+    """256 R-MAT graphs, node counts log-uniform in [2^12, 2^18], average
+    out-degree 16, packed block-diagonally, 4 seeds per block, row-softmax
+    weights from logits theta ~ N(0, 0.1), loss weights w ~ N(0, 1):
+    forward and both gradients against the oracle on sampled blocks."""
+    sizes = ti.block_sizes(256, 2024)
+    params = ti.block_rmat_params(sizes, 2024)
+    print("uneven: building 256 graphs", flush=True)
+    ggs = [tpa.Graph.rmat(sc, smp, sd, n_nodes=ng) for sc, ng, smp, sd in params]
+    pk = tpa.Graph.pack(ggs)
+    off = pk.block_offsets()
+    eoff = np.concatenate([[0], np.cumsum([g.m for g in ggs])])
+    del ggs
+    theta = ti.draw_logits(pk.m, 2025)
+    pk.set_logits(torch.from_numpy(theta).cuda())
+    pk.preprocess(c, T)
+    padded = pk.padded().cpu().numpy()
+    P = 4
+    seeds = np.stack([off[b] + ti.draw_seeds(padded[off[b]:off[b + 1]] == 0, P, 3000 + b)
+                      for b in range(256)]).astype(np.int32)
+    W = ti.draw_loss_weights((P, pk.n), 2026)
+    sd = torch.from_numpy(seeds).cuda()
+    print(f"uneven: N={pk.n} m={pk.m}: query + backward", flush=True)
+    R = pk.query_packed(sd, c, S, T)
+    dth, dq = pk.backward(torch.from_numpy(W), c, S, T, seeds=sd, packed=True)
+    R, dth, dq = R.cpu().numpy(), dth.cpu().numpy(), dq.cpu().numpy()
+    assert np.all(np.isfinite(R)) and R.min() >= 0
+    for b in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 200}):
+        sc, ng, smp, sdd = params[b]
+        lo, hi = off[b], off[b + 1]
+        og = oracle.Graph.rmat(sc, smp, sdd, n_nodes=ng)
+        assert og.m == eoff[b + 1] - eoff[b]
+        og.set_logits(theta[eoff[b]:eoff[b + 1]].astype(np.float64))
+        og.preprocess(c, T, EPS)
+        loc = seeds[b] - lo
+        for j in range(P):
+            assert l1_rows(R[j, lo:hi], og.query(int(loc[j]), c, S, T)) <= TOL
+        q = np.zeros((P, ng))
+        q[np.arange(P), loc] = 1.0
+        odth, _, odq = og.backward(q, W[:, lo:hi].astype(np.float64), c, S, T, og.K)
+        assert nl1(dth[eoff[b]:eoff[b + 1]], odth) <= TOL, b
+        assert nl1(dq[:, lo:hi], odq) <= TOL, b
+
+
+def test_billion_edge_graph_properties(tpa, torch):
+    """2^27 nodes, 2^31 R-MAT samples (about 2.2e9 edges after dedupe and
+    dangling self-loops): preprocess, a 16-seed batched query and the adjoint
+    of 4 seeds with checkpointed iterates.  No oracle fits this size on the
+    host, so the check is by invariants: per-seed mass 1 - (1-c)^(K+1),
+    non-negativity, agreement of the single-vector and seed-tile paths,
+    zero row sums of the softmax backward, and equal gradients with and
+    without checkpointing."""
+    scale, samples, gseed = ti.GRAPHS["rmat27"]
+    print("rmat27: GPU build", flush=True)
+    g = tpa.Graph.rmat(scale, samples, gseed)
+    print(f"rmat27: n={g.n} m={g.m}: preprocess", flush=True)
+    assert g.m > 2_000_000_000
+    g.preprocess(c, T)
+    eligible = (g.padded() == 0).cpu().numpy()
+    seeds = torch.from_numpy(ti.draw_seeds(eligible, 16, 27)).cuda()
+    print("rmat27: batched query (kt=16) + two single-seed queries", flush=True)
+    g.set_tuning(seed_tile=16)
+    R = g.query(seeds, c, S, T)
+    g.set_tuning(0, 0)
+    mass = R.sum(dim=1, dtype=torch.float64).cpu().numpy()
+    assert np.all(np.abs(mass - MASS) < 1e-5)
+    assert float(R.min()) >= 0.0
+    for i in (0, 9):
+        r1 = g.query(seeds[i:i + 1], c, S, T)[0]
+        assert float((r1.double() - R[i].double()).abs().sum()) <= TOL
+    del R
+    print("rmat27: adjoint of 4 seeds (checkpoint every ceil(sqrt(K)))", flush=True)
+    W = torch.from_numpy(ti.draw_loss_weights((4, g.n), 28)).cuda()
+    dth, dq = g.backward(W, c, S, T, seeds=seeds[:4])
+    assert bool(torch.isfinite(dth).all()) and bool(torch.isfinite(dq).all())
+    # softmax backward: sum_v A~_uv dtheta_uv = 0 on every row u (sampled rows)
+    rp = g.export(transpose=False, col=False, weights=False)[0].cpu().numpy()
+    deg = np.diff(rp)
+    rng = np.random.default_rng(29)
+    rows = np.concatenate([[int(np.argmax(deg))], rng.integers(0, g.n, 2000)])
+    dth_h = dth.cpu().numpy()
+    scale_ref = float(np.abs(dth_h).max())
+    for u in rows:
+        seg = dth_h[rp[u]:rp[u + 1]].astype(np.float64)
+        assert abs(seg.sum()) <= 1e-5 * max(scale_ref, 1e-30) * max(1, len(seg)) ** 0.5
+    del dth_h
+    print("rmat27: adjoint without checkpoints (one segment)", flush=True)
+    dth2, dq2 = g.backward(W, c, S, T, seeds=seeds[:4], checkpoint_every=-1)
+    assert torch.equal(dth, dth2) and torch.equal(dq, dq2)
