@@ -63,10 +63,10 @@ tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStrea
 // x(0) = c*e_seed tile for seed lists (node-major), columns >= ncols zero.
 tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 
-// First family step for one seed per block (kt == 1) pushed over the
-// seed's out-edges of A~: zout = y1 scaled as the gathered vector, zero
-// elsewhere (a fill launch, then one wave per seed).
-tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nseeds, hipStream_t st);
+// First family step from seeds (any tile width) pushed over each seed's
+// out-edges of A~: zout = y1 scaled as the gathered vector, zero elsewhere
+// (a fill launch, then one wave per (block, column) seed).
+tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
 // A seed outside [0, n) (or outside its block on a packed graph) gives a

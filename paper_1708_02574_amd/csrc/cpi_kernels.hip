@@ -288,8 +288,39 @@ __device__ __forceinline__ float walk_value(const StepParams &p, int32_t u, floa
     return WEIGHTED ? w * z : z;
 }
 
+// Final output of the last family step for row v, column j (the fused
+// combine of Algorithm 3); NaN (and the sticky flag) for an invalid seed.
+__device__ __forceinline__ float family_out_value(const StepParams &p, int64_t v, int j, float sum) {
+    int32_t seed = -1;
+    float restart;
+    if (p.qdense) {
+        restart = p.c * p.qdense[(int64_t)j * p.n + v];
+    } else {
+        seed = seed_of(p, v, j);
+        restart = (v == (int64_t)seed) ? p.c : 0.0f;
+    }
+    const float y = fmaf(p.omc, sum, restart);
+    if (p.qdense || seed_valid(p, v, seed)) return fmaf(p.alpha, y, p.str[v]);
+    *p.err = 1;
+    return qnan();
+}
+
+// The last step of a 64-column tile stages 16 rows x 64 columns in LDS
+// (row stride 65) and writes each seed column's run of rows with one
+// coalesced store, instead of 64 scattered 4-byte stores per row.
+constexpr int kStageRows = 16;
+constexpr int kStageStride = 65;
+
+__device__ __forceinline__ void stage_write(const StepParams &p, const float *buf, int64_t row_base, int cnt,
+                                            int lane) {
+    wave_sync();
+    for (int j = 0; j < p.ncols; ++j)
+        if (lane < cnt) p.out[(p.out_col0 + j) * p.n + row_base + lane] = buf[lane * kStageStride + j];
+    wave_sync();
+}
+
 template <int MODE, bool FIRST, bool WEIGHTED>
-__device__ __forceinline__ void item_64(const StepParams &p, const Item it, int64_t wid, int lane) {
+__device__ __forceinline__ void item_64(const StepParams &p, const Item it, int64_t wid, int lane, float *buf) {
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     int32_t seed_plain = -1;
@@ -300,6 +331,7 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
     }
     constexpr int U = 16;
     if (kind == (int)kItemGroup) {
+        const bool staged = MODE == kFamily && p.last;
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
         int r = 0;
@@ -322,7 +354,14 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
                     if (t0 + k < cnt) {
                         const int e = base + t0 + k;
                         while (e >= rend) {
-                            epilogue<MODE>(p, it.row0 + r, lane, acc);
+                            if (staged) {
+                                buf[(r % kStageRows) * kStageStride + lane] =
+                                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc) : 0.0f;
+                                if (r % kStageRows == kStageRows - 1)
+                                    stage_write(p, buf, it.row0 + r - (kStageRows - 1), kStageRows, lane);
+                            } else {
+                                epilogue<MODE>(p, it.row0 + r, lane, acc);
+                            }
                             acc = 0.0f;
                             ++r;
                             rend = __builtin_amdgcn_readlane(rel, r + 1);
@@ -333,9 +372,18 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
             }
         }
         for (; r < nrows; ++r) {
-            epilogue<MODE>(p, it.row0 + r, lane, acc);
+            if (staged) {
+                buf[(r % kStageRows) * kStageStride + lane] =
+                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc) : 0.0f;
+                if (r % kStageRows == kStageRows - 1)
+                    stage_write(p, buf, it.row0 + r - (kStageRows - 1), kStageRows, lane);
+            } else {
+                epilogue<MODE>(p, it.row0 + r, lane, acc);
+            }
             acc = 0.0f;
         }
+        if (staged && nrows % kStageRows)
+            stage_write(p, buf, it.row0 + nrows - nrows % kStageRows, nrows % kStageRows, lane);
         return;
     }
     // one row (or a chunk of one): U edges in flight, sequential per lane
@@ -366,10 +414,11 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
 template <int MODE, bool FIRST, bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void step_kernel_64(const Item *__restrict__ items, int64_t n_items,
                                                            StepParams p) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    __shared__ float stage[kWaves][kStageRows * kStageStride];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
     if (wid >= n_items) return;
-    item_64<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane);
+    item_64<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane, stage[wv]);
 }
 
 // ------------------------------------------------------------ kt = 2..32
@@ -468,15 +517,17 @@ __global__ void fill_zero_kernel(float *z, int64_t n) {
         z[i] = 0.0f;
 }
 
-// First family step from one-hot seeds, pushed over the seed's out-edges:
+// First family step from one-hot seeds, pushed over each seed's out-edges:
 // y1 = c e_s + (1-c) c A~^T e_s is non-zero only at s and its out-neighbors
-// (one wave per block's seed; the rest of z1 was zero-filled).
+// (one wave per (block, column) seed; the rest of zout was zero-filled).
 __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
-                                  int64_t nseeds) {
+                                  int64_t nslots) {
     const int lane = threadIdx.x & 63;
-    const int64_t b = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    if (b >= nseeds) return;
-    const int32_t s = p.seeds[b * (p.node_block ? p.seed_stride : 0)];
+    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (w >= nslots) return;
+    const int64_t b = w / p.ncols;
+    const int j = (int)(w - b * p.ncols);
+    const int32_t s = p.seeds[b * (p.node_block ? p.seed_stride : 0) + j];
     if (s < 0 || (int64_t)s >= p.n) return;
     if (p.node_block && p.node_block[s] != b) return;
     const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
@@ -484,12 +535,12 @@ __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const i
     bool self = false;
     for (int64_t e = e0 + lane; e < e1; e += 64) {
         const int32_t v = a_col[e];
-        const float w = a_w ? a_w[e] : p.inv[s];
-        const float y = fmaf(cw, w, v == s ? p.c : 0.0f);
-        p.zout[v] = a_w ? y : y * p.inv[v];
+        const float wt = a_w ? a_w[e] : p.inv[s];
+        const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
+        p.zout[(int64_t)v * p.kt + j] = a_w ? y : y * p.inv[v];
         self |= (v == s);
     }
-    if (!__any(self) && lane == 0) p.zout[s] = a_w ? p.c : p.c * p.inv[s];
+    if (!__any(self) && lane == 0) p.zout[(int64_t)s * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
 }
 
 __global__ void combine_only_kernel(StepParams p) {
@@ -605,10 +656,11 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st) {
     return TPA_OK;
 }
 
-tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nseeds, hipStream_t st) {
-    fill_zero_kernel<<<grid_1d(p.n), 256, 0, st>>>(p.zout, p.n);
-    push_first_kernel<<<(unsigned)((nseeds * 64 + 255) / 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col,
-                                                                            g->weighted ? g->a.w : nullptr, nseeds);
+tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st) {
+    const int64_t nslots = nblocks * p.ncols;
+    fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
+    push_first_kernel<<<(unsigned)((nslots * 64 + 255) / 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col,
+                                                                            g->weighted ? g->a.w : nullptr, nslots);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

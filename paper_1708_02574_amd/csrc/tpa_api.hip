@@ -179,8 +179,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             p.zin = (step & 1) ? z0 : z1;
             p.zout = (step & 1) ? z1 : z0;
             p.last = step == S - 1;
-            if (step == 1 && !q && kt == 1 && !p.last) {
-                // one seed: x(1) lives on the seed's out-edges; push it
+            if (step == 1 && !q && !p.last) {
+                // one-hot restarts: x(1) lives on the seeds' out-edges; push it
                 TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, st));
                 continue;
             }
