@@ -395,8 +395,10 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     Scratch sc;
 
     const Schedule *sf1 = nullptr, *sa1 = nullptr;
+    SchedShape adj_shape = choose_shape(g, 1);
+    adj_shape.eb = 0;  // the adjoint kernels take wave, group and chunk items
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
-    TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sa1, true));
+    TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
 
     if (grad_logits) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
@@ -484,8 +486,10 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     // ---- family chains per seed tile ----
     const int kt = choose_kt(g, k);
     const Schedule *sfk = nullptr, *sak = nullptr;
+    SchedShape adj_shape_k = choose_shape(g, kt);
+    adj_shape_k.eb = 0;
     TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &sfk, false));
-    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &sak, true));
+    TPA_TRY(get_schedule(g, adj_shape_k, st, &sak, true));
     const int nit = std::max(S - 1, 1);  // stored iterates x(0..S-2)
     float *xf, *z0, *z1, *lam0, *lam1, *part_f, *part_a;
     TPA_TRY(sc.get(&xf, (size_t)nit * n * kt, st));

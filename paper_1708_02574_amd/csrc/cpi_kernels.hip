@@ -262,7 +262,46 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
     }
 }
 
-// One wave per work item (the hardware dispatcher balances the waves).
+// A block item: the block's 4 waves each add a quarter of one row (64-edge
+// aligned), then wave 0 adds the quarter sums in wave order.
+template <int MODE, bool FIRST, bool WEIGHTED>
+__device__ __forceinline__ void block_row_1(const StepParams &p, const Item it, int lane, int wv,
+                                            float (*lds)[kGroupMax]) {
+    const int nnz = (int)item_nnz(it.meta);
+    const int qlen = (((nnz + kWaves - 1) / kWaves) + 63) & ~63;
+    const int qb = wv * qlen, qe = min(nnz, qb + qlen);
+    EpiPre q;
+    if (wv == 0 && lane == 0) q = epi_load<MODE>(p, it.row0);
+    const int32_t *col = p.col + it.e0;
+    constexpr int UNR = 16;
+    float s = 0.0f;
+    for (int base = qb; base < qe; base += 64 * UNR) {
+        int32_t u[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int e = base + k * 64 + lane;
+            u[k] = e < qe ? col[e] : -1;
+        }
+        float v[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k)
+            v[k] = u[k] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + base + k * 64 + lane, u[k], 0) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) s += v[k];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) lds[wv][0] = s;
+    __syncthreads();
+    if (wv == 0 && lane == 0) {
+        float t = lds[0][0];
+        for (int w = 1; w < kWaves; ++w) t += lds[w][0];
+        epi_store<MODE>(p, it.row0, 0, t, q);
+    }
+}
+
+// One wave per work item (the hardware dispatcher balances the waves); the
+// 4 slots of a block item are taken by the 4 waves of one block.
 template <int MODE, bool FIRST, bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict__ items, int64_t n_items,
                                                           StepParams p) {
@@ -270,7 +309,12 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
     if (wid >= n_items) return;
-    item_1<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane, lds[wv]);
+    const Item it = items[wid];
+    if (item_kind(it.meta) == kItemBlock) {
+        block_row_1<MODE, FIRST, WEIGHTED>(p, it, lane, wv, lds);
+        return;
+    }
+    item_1<MODE, FIRST, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
 // ------------------------------------------------------------ kt == 64
@@ -605,6 +649,7 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
     if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
+    if (p.kt != 1 && s.eb > s.el) return fail(TPA_ERR_INVALID_ARG, "block items need a single-column step");
     if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
         return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
     if (s.n_items > 0) {

@@ -410,7 +410,8 @@ void Schedule::release() {
 }
 
 // Rows of A~^T are cut into wave items, heaviest first so they start early:
-//   * rows longer than EL edges: chunks of CH edges (chunk items);
+//   * rows of EL+1..EB edges: one block item per row (4 aligned slots);
+//   * rows longer than max(EL, EB) edges: chunks of CH edges (chunk items);
 //   * rows of EW+1..EL edges: one item per row;
 //   * runs of rows with <= EW edges: greedy groups of at most 63 rows and
 //     EW edges (rows of <= DS = 32 edges are summed one lane per row, longer
@@ -422,13 +423,14 @@ tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Sc
     if (it != cache.end()) { *out = &it->second; return TPA_OK; }
     const int64_t n = g->n;
     const int ew = shape.ew, el = shape.el, chunk = shape.chunk;
-    if (ew < 1 || el < ew || chunk < 1 || el > (1 << 16) || chunk > (1 << 16))
+    const int64_t eb = std::max(shape.eb, el);
+    if (ew < 1 || el < ew || chunk < 1 || el > (1 << 16) || chunk > (1 << 16) || eb > (1 << 17) - 1)
         return fail(TPA_ERR_INVALID_ARG, "bad schedule shape");
     const int ds = std::min(32, ew);
     std::vector<int64_t> rp(n + 1);
     TPA_TRY_HIP(hipMemcpyAsync(rp.data(), rowptr_dev, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
     TPA_TRY_HIP(hipStreamSynchronize(st));
-    std::vector<Item> chunks, rows, groups;
+    std::vector<Item> blocks, chunks, rows, groups;
     std::vector<LongRow> longs;
     int64_t gstart = -1, gnnz = 0;
     auto close_group = [&](int64_t end) {
@@ -439,7 +441,11 @@ tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Sc
     };
     for (int64_t r = 0; r < n; ++r) {
         const int64_t d = rp[r + 1] - rp[r];
-        if (d > el) {
+        if (d > el && d <= eb) {
+            close_group(r);
+            const Item b = {rp[r], (int32_t)r, item_meta(1, (uint32_t)d, kItemBlock)};
+            for (int k = 0; k < 4; ++k) blocks.push_back(b);
+        } else if (d > el) {
             close_group(r);
             const int64_t nch = (d + chunk - 1) / chunk;
             if ((int64_t)chunks.size() + nch > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many chunk items");
@@ -464,13 +470,18 @@ tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Sc
     s.ds = ds;
     s.el = el;
     s.chunk = chunk;
+    s.eb = (int)eb;
+    // block items first (4-aligned), then chunks: chunk item i sits at index
+    // blocks.size() + i, which the finish pass's first_item must include
+    for (auto &lr : longs) lr.first_item += (int32_t)blocks.size();
     std::vector<Item> all;
-    all.reserve(chunks.size() + rows.size() + groups.size());
+    all.reserve(blocks.size() + chunks.size() + rows.size() + groups.size());
+    all.insert(all.end(), blocks.begin(), blocks.end());
     all.insert(all.end(), chunks.begin(), chunks.end());
     all.insert(all.end(), rows.begin(), rows.end());
     all.insert(all.end(), groups.begin(), groups.end());
     s.n_items = (int64_t)all.size();
-    s.n_chunk_items = (int64_t)chunks.size();
+    s.n_chunk_items = (int64_t)(blocks.size() + chunks.size());  // partial slots are item indices
     s.n_long = (int64_t)longs.size();
     if (s.n_items > 0) {
         TPA_TRY(dalloc(&s.items, s.n_items, st));

@@ -61,15 +61,17 @@ int64_t stranger_last_iteration(double c, double eps) {
 }
 
 // Schedule shape per seed-tile width: a single vector takes groups of up to
-// 512 edges, rows of up to 4*EW edges as one item and chunks of 2*EW; seed
-// tiles move kt floats per edge, so their items are shorter.
+// 512 edges, rows of up to 4*EW edges as one wave item, rows of up to
+// 128*EW edges as one block item (4 waves) and chunks of 16*EW beyond; seed tiles
+// move kt floats per edge, so their items are shorter and they have no
+// block items.
 SchedShape choose_shape(const tpa_graph *g, int kt) {
     if (kt == 1) {
         const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW1;
-        return {ew, 4 * ew, 2 * ew};
+        return {ew, 4 * ew, 16 * ew, 128 * ew};
     }
     const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW64;
-    return {ew, 2 * ew, ew};
+    return {ew, 2 * ew, ew, 0};
 }
 
 int choose_kt(const tpa_graph *g, int64_t k) {

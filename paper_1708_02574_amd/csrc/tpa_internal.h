@@ -48,12 +48,15 @@ void dfree(void *p);
 //   kind 2 (chunk) : a chunk [e0, e0+nnz) of a long row; its sum goes to
 //                    partial slot <item index>; a finish pass adds each long
 //                    row's partials in chunk order
+//   kind 3 (block) : the single row row0 shared by the 4 waves of a block
+//                    (the item is repeated in the block's 4 slots); the
+//                    waves' quarter sums are added in LDS in wave order
 struct Item {
     int64_t e0;
     int32_t row0;
     uint32_t meta;  // nrows [0,7) | nnz [7,24) | kind [24,26)
 };
-constexpr uint32_t kItemGroup = 0, kItemRow = 1, kItemChunk = 2;
+constexpr uint32_t kItemGroup = 0, kItemRow = 1, kItemChunk = 2, kItemBlock = 3;
 __host__ __device__ inline uint32_t item_meta(uint32_t nrows, uint32_t nnz, uint32_t kind) {
     return nrows | (nnz << 7) | (kind << 24);
 }
@@ -66,11 +69,15 @@ struct LongRow {
 };
 
 // Shape of a schedule: group items hold <= ew edges; rows of ew+1..el edges
-// are one item each; longer rows are cut into chunks of `chunk` edges.
+// are one wave item each; rows of el+1..eb edges are block items; longer
+// rows are cut into chunks of `chunk` edges.
 struct SchedShape {
-    int ew, el, chunk;
+    int ew, el, chunk, eb;
     bool operator<(const SchedShape &o) const {
-        return ew != o.ew ? ew < o.ew : (el != o.el ? el < o.el : chunk < o.chunk);
+        if (ew != o.ew) return ew < o.ew;
+        if (el != o.el) return el < o.el;
+        if (chunk != o.chunk) return chunk < o.chunk;
+        return eb < o.eb;
     }
 };
 
@@ -79,6 +86,7 @@ struct Schedule {
     int ds = 0;                  // group rows with <= ds edges are summed per lane
     int el = 0;                  // rows with > el edges are chunked
     int chunk = 0;               // chunk length
+    int eb = 0;                  // rows of el+1..eb edges are block items
     Item *items = nullptr;       // device; chunk items first
     int64_t n_items = 0;
     int64_t n_chunk_items = 0;

@@ -153,6 +153,28 @@ def test_schedules_with_long_rows(rmat13, torch, ew, kt):
     assert np.all(l1_rows(R, expect) <= TOL)
 
 
+@pytest.mark.parametrize("ew,kt", [(64, 1), (512, 1), (64, 4), (128, 64)])
+def test_hub_rows_blocks_and_chunks(tpa, torch, ew, kt):
+    """A graph whose hub has 20000 in-edges: with small items it becomes a
+    chunked row (finish pass); with the default single-vector shape it is a
+    block item shared by 4 waves."""
+    n = 30000
+    r = np.random.default_rng(9)
+    src = np.concatenate([np.arange(1, 20001), r.integers(0, n, 150000)]).astype(np.int32)
+    dst = np.concatenate([np.zeros(20000, np.int64), r.integers(0, n, 150000)]).astype(np.int32)
+    dst[20000:20000 + 3000] = 7          # a second, mid-size hub
+    og = oracle.Graph(n, src, dst)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    gg.set_tuning(seed_tile=kt, edges_per_item=ew)
+    gg.preprocess(c, T)
+    assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
+    seeds = np.array([5, 17, 20000, 29999, 7, 0], np.int32)
+    R = gg.query(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+    expect = np.stack([og.query(int(s), c, S, T) for s in seeds])
+    assert np.all(l1_rows(R, expect) <= TOL)
+
+
 @pytest.mark.parametrize("Sq,Tq", [(1, 10), (2, 10), (5, 5), (3, 7), (8, 10)])
 def test_query_S_T_cases(tpa, torch, Sq, Tq):
     og = oracle.Graph.rmat(11, 30000, 17)
