@@ -228,6 +228,34 @@ tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
 tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item);
 tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
 
+/* Direction of the second family step of a single-seed query (seed tile 1,
+ * unpacked graph, S >= 4).  x(1) lives on the seed's out-neighbours, so
+ * x(2) can be pushed over the out-edges of F = out(s) + {s} instead of
+ * pulled over all m edges (the same sum; Section 2.3's CPI step).  The
+ * choice is made on the device per query: push when the frontier's edge
+ * count W = sum of outdeg over F is at most `max_edges`.  max_edges = -1
+ * restores the default (m/8, at least 1024), 0 always pulls.  The pushed
+ * sums are exact fixed-point additions of FP32 terms, so results are
+ * reproducible but may differ from the pulled step in the last bits.
+ * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
+tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
+
+/* Memory order of the vectors a CPI step gathers (internal work buffers),
+ * for graphs with 1/outdeg weights.  hub_first = 1 (default): node v's
+ * entries sit at the rank of v by descending out-degree (ties by id), so
+ * the most gathered entries, those of high out-degree sources, share cache
+ * lines, and each row of A~^T is summed in ascending rank, so the lanes
+ * that read the first edges of neighbouring rows hit the same lines.  The
+ * re-sorted column ids are a second int32[m] array (plus int32[n] ranks),
+ * built by tpa_preprocess, or here when the graph is already preprocessed.
+ * hub_first = 0 keeps node order, A~^T's own edge order and no extra
+ * memory.  The two orders give the same sums up to FP32 rounding (each row
+ * is added in a different order).  Graphs with logit weights always use
+ * node order.  Synchronous when it builds.  Errors: INVALID_ARG, OOM, HIP. */
+tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first);
+tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
+tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);
+
 /* Sticky device-side error (synchronises `stream`): TPA_ERR_INVALID_ARG if
  * any query since the last call saw an out-of-range seed, else TPA_OK.
  * Clears the flag. */
@@ -241,8 +269,10 @@ tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
  * (mode 0 = online family step, 1 = preprocessing stranger step, 2 =
  * plain step keeping its iterate, 3 = adjoint step; first = the gather-free
  * first step from one-hot seeds, or for mode 3 = with the edge gradient;
- * weighted = explicit edge weights), and code 127 is the long-row finish
- * pass.  tpa_profile_read synchronises the
+ * weighted = explicit edge weights); codes 120 and 121 are the gated pull
+ * of a single seed's second family step (uniform, explicit weights), 124
+ * its pushed form (push and convert launches together), and 127 the
+ * long-row finish pass.  tpa_profile_read synchronises the
  * recorded events, adds their durations into per-code totals and returns
  * them (launches timed, milliseconds).  tpa_profile_reset clears the
  * totals.  Errors: INVALID_ARG (capacity outside 1..2^20, sample_period

@@ -58,6 +58,10 @@ _SIGS = {
     "tpa_reserve": (_i, [_vp, _i64]),
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
+    "tpa_set_push_limit": (_i, [_vp, _i64]),
+    "tpa_set_gather_layout": (_i, [_vp, _i]),
+    "tpa_get_gather_layout": (_i, [_vp, _vp]),
+    "tpa_get_push_limit": (_i, [_vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
     "tpa_profile_enable": (_i, [_i, _i, _i]),
     "tpa_profile_read": (_i, [_i, _vp, _vp]),
@@ -358,6 +362,28 @@ class Graph:
 
     def set_tuning(self, seed_tile: int = 0, edges_per_item: int = 0):
         _call("tpa_set_tuning", self._h, seed_tile, edges_per_item)
+
+    def set_push_limit(self, max_edges: int = -1):
+        """Single-seed queries push their second family step when the
+        seed's frontier has at most max_edges out-edges (-1: default m/8,
+        0: always pull)."""
+        _call("tpa_set_push_limit", self._h, max_edges)
+
+    def set_gather_layout(self, hub_first: bool = True):
+        """Order of the gathered work vectors and of each row's edge sum:
+        hub-first (default, 1/outdeg weights only) or node order; results
+        agree up to FP32 rounding."""
+        _call("tpa_set_gather_layout", self._h, int(bool(hub_first)))
+
+    def get_gather_layout(self) -> bool:
+        v = C.c_int()
+        _call("tpa_get_gather_layout", self._h, C.byref(v))
+        return bool(v.value)
+
+    def get_push_limit(self) -> int:
+        v = C.c_int64()
+        _call("tpa_get_push_limit", self._h, C.byref(v))
+        return v.value
 
     def get_tuning(self):
         a, b = C.c_int(), C.c_int()

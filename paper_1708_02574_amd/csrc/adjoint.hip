@@ -420,7 +420,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         // forward pass: checkpoints x'(0), x'(C), ...
-        TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, st));
+        TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, nullptr, st));
         StepParams fp;
         fp.rowptr = g->t.rowptr;
         fp.col = g->t.col;

@@ -25,6 +25,8 @@ struct StepParams {
     const float *inv = nullptr;        // 1/outdeg (uniform weights)
     const float *zin = nullptr;        // gathered vector [n][kt]
     float *zout = nullptr;             // next gathered vector [n][kt]
+    const int32_t *zperm = nullptr;    // row of node v in zin/zout (null: v); col is
+                                       // then given in those rows, except on first steps
     float *partials = nullptr;         // [chunk items][kt] chunk sums of long rows
     float omc = 0.f;                   // 1 - c
     float c = 0.f;
@@ -47,14 +49,35 @@ struct StepParams {
     float *acc = nullptr;
     float *comp = nullptr;
     int accumulate = 0;
+    // gated family step: does nothing when *skip != 0 (set on the device by
+    // the pushed second step)
+    const int32_t *skip = nullptr;
 };
+
+// Device state of the pushed second family step of a single seed (kt == 1).
+// The frontier of step 2 is F = out(s) + {s} (s appended when it has no
+// self-loop); offs[f] is the exclusive prefix sum of outdeg over F, so the
+// push touches W = offs[|F|] edges of A~.  acc holds y2's pulled sums as
+// fixed point (2^62 units) and is all zero between queries.
+struct PushPlan {
+    unsigned long long *acc = nullptr;  // [n], zero between queries
+    int64_t *offs = nullptr;            // [max_outdeg + 2]
+    int64_t *ctrl = nullptr;            // {W, |F|}
+    int32_t *flag = nullptr;            // 1: the push ran (the gated pull step skips)
+    int64_t wmax = 0;                   // push only when W <= wmax
+};
+
+// Bytes of the push state (kept at the front of the query workspace).
+size_t push_plan_bytes(int64_t n, int64_t max_outdeg);
+PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax);
 
 tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams &p, hipStream_t st);
 
 // x'(0) for the stranger chain: zout = c*r0*(1/outdeg or 1), acc = c*r0 if
-// T == 0 else 0, comp = 0, where r0 = 1/n or 1/n_block(v).
+// T == 0 else 0, comp = 0, where r0 = 1/n or 1/n_block(v); zout rows follow
+// zperm when set.
 tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, float *zout, float *acc,
-                                float *comp, hipStream_t st);
+                                float *comp, const int32_t *zperm, hipStream_t st);
 
 // z0 = c*Q^T tile (node-major, scaled by 1/outdeg for uniform weights) and,
 // when x0 is set, the unscaled x(0) = c*Q tile; columns >= ncols are zero.
@@ -67,6 +90,18 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 // out-edges of A~: zout = y1 scaled as the gathered vector, zero elsewhere
 // (a fill launch, then one wave per (block, column) seed).
 tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st);
+
+// Single seed (kt == 1, unpacked): the first step as above, plus the plan of
+// the second step (offs, W, |F|, flag = W <= wmax).
+tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
+
+// Second family step of a single seed pushed over the out-edges of F when
+// the plan's flag is set: y2 = c e_s + (1-c) A~^T y1 accumulated in fixed
+// point (order-independent, so bitwise reproducible), then written as the
+// next gathered vector p.zout with zeros elsewhere, and acc cleared.  With
+// the flag clear both launches return at once and the gated pull step
+// (p.skip = pp.flag) computes the step instead.
+tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
 // A seed outside [0, n) (or outside its block on a packed graph) gives a

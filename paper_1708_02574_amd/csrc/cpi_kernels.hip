@@ -65,11 +65,16 @@ __device__ __forceinline__ bool seed_valid(const StepParams &p, int64_t v, int32
 //   stranger a = 1/outdeg(v), b = r~_stranger[v], c = Kahan compensation
 struct EpiPre {
     float a = 0.f, b = 0.f, c = 0.f;
+    int32_t zi = 0;  // row of v in zout
 };
+
+// Row of node v in the work vectors.
+__device__ __forceinline__ int64_t zrow(const StepParams &p, int64_t v) { return p.zperm ? p.zperm[v] : v; }
 
 template <int MODE>
 __device__ __forceinline__ EpiPre epi_load(const StepParams &p, int64_t v) {
     EpiPre q;
+    if (!(MODE == kFamily && p.last)) q.zi = (int32_t)zrow(p, v);
     if (MODE == kFamily) {
         if (p.last) q.a = p.str[v];
         else if (!p.w) q.a = p.inv[v];
@@ -90,6 +95,7 @@ __device__ __forceinline__ EpiPre epi_readlane(const EpiPre &q, int r) {
     o.a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.a), r));
     o.b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.b), r));
     o.c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(q.c), r));
+    o.zi = __builtin_amdgcn_readlane(q.zi, r);
     return o;
 }
 
@@ -117,15 +123,15 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
             }
             p.out[(p.out_col0 + j) * p.n + v] = o;
         } else {
-            p.zout[v * p.kt + j] = p.w ? y : y * q.a;
+            p.zout[(int64_t)q.zi * p.kt + j] = p.w ? y : y * q.a;
         }
     } else if (MODE == kPlain) {
         const float x = p.omc * sum;
         if (p.xs_out) p.xs_out[v * p.kt + j] = x;
-        p.zout[v * p.kt + j] = p.w ? x : x * q.a;
+        p.zout[(int64_t)q.zi * p.kt + j] = p.w ? x : x * q.a;
     } else {
         const float x = p.omc * sum;
-        p.zout[v] = p.w ? x : x * q.a;
+        p.zout[q.zi] = p.w ? x : x * q.a;
         if (p.accumulate) {
             // Kahan-compensated r~_stranger += x
             const float yk = x - q.c;
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
                                                           StepParams p) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_long) return;
+    if (wid >= n_long || (p.skip && *p.skip)) return;
     const LongRow lr = longs[wid];
     const int kt = p.kt;
     if (kt == 1) {
@@ -315,6 +321,24 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
         return;
     }
     item_1<MODE, FIRST, WEIGHTED>(p, it, wid, lane, lds[wv]);
+}
+
+// The same step, gated by a device flag: the pulled second family step of
+// a single seed, which returns at once when the step was pushed instead.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__restrict__ items, int64_t n_items,
+                                                                StepParams p) {
+    __shared__ float lds[kWaves][kGroupMax];
+    if (*p.skip) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items) return;
+    const Item it = items[wid];
+    if (item_kind(it.meta) == kItemBlock) {
+        block_row_1<kFamily, false, WEIGHTED>(p, it, lane, wv, lds);
+        return;
+    }
+    item_1<kFamily, false, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
 // ------------------------------------------------------------ kt == 64
@@ -524,11 +548,11 @@ __global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restric
 
 __global__ void stranger_init_kernel(int64_t n, float c, const float *restart_pr, float inv_n,
                                      const float *inv, const float *w_present, int include_x0,
-                                     float *zout, float *acc, float *comp) {
+                                     float *zout, float *acc, float *comp, const int32_t *zperm) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n;
          v += (int64_t)gridDim.x * blockDim.x) {
         const float x0 = c * (restart_pr ? restart_pr[v] : inv_n);
-        zout[v] = w_present ? x0 : x0 * inv[v];
+        zout[zperm ? zperm[v] : v] = w_present ? x0 : x0 * inv[v];
         acc[v] = include_x0 ? x0 : 0.0f;
         comp[v] = 0.0f;
     }
@@ -541,7 +565,7 @@ __global__ void dense_init_kernel(StepParams p, float *z0, float *x0) {
         const int64_t v = i / p.kt;
         const int j = (int)(i - v * p.kt);
         const float x = j < p.ncols ? p.c * p.qdense[(int64_t)j * p.n + v] : 0.0f;
-        z0[i] = p.w ? x : x * p.inv[v];
+        z0[zrow(p, v) * p.kt + j] = p.w ? x : x * p.inv[v];
         if (x0) x0[i] = x;
     }
 }
@@ -581,10 +605,127 @@ __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const i
         const int32_t v = a_col[e];
         const float wt = a_w ? a_w[e] : p.inv[s];
         const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
-        p.zout[(int64_t)v * p.kt + j] = a_w ? y : y * p.inv[v];
+        p.zout[zrow(p, v) * p.kt + j] = a_w ? y : y * p.inv[v];
         self |= (v == s);
     }
-    if (!__any(self) && lane == 0) p.zout[(int64_t)s * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
+    if (!__any(self) && lane == 0) p.zout[zrow(p, s) * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ long long wave_scan_incl(long long x, int lane) {
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// push_first_kernel for one seed (one wave), which also lays out the second
+// step's frontier F = out(s) + {s}: offs = exclusive prefix sums of outdeg
+// over F, ctrl = {W, |F|}, flag = (W <= wmax).
+__global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col,
+                                       const float *a_w, PushPlan pp) {
+    const int lane = threadIdx.x & 63;
+    const int32_t s = p.seeds[0];
+    if (s < 0 || (int64_t)s >= p.n) {
+        if (lane == 0) {
+            pp.ctrl[0] = 0;
+            pp.ctrl[1] = 0;
+            *pp.flag = 0;
+        }
+        return;
+    }
+    const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
+    const float cw = p.c * p.omc;
+    bool self = false;
+    long long run = 0;
+    if (lane == 0) pp.offs[0] = 0;
+    for (int64_t base = e0; base < e1; base += 64) {
+        const int64_t e = base + lane;
+        const bool on = e < e1;
+        long long d = 0;
+        if (on) {
+            const int32_t v = a_col[e];
+            const float wt = a_w ? a_w[e] : p.inv[s];
+            const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
+            p.zout[zrow(p, v)] = a_w ? y : y * p.inv[v];
+            self |= (v == s);
+            d = a_rowptr[v + 1] - a_rowptr[v];
+        }
+        const long long incl = wave_scan_incl(d, lane);
+        if (on) pp.offs[e - e0 + 1] = run + incl;
+        run += __shfl(incl, 63, 64);
+    }
+    int64_t nf = e1 - e0;
+    if (!__any(self)) {
+        const long long ds = a_rowptr[s + 1] - e0;
+        if (lane == 0) {
+            p.zout[zrow(p, s)] = a_w ? p.c : p.c * p.inv[s];
+            pp.offs[nf + 1] = run + ds;
+        }
+        run += ds;
+        ++nf;
+    }
+    if (lane == 0) {
+        pp.ctrl[0] = run;
+        pp.ctrl[1] = nf;
+        *pp.flag = run <= pp.wmax ? 1 : 0;
+    }
+}
+
+constexpr int kPushLdsOffs = 2048;  // frontier offsets searched in LDS up to this size
+
+// Second family step pushed from F: thread t takes edge slots t, t + T, ...
+// (T threads), finds its frontier node by binary search over offs and adds
+// its term to acc[v] in 2^62 fixed point.  Every term is in [0, 1] and the
+// terms add up to (1-c)-weighted mass below 1, so the sum cannot overflow.
+__global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const int64_t *a_rowptr,
+                                                          const int32_t *a_col, const float *a_w, PushPlan pp) {
+    __shared__ long long soffs[kPushLdsOffs + 1];
+    if (!*pp.flag) return;
+    const int64_t W = pp.ctrl[0];
+    const int64_t nf = pp.ctrl[1];
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    if (first >= W) return;
+    const bool in_lds = nf <= kPushLdsOffs;
+    if (in_lds)
+        for (int64_t i = threadIdx.x; i <= nf; i += blockDim.x) soffs[i] = pp.offs[i];
+    __syncthreads();
+    const int32_t s = p.seeds[0];
+    const int64_t es = a_rowptr[s];
+    const int64_t outdeg_s = a_rowptr[s + 1] - es;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = first + threadIdx.x; t < W; t += stride) {
+        int64_t lo = 0, hi = nf;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            const long long om = in_lds ? soffs[mid] : pp.offs[mid];
+            if (om <= t) lo = mid;
+            else hi = mid;
+        }
+        const long long olo = in_lds ? soffs[lo] : pp.offs[lo];
+        const int32_t u = lo < outdeg_s ? a_col[es + lo] : s;
+        const int64_t e = a_rowptr[u] + (t - olo);
+        const int32_t v = a_col[e];
+        const float zu = p.zin[zrow(p, u)];
+        const float term = a_w ? zu * a_w[e] : zu;
+        atomicAdd(&pp.acc[v], __double2ull_rn((double)term * 0x1p62));
+    }
+}
+
+// y2 = c [v == s] + (1-c) acc[v] 2^-62 as the next gathered vector; clears acc.
+__global__ void push_convert_kernel(StepParams p, PushPlan pp) {
+    if (!*pp.flag) return;
+    const int32_t s = p.seeds[0];
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long a = pp.acc[v];
+        const float sum = (float)((double)a * 0x1p-62);
+        const float y = fmaf(p.omc, sum, v == (int64_t)s ? p.c : 0.0f);
+        p.zout[zrow(p, v)] = p.w ? y : y * p.inv[v];
+        if (a) pp.acc[v] = 0ull;
+    }
 }
 
 __global__ void combine_only_kernel(StepParams p) {
@@ -655,6 +796,14 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (s.n_items > 0) {
         int lg = 0;
         while ((1 << lg) < p.kt) ++lg;
+        if (p.skip) {
+            if (p.kt != 1 || mode != kFamily || first)
+                return fail(TPA_ERR_INVALID_ARG, "a gated step is a single-column non-first family step");
+            const int slot = profile_begin(120 + (p.w ? 1 : 0), st);
+            if (p.w) gated_step_kernel_1<true><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p);
+            else gated_step_kernel_1<false><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p);
+            profile_end(slot, st);
+        } else {
         const int slot = profile_begin(16 * lg + 4 * mode + 2 * (first ? 1 : 0) + (p.w ? 1 : 0), st);
         if (mode == kFamily) {
             if (first) launch_w<kFamily, true>(s, p, st);
@@ -666,6 +815,7 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
             launch_w<kStranger, false>(s, p, st);
         }
         profile_end(slot, st);
+        }
     }
     if (s.n_long > 0) {
         const int slot = profile_begin(127, st);
@@ -682,9 +832,9 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
 }
 
 tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, float *zout, float *acc,
-                                float *comp, hipStream_t st) {
+                                float *comp, const int32_t *zperm, hipStream_t st) {
     stranger_init_kernel<<<grid_1d(g->n), 256, 0, st>>>(g->n, c, g->restart_pr, (float)(1.0 / (double)g->n),
-                                                         g->inv_deg, g->t.w, include_x0, zout, acc, comp);
+                                                         g->inv_deg, g->t.w, include_x0, zout, acc, comp, zperm);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
@@ -706,6 +856,47 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
     fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
     push_first_kernel<<<(unsigned)((nslots * 64 + 255) / 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col,
                                                                             g->weighted ? g->a.w : nullptr, nslots);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
+    const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
+    const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
+    return a + o + 256;
+}
+
+PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
+    char *b = static_cast<char *>(base);
+    const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
+    const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
+    PushPlan pp;
+    pp.acc = reinterpret_cast<unsigned long long *>(b);
+    pp.offs = reinterpret_cast<int64_t *>(b + a);
+    pp.ctrl = reinterpret_cast<int64_t *>(b + a + o);
+    pp.flag = reinterpret_cast<int32_t *>(b + a + o + 64);
+    pp.wmax = wmax;
+    return pp;
+}
+
+tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
+    if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
+    fill_zero_kernel<<<grid_1d(p.n), 256, 0, st>>>(p.zout, p.n);
+    push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
+    if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
+    // grid-stride over the W edge slots: about 4 slots per thread up to the
+    // bound, more beyond 2^24 slots
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (pp.wmax + 4 * 256 - 1) / (4 * 256)), 1 << 14);
+    const int slot = profile_begin(124, st);
+    push_second_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr,
+                                                         pp);
+    push_convert_kernel<<<grid_1d(p.n), 256, 0, st>>>(p, pp);
+    profile_end(slot, st);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

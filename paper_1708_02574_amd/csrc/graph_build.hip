@@ -401,6 +401,106 @@ tpa_status ensure_t2a(tpa_graph *g, hipStream_t st) {
     return TPA_OK;
 }
 
+namespace {
+
+__global__ void hub_keys_kernel(const int64_t *rowptr, int64_t n, int64_t maxd, uint32_t *keys, int32_t *ids) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        keys[v] = (uint32_t)(maxd - (rowptr[v + 1] - rowptr[v]));
+        ids[v] = (int32_t)v;
+    }
+}
+
+__global__ void invert_perm_kernel(const int32_t *order, int64_t n, int32_t *rank) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        rank[order[i]] = (int32_t)i;
+}
+
+__global__ void map_cols_kernel(const int32_t *col, int64_t m, const int32_t *rank, int32_t *out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = rank[col[e]];
+}
+
+__global__ void row_col_keys_kernel(const int64_t *rowptr, int64_t n, const int32_t *colz, uint64_t *keys) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = w0; v < n; v += nw)
+        for (int64_t e = rowptr[v] + lane; e < rowptr[v + 1]; e += 64)
+            keys[e] = ((uint64_t)v << 32) | (uint32_t)colz[e];
+}
+
+__global__ void low32_kernel(const uint64_t *keys, int64_t m, int32_t *out) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = (int32_t)(uint32_t)keys[e];
+}
+
+}  // namespace
+
+// Rank of every node by descending out-degree (a stable radix sort keeps
+// ties in id order), and A~^T's column ids mapped through it with each row
+// re-sorted by rank.
+tpa_status ensure_zlayout(tpa_graph *g, hipStream_t st) {
+    if (g->zperm) return TPA_OK;
+    const int64_t n = g->n, m = g->m;
+    int end_bit = 1;
+    while (end_bit < 32 && ((int64_t)1 << end_bit) <= g->max_outdeg) ++end_bit;
+    uint32_t *k0 = nullptr, *k1 = nullptr;
+    int32_t *v0 = nullptr, *v1 = nullptr, *rank = nullptr, *colz = nullptr;
+    void *tmp = nullptr;
+    auto cleanup = [&]() { dfree(k0); dfree(k1); dfree(v0); dfree(v1); dfree(tmp); };
+    tpa_status rc = TPA_OK;
+    if ((rc = dalloc(&k0, n, st)) != TPA_OK || (rc = dalloc(&k1, n, st)) != TPA_OK ||
+        (rc = dalloc(&v0, n, st)) != TPA_OK || (rc = dalloc(&v1, n, st)) != TPA_OK) {
+        cleanup();
+        return rc;
+    }
+    hub_keys_kernel<<<grid_for(n), kBlock, 0, st>>>(g->a.rowptr, n, g->max_outdeg, k0, v0);
+    rocprim::double_buffer<uint32_t> kb(k0, k1);
+    rocprim::double_buffer<int32_t> vb(v0, v1);
+    size_t bytes = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+    if (e == hipSuccess) rc = dmalloc(&tmp, std::max<size_t>(bytes, 16), st);
+    if (e == hipSuccess && rc == TPA_OK)
+        e = rocprim::radix_sort_pairs(tmp, bytes, kb, vb, (size_t)n, 0u, (unsigned)end_bit, st);
+    if (e != hipSuccess) rc = fail(TPA_ERR_HIP, std::string("radix_sort_pairs: ") + hipGetErrorString(e));
+    if (rc == TPA_OK) rc = dalloc(&rank, n, st);
+    if (rc == TPA_OK) rc = dalloc(&colz, m, st);
+    if (rc != TPA_OK) {
+        dfree(rank);
+        cleanup();
+        return rc;
+    }
+    invert_perm_kernel<<<grid_for(n), kBlock, 0, st>>>(vb.current(), n, rank);
+    map_cols_kernel<<<grid_for(m), kBlock, 0, st>>>(g->t.col, m, rank, colz);
+    e = hipStreamSynchronize(st);
+    cleanup();
+    // each row's edges in ascending hub rank: the first edges of every row
+    // then read the same few cache lines of the gathered vector
+    if (e == hipSuccess) {
+        uint64_t *keys = nullptr, *sorted = nullptr;
+        rc = dalloc(&keys, m, st);
+        if (rc == TPA_OK) {
+            row_col_keys_kernel<<<grid_for(n * 64), kBlock, 0, st>>>(g->t.rowptr, n, colz, keys);
+            rc = sort_keys(keys, m, 32 + g->bits, st, &sorted);
+        }
+        if (rc == TPA_OK) {
+            low32_kernel<<<grid_for(m), kBlock, 0, st>>>(sorted, m, colz);
+            e = hipStreamSynchronize(st);
+        }
+        if (sorted) dfree(sorted);
+        else dfree(keys);
+        if (rc != TPA_OK) { dfree(rank); dfree(colz); return rc; }
+    }
+    if (e != hipSuccess) {
+        dfree(rank);
+        dfree(colz);
+        return fail(TPA_ERR_HIP, std::string("gather layout: ") + hipGetErrorString(e));
+    }
+    g->zperm = rank;
+    g->t_colz = colz;
+    return TPA_OK;
+}
+
 // ------------------------------------------------------------------ schedule
 void Schedule::release() {
     dfree(items);
@@ -502,6 +602,9 @@ void graph_release(tpa_graph *g) {
     dfree(g->a.rowptr); dfree(g->a.col); dfree(g->a.w);
     dfree(g->t.rowptr); dfree(g->t.col); dfree(g->t.w);
     dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
+    dfree(g->zperm); dfree(g->t_colz);
+    g->zperm = nullptr;
+    g->t_colz = nullptr;
     dfree(g->str); dfree(g->ws); dfree(g->dev_err);
     for (auto &kv : g->sched_t) kv.second.release();
     for (auto &kv : g->sched_a) kv.second.release();

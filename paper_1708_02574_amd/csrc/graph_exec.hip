@@ -68,6 +68,9 @@ extern "C" tpa_status tpa_query_graph_create(tpa_graph_t g, const int32_t *seeds
     tpa_status rc = dmalloc(reinterpret_cast<void **>(&qg->ws), bytes, st);
     if (rc != TPA_OK) { delete qg; return rc; }
     qg->ws_bytes = bytes;
+    rc = clear_push_state(g, qg->ws, st);
+    if (rc == TPA_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(TPA_ERR_HIP, "hipStreamSynchronize failed");
+    if (rc != TPA_OK) { dfree(qg->ws); delete qg; return rc; }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
         dfree(qg->ws); delete qg;

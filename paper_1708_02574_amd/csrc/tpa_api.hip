@@ -82,13 +82,30 @@ int choose_kt(const tpa_graph *g, int64_t k) {
     return kt;
 }
 
+// The push accumulator must be zero before the first query on a workspace.
+tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st) {
+    TPA_TRY_HIP(hipMemsetAsync(ws, 0, push_plan_bytes(g->n, g->max_outdeg), st));
+    return TPA_OK;
+}
+
+// Largest frontier edge count for which the second family step is pushed
+// rather than pulled: an eighth of the edges (a pushed edge costs a binary
+// search, a gather and an atomic; a pulled edge one coalesced index and one
+// gather).
+int64_t push_wmax(const tpa_graph *g) {
+    if (g->push_limit >= 0) return g->push_limit;
+    return std::max<int64_t>(1024, g->m / 8);
+}
+
 namespace {
 
-// Workspace layout (floats): z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt]
+// Workspace layout: push state (push_plan_bytes, the same for every tile
+// width, so its all-zero accumulator survives queries of any width) |
+// z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt] (floats)
 size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt) {
     const size_t zf = (size_t)g->n * kt;
     const size_t pf = (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;
-    return sizeof(float) * (2 * zf + pf) + 256;
+    return push_plan_bytes(g->n, g->max_outdeg) + sizeof(float) * (2 * zf + pf) + 256;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -104,6 +121,8 @@ tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
     }
     TPA_TRY(dmalloc(reinterpret_cast<void **>(&g->ws), bytes, st));
     g->ws_bytes = bytes;
+    TPA_TRY(clear_push_state(g, g->ws, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));  // ordered before queries on any stream
     return TPA_OK;
 }
 
@@ -145,18 +164,27 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
         TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt), st));
         ws = g->ws;
     }
-    float *z0 = ws;
+    const PushPlan pp = push_plan_at(ws, g->n, g->max_outdeg, push_wmax(g));
+    float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->max_outdeg));
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
+    // a single seed whose step 2 is not the last: push steps 1 and 2 from
+    // the seed's neighbourhood when it is small, pull otherwise (decided on
+    // the device, so the launch sequence is fixed and capturable)
+    const bool push2 = kt == 1 && !packed && !q && S >= 4 && pp.wmax > 0;
 
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     StepParams p;
     p.rowptr = g->t.rowptr;
-    p.col = g->t.col;
     p.w = g->weighted ? g->t.w : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
     p.err = g->dev_err;
+    // gathered vectors in hub-first rows (first steps read node ids: t.col)
+    const bool hub = g->gather_layout && g->zperm && !g->weighted;
+    p.zperm = hub ? g->zperm : nullptr;
+    const int32_t *col_gather = hub ? g->t_colz : g->t.col;
+    p.col = col_gather;
     p.omc = (float)(1.0 - c);
     p.c = (float)c;
     p.kt = kt;
@@ -183,11 +211,22 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             p.last = step == S - 1;
             if (step == 1 && !q && !p.last) {
                 // one-hot restarts: x(1) lives on the seeds' out-edges; push it
-                TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, st));
+                if (push2) TPA_TRY(launch_push_first_plan(p, g, pp, st));
+                else TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, st));
+                continue;
+            }
+            if (step == 2 && push2) {
+                TPA_TRY(launch_push_second(p, g, pp, st));
+                p.skip = pp.flag;
+                const tpa_status rc = launch_step(*s, kFamily, false, p, st);
+                p.skip = nullptr;
+                TPA_TRY(rc);
                 continue;
             }
             // one-hot restart: the first step needs no gather
-            TPA_TRY(launch_step(*s, kFamily, step == 1 && !q, p, st));
+            const bool first = step == 1 && !q;
+            p.col = first ? g->t.col : col_gather;
+            TPA_TRY(launch_step(*s, kFamily, first, p, st));
         }
     }
     return TPA_OK;
@@ -222,15 +261,18 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     const int64_t K = stranger_last_iteration(c, eps);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
+    if (g->gather_layout && !g->weighted) TPA_TRY(ensure_zlayout(g, st));
+    const bool hub = g->gather_layout && g->zperm && !g->weighted;
     if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
     float *tmp = nullptr;
     const size_t n = (size_t)g->n;
     TPA_TRY(dalloc(&tmp, 3 * n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));
     float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
-    tpa_status rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, st);
+    tpa_status rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, hub ? g->zperm : nullptr, st);
     StepParams p;
     p.rowptr = g->t.rowptr;
-    p.col = g->t.col;
+    p.col = hub ? g->t_colz : g->t.col;
+    p.zperm = hub ? g->zperm : nullptr;
     p.w = g->weighted ? g->t.w : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
@@ -310,6 +352,33 @@ extern "C" tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_p
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     if (seed_tile) *seed_tile = g->seed_tile;
     if (edges_per_item) *edges_per_item = g->edges_per_item;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (hub_first != 0 && hub_first != 1) return fail(TPA_ERR_INVALID_ARG, "hub_first must be 0 or 1");
+    if (hub_first && g->preprocessed && !g->weighted) TPA_TRY(ensure_zlayout(g, nullptr));
+    g->gather_layout = hub_first;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first) {
+    if (!g || !hub_first) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    *hub_first = g->gather_layout;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (max_edges < -1) return fail(TPA_ERR_INVALID_ARG, "max_edges must be >= -1");
+    g->push_limit = max_edges;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges) {
+    if (!g || !max_edges) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    *max_edges = g->push_limit;
     return TPA_OK;
 }
 

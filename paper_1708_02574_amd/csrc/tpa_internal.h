@@ -116,6 +116,13 @@ struct tpa_graph {
     tpa::Csr a;                             // A~   (rows = sources)
     tpa::Csr t;                             // A~^T (rows = destinations)
     int64_t *t2a = nullptr;                 // A~^T entry -> A~ entry (lazy)
+    // gather layout of the CPI work vectors (uniform weights only): node v's
+    // entries sit at row zperm[v] (rank of v by descending out-degree, ties
+    // by id); t_colz holds zperm[t.col] with each row of A~^T re-sorted in
+    // ascending rank (built at preprocessing)
+    int32_t *zperm = nullptr;               // n
+    int32_t *t_colz = nullptr;              // m
+    int gather_layout = 1;                  // 1 = hub-first order, 0 = node order
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
     bool weighted = false;                  // weights from logits (a.w, t.w set)
@@ -139,6 +146,7 @@ struct tpa_graph {
     // tuning
     int seed_tile = 0;                      // 0 = automatic
     int edges_per_item = 0;                 // 0 = automatic
+    int64_t push_limit = -1;                // -1 = automatic, 0 = never push
 };
 
 namespace tpa {
@@ -150,11 +158,15 @@ SchedShape choose_shape(const tpa_graph *g, int kt);
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
                      int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes);
 size_t query_workspace_bytes(tpa_graph *g, int64_t k, hipStream_t st);
+// Zero the push state at the front of a fresh query workspace.
+tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st);
 tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);
 // Work schedule over the rows of A~^T (over_a = false) or of A~ (true).
 tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out,
                         bool over_a = false);
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
+// Build zperm and t_colz (synchronises `stream`); no-op when present.
+tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

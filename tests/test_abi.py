@@ -43,6 +43,10 @@ def test_header_status_codes_match_binding():
     lambda L: L.tpa_stranger(None, None, None),
     lambda L: L.tpa_set_tuning(None, 0, 0),
     lambda L: L.tpa_get_tuning(None, None, None),
+    lambda L: L.tpa_set_push_limit(None, -1),
+    lambda L: L.tpa_get_push_limit(None, None),
+    lambda L: L.tpa_set_gather_layout(None, 1),
+    lambda L: L.tpa_get_gather_layout(None, None),
     lambda L: L.tpa_graph_blocks(None, None),
     lambda L: L.tpa_graph_export(None, 0, None, None, None, None),
     lambda L: L.tpa_graph_padded(None, None, None),

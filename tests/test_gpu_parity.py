@@ -225,6 +225,132 @@ def test_cycle_closed_form_on_gpu(tpa, torch):
     assert l1_rows(r, expect) <= TOL
 
 
+# ---------------------------------------------------------------- pushed step 2
+def frontier_edges(ex, s):
+    """Edges of A~ leaving F = out(s) + {s}: the work of a pushed step 2."""
+    rp, col = ex["a_rowptr"], ex["a_col"]
+    nb = col[rp[s]:rp[s + 1]]
+    f = nb if s in nb else np.append(nb, s)
+    return int(np.diff(rp)[f].sum())
+
+
+def run_single(gg, torch, sd, Sq, order):
+    out = [None] * len(order)
+    for i in order:
+        out[i] = gg.query(sd[i:i + 1], c, Sq, T)[0]
+    return torch.stack(out)
+
+
+@pytest.mark.parametrize("Sq", [4, 5, 8])
+def test_second_step_push_and_pull(rmat13, torch, Sq):
+    """Single-seed queries with step 2 always pushed (limit m), always pulled
+    (limit 0) and chosen per seed (limit = the median frontier): all within
+    L1 of the oracle, push and pull within FP32 rounding of each other,
+    bitwise reproducible in any query order, and the per-seed choice equal
+    bit for bit to the forced direction it picked."""
+    og, gg = rmat13
+    ex = og.export()
+    seeds = [int(s) for s in seeds_for(og, 10, 303)]
+    seeds += [int(np.argmax(np.diff(ex["a_rowptr"]))), int(np.flatnonzero(ex["padded"])[0])]
+    W = np.array([frontier_edges(ex, s) for s in seeds])
+    mid = int(np.median(W))
+    assert (W <= mid).any() and (W > mid).any()
+    expect = np.stack([og.query(s, c, Sq, T) for s in seeds])
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    runs = {}
+    try:
+        for limit in (0, og.m, mid, -1):
+            gg.set_push_limit(limit)
+            assert gg.get_push_limit() == limit
+            R = run_single(gg, torch, sd, Sq, list(range(len(seeds))))
+            R2 = run_single(gg, torch, sd, Sq, list(reversed(range(len(seeds)))))
+            assert torch.equal(R, R2), limit
+            runs[limit] = R.cpu().numpy()
+            assert np.all(l1_rows(runs[limit], expect) <= TOL), limit
+    finally:
+        gg.set_push_limit(-1)
+    pushed, pulled, mixed = runs[og.m], runs[0], runs[mid]
+    assert np.abs(pushed - pulled).max() <= 1e-6
+    for i, w in enumerate(W):
+        assert np.array_equal(mixed[i], (pushed if w <= mid else pulled)[i]), i
+
+
+def test_second_step_push_weighted(tpa, torch):
+    """Row-softmax edge weights: the pushed step multiplies each gathered
+    value by its A~ edge weight."""
+    og = oracle.Graph.rmat(10, 12000, 22)
+    gg = tpa.Graph.rmat(10, 12000, 22)
+    theta = ti.draw_logits(og.m, 7)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    seeds = [int(s) for s in seeds_for(og, 8, 2)] + [int(np.argmax(np.diff(og.export()["a_rowptr"])))]
+    expect = np.stack([og.query(s, c, S, T) for s in seeds])
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    res = []
+    for limit in (og.m, 0):
+        gg.set_push_limit(limit)
+        res.append(run_single(gg, torch, sd, S, list(range(len(seeds)))).cpu().numpy())
+        assert np.all(l1_rows(res[-1], expect) <= TOL), limit
+    gg.set_push_limit(-1)
+    assert np.abs(res[0] - res[1]).max() <= 1e-6
+
+
+# ---------------------------------------------------------------- gather layout
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
+    """Hub-first and node-order work vectors: stranger vector, single-seed
+    queries (pushed and pulled step 2, S = 2 with a pulled first step), seed
+    tiles 4 and 64 and dense restart vectors all match the oracle, and agree
+    with each other to FP32 rounding (bit for bit with logit weights, which
+    always use node order)."""
+    og = oracle.Graph.rmat(12, 60000, 31)
+    gg = tpa.Graph.rmat(12, 60000, 31)
+    if weighted:
+        theta = ti.draw_logits(gg.m, 8)
+        og.set_logits(theta.astype(np.float64))
+        gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    sd = ti.draw_seeds(og.export()["padded"] == 0, 70, 5)
+    seeds = torch.from_numpy(sd).cuda()
+    Q = np.random.default_rng(6).random((3, gg.n))
+    Q /= Q.sum(axis=1, keepdims=True)
+    Qt = torch.from_numpy(Q.astype(np.float32)).cuda()
+    single = np.stack([og.query(int(s), c, S, T) for s in sd])
+    expect = [og.str]
+    for kt in (1, 4, 64):
+        expect += [single[:9] if kt == 1 else single, np.stack([og.query_q(q, c, S, T) for q in Q])]
+    expect += [single[:3], np.stack([og.query(int(s), c, 2, T) for s in sd[:3]])]
+    res = []
+    try:
+        for hub in (True, False):
+            gg.set_gather_layout(hub)
+            assert gg.get_gather_layout() == hub
+            gg.preprocess(c, T)
+            out = [gg.stranger()]
+            for kt in (1, 4, 64):
+                gg.set_tuning(seed_tile=kt)
+                out.append(gg.query(seeds[:9] if kt == 1 else seeds, c, S, T))
+                out.append(gg.query_dense(Qt, c, S, T))
+            gg.set_tuning(seed_tile=1)
+            gg.set_push_limit(0)
+            out.append(gg.query(seeds[:3], c, S, T))
+            gg.set_push_limit(-1)
+            out.append(gg.query(seeds[:3], c, 2, T))
+            res.append(out)
+    finally:
+        gg.set_tuning(0, 0)
+        gg.set_gather_layout(True)
+    for i, (a, b, e) in enumerate(zip(res[0], res[1], expect)):
+        assert np.all(l1_rows(a.cpu().numpy(), e) <= TOL), i
+        assert np.all(l1_rows(b.cpu().numpy(), e) <= TOL), i
+        if weighted:
+            assert torch.equal(a, b), i
+        else:
+            assert float((a - b).abs().max()) <= 1e-6, i
+
+
 # ---------------------------------------------------------------- packed
 def test_packed_blocks_equal_separate_graphs(tpa, torch):
     params = [(9, 4000, 1, 400), (10, 9000, 2, 0), (8, 1500, 3, 200)]
