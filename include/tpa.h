@@ -262,6 +262,43 @@ tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);
 tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Exact RWR and the accuracy harness (Section 2.3 Algorithm 1, Theorem 1;
+ * Section 4's error and top-k recall measurements).
+ *
+ * tpa_cpi: Algorithm 1 for one restart vector, r = sum of x(i) over
+ * s_iter <= i <= t_iter with x(0) = c q, x(i) = (1-c) A~^T x(i-1), x(0)
+ * included when s_iter = 0, stopping after the first i whose ||x(i)||_1 is
+ * below eps.  The restart is either a seed (seed >= 0, q NULL: q = e_seed)
+ * or a dense vector q (float[n], seed = -1).  t_iter = -1 means no last
+ * iteration (only the eps test).  The norm test uses Lemma 2's closed form
+ * c (1-c)^i ||q||_1 (exact for q >= 0; an upper bound otherwise, so the
+ * loop never stops early), with ||q||_1 = 1 for a seed and reduced on the
+ * device for dense q.  s_iter = 0, t_iter = -1 gives exact RWR up to the
+ * truncation (Theorem 1); [0, S-1], [S, T-1] and [T, -1] give the exact
+ * family, neighbor and stranger parts.  out: float[n], the summed window
+ * (Kahan-compensated FP32).  Needs no preprocessing.  Synchronous (it
+ * allocates and frees its work vectors).  Errors: INVALID_ARG (not exactly
+ * one of seed >= 0 and q, seed >= n, c outside (0,1), s_iter < 0,
+ * t_iter < -1, t_iter < s_iter, eps < 0, eps = 0 with t_iter = -1), OOM,
+ * HIP. */
+tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, double c, int s_iter, int t_iter, double eps,
+                   float *out, hipStream_t stream);
+
+/* The k largest entries of each row of vals (row-major [rows][n]), ordered
+ * by value descending and, among equal values, index ascending; NaN ranks
+ * below every number.  idx_out int32[rows][k], val_out float[rows][k].
+ * 1 <= k <= min(n, 1024).  Errors: INVALID_ARG (sizes, NULL), INDEX_OVERFLOW
+ * (n or rows above 2^31 - 1), HIP. */
+tpa_status tpa_topk(const float *vals, int64_t rows, int64_t n, int k, int32_t *idx_out, float *val_out,
+                    hipStream_t stream);
+
+/* Per-row L1 distance out[r] = sum_v |a x[r][v] - y[r][v]| (row-major
+ * [rows][n] FP32 inputs, double[rows] output), summed in FP64 in a fixed
+ * order.  Errors: INVALID_ARG (negative sizes, NULL), INDEX_OVERFLOW, HIP. */
+tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, int64_t n, double a, double *out,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (a tracing aid, process-wide).  While enabled, HIP events
  * bracket one in every `sample_period` launches of each CPI step-kernel
  * variant, on the launch's stream; variants are numbered

@@ -25,6 +25,11 @@ what pins it (tests/test_oracle_*.py):
                       Pinned by dense brute force, closed-form graphs, the
                       Table 3 bound values, and Lemma 1 / Lemma 3 / Theorem 2
                       against exact CPI.
+* ``topk``            the k largest entries per row, ties by smaller index
+                      (the ranking whose recall Section 4 reports).  Pinned
+                      by the properties that define it uniquely: order,
+                      domination of every unselected entry, smallest indices
+                      among ties at the cut.
 * ``backward``        reverse-mode derivative of the online + preprocessing
                       chains w.r.t. edge logits and the restart vector (an
                       extension, not in the paper).  Pinned by central finite
@@ -113,6 +118,24 @@ def rmat(scale: int, samples: int, seed: int, n_nodes: int | None = None,
     got = lib.orc_rmat(scale, n_nodes, samples, seed & 0xFFFFFFFFFFFFFFFF,
                        abcd[0], abcd[1], abcd[2], max_raw, _p(src), _p(dst), _p(raw))
     return src[:got].copy(), dst[:got].copy(), int(raw[0])
+
+
+def topk(vals, k: int):
+    """Indices and values of the k largest entries of each row of vals
+    ([rows, n] or [n]), ordered by value descending then index ascending;
+    NaN ranks below every number, -0 equals +0.  Values are compared in the
+    dtype given (float32 results stay float32)."""
+    v = np.atleast_2d(np.asarray(vals))
+    rows, n = v.shape
+    idx = np.arange(n)
+    out_i = np.empty((rows, k), np.int64)
+    for r in range(rows):
+        row = v[r]
+        nan = np.isnan(row)
+        key = np.where(nan, 0, -row.astype(np.float64))  # -x: ascending sort = descending value
+        order = np.lexsort((idx, key, nan))
+        out_i[r] = order[:k]
+    return out_i, np.take_along_axis(v, out_i, axis=1)
 
 
 def neighbor_scale(c: float, S: int, T: int) -> float:

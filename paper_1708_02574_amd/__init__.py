@@ -63,6 +63,9 @@ _SIGS = {
     "tpa_get_gather_layout": (_i, [_vp, _vp]),
     "tpa_get_push_limit": (_i, [_vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
+    "tpa_cpi": (_i, [_vp, C.c_int32, _vp, _d, _i, _i, _d, _vp, _vp]),
+    "tpa_topk": (_i, [_vp, _i64, _i64, _i, _vp, _vp, _vp]),
+    "tpa_row_l1": (_i, [_vp, _vp, _i64, _i64, _d, _vp, _vp]),
     "tpa_profile_enable": (_i, [_i, _i, _i]),
     "tpa_profile_read": (_i, [_i, _vp, _vp]),
     "tpa_profile_reset": (_i, []),
@@ -286,6 +289,25 @@ class Graph:
         _call("tpa_query_packed", self._h, _ptr(sd), P, c, S, T, _ptr(out), _stream(stream))
         return out
 
+    def cpi(self, c: float, s_iter: int, t_iter: int = -1, eps: float = 1e-9, seed: int | None = None,
+            q=None, out=None, stream=None):
+        """Algorithm 1 for one restart (a seed, or a dense q [n]): the sum of
+        x(i) over s_iter <= i <= t_iter (t_iter = -1: until ||x(i)||_1 < eps).
+        cpi(c, 0) is exact RWR up to the truncation.  Returns float32 [n]."""
+        torch = _torch()
+        if (seed is None) == (q is None):
+            raise ValueError("pass exactly one of seed and q")
+        qd = None
+        if q is not None:
+            qd = q.to(device="cuda", dtype=torch.float32).contiguous()
+            if qd.shape != (self.n,):
+                raise ValueError("q must be [n]")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        _call("tpa_cpi", self._h, -1 if seed is None else int(seed), None if qd is None else _ptr(qd), c, s_iter,
+              t_iter, eps, _ptr(out), _stream(stream))
+        return out
+
     def query_dense(self, q, c: float, S: int, T: int, out=None, stream=None):
         """r_TPA for dense restart vectors q [k, n] (float32): returns [k, n]."""
         torch = _torch()
@@ -393,6 +415,35 @@ class Graph:
     def device_error(self, stream=None):
         """Raise TPAError if a query since the last check saw a bad seed."""
         _call("tpa_get_device_error", self._h, _stream(stream))
+
+
+def topk(vals, k: int, stream=None):
+    """The k largest entries of each row of vals [rows, n] (value
+    descending, ties by smaller index, NaN last): (int32 idx, float32 val),
+    both [rows, k]."""
+    torch = _torch()
+    v = vals.to(device="cuda", dtype=torch.float32).contiguous()
+    if v.dim() == 1:
+        v = v.unsqueeze(0)
+    rows, n = v.shape
+    idx = torch.empty((rows, k), dtype=torch.int32, device="cuda")
+    val = torch.empty((rows, k), dtype=torch.float32, device="cuda")
+    _call("tpa_topk", _ptr(v), rows, n, k, _ptr(idx), _ptr(val), _stream(stream))
+    return idx, val
+
+
+def row_l1(x, y, a: float = 1.0, stream=None):
+    """Per-row sum |a x - y| in FP64 (x, y: [rows, n] or [n])."""
+    torch = _torch()
+    xd = x.to(device="cuda", dtype=torch.float32).contiguous()
+    yd = y.to(device="cuda", dtype=torch.float32).contiguous()
+    if xd.shape != yd.shape:
+        raise ValueError("x and y differ in shape")
+    if xd.dim() == 1:
+        xd, yd = xd.unsqueeze(0), yd.unsqueeze(0)
+    out = torch.empty(xd.shape[0], dtype=torch.float64, device="cuda")
+    _call("tpa_row_l1", _ptr(xd), _ptr(yd), xd.shape[0], xd.shape[1], a, _ptr(out), _stream(stream))
+    return out
 
 
 class QueryGraph:

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtpa.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["graph_build.hip", "cpi_kernels.hip", "tpa_api.hip", "profile.hip", "adjoint.hip", "graph_exec.hip"]
+SOURCES = ["graph_build.hip", "cpi_kernels.hip", "tpa_api.hip", "profile.hip", "adjoint.hip", "graph_exec.hip",
+           "accuracy.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [

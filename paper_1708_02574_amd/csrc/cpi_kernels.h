@@ -49,21 +49,20 @@ struct StepParams {
     float *acc = nullptr;
     float *comp = nullptr;
     int accumulate = 0;
-    // gated family step: does nothing when *skip != 0 (set on the device by
-    // the pushed second step)
-    const int32_t *skip = nullptr;
 };
 
-// Device state of the pushed second family step of a single seed (kt == 1).
-// The frontier of step 2 is F = out(s) + {s} (s appended when it has no
-// self-loop); offs[f] is the exclusive prefix sum of outdeg over F, so the
-// push touches W = offs[|F|] edges of A~.  acc holds y2's pulled sums as
-// fixed point (2^62 units) and is all zero between queries.
+// Device state of the pushed first two family steps of a single seed
+// (kt == 1).  The frontier of step 2 is F = out(s) + {s} (s appended when
+// it has no self-loop); y1f holds y1 on F as gathered values, offs[f] the
+// exclusive prefix sum of outdeg over F, so the push touches W = offs[|F|]
+// edges of A~.  acc holds y2's pulled sums as fixed point (2^62 units) and
+// is all zero between queries.
 struct PushPlan {
     unsigned long long *acc = nullptr;  // [n], zero between queries
     int64_t *offs = nullptr;            // [max_outdeg + 2]
+    float *y1f = nullptr;               // [max_outdeg + 1]
     int64_t *ctrl = nullptr;            // {W, |F|}
-    int32_t *flag = nullptr;            // 1: the push ran (the gated pull step skips)
+    int32_t *flag = nullptr;            // 1: step 2 is pushed (the gated step converts acc)
     int64_t wmax = 0;                   // push only when W <= wmax
 };
 
@@ -91,17 +90,22 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 // (a fill launch, then one wave per (block, column) seed).
 tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st);
 
-// Single seed (kt == 1, unpacked): the first step as above, plus the plan of
-// the second step (offs, W, |F|, flag = W <= wmax).
+// Single seed (kt == 1, unpacked): the first step kept compact on F (y1f)
+// with the plan of the second step (offs, W, |F|, flag = W <= wmax); when
+// the flag is clear, a second launch also writes y1 densely to p.zout for
+// the pulled second step.
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // Second family step of a single seed pushed over the out-edges of F when
-// the plan's flag is set: y2 = c e_s + (1-c) A~^T y1 accumulated in fixed
-// point (order-independent, so bitwise reproducible), then written as the
-// next gathered vector p.zout with zeros elsewhere, and acc cleared.  With
-// the flag clear both launches return at once and the gated pull step
-// (p.skip = pp.flag) computes the step instead.
+// the plan's flag is set: the pulled sums of y2 = c e_s + (1-c) A~^T y1
+// accumulated in fixed point (order-independent, so bitwise reproducible)
+// into acc.  With the flag clear it returns at once.
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
+
+// The second family step proper (p.zin = dense y1, p.zout = y2 as the next
+// gathered vector): with the flag set every row is converted from acc (and
+// acc cleared); with it clear the step is pulled over A~^T as usual.
+tpa_status launch_gated_step(const Schedule &s, const StepParams &p, const PushPlan &pp, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).
 // A seed outside [0, n) (or outside its block on a packed graph) gives a

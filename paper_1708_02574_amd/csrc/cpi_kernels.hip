@@ -166,12 +166,7 @@ __device__ __forceinline__ float edge_value(const StepParams &p, int64_t e, int3
 // and apply the epilogue (a separate launch after the step kernel, so no
 // cross-workgroup synchronisation is needed inside the step).
 template <int MODE>
-__global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
-                                                          StepParams p) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_long || (p.skip && *p.skip)) return;
-    const LongRow lr = longs[wid];
+__device__ __forceinline__ void finish_row(const StepParams &p, const LongRow &lr, int lane) {
     const int kt = p.kt;
     if (kt == 1) {
         float t = 0.0f;
@@ -186,6 +181,25 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
             epilogue<MODE>(p, lr.row, j, t);
         }
     }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
+                                                          StepParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_long) return;
+    finish_row<MODE>(p, longs[wid], lane);
+}
+
+// Row v of the pushed second step: y2 = c [v == s] + (1-c) acc[v] 2^-62,
+// stored as the next gathered vector; acc[v] is cleared for the next query.
+__device__ __forceinline__ void push_convert_row(const StepParams &p, const PushPlan &pp, int64_t v, int32_t s) {
+    const unsigned long long a = pp.acc[v];
+    const float sum = (float)((double)a * 0x1p-62);
+    const float y = fmaf(p.omc, sum, v == (int64_t)s ? p.c : 0.0f);
+    p.zout[zrow(p, v)] = p.w ? y : y * p.inv[v];
+    if (a) pp.acc[v] = 0ull;
 }
 
 // ------------------------------------------------------------ kt == 1
@@ -323,22 +337,43 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     item_1<MODE, FIRST, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
-// The same step, gated by a device flag: the pulled second family step of
-// a single seed, which returns at once when the step was pushed instead.
+// The pulled second family step of a single seed, gated by the push plan's
+// flag: when the step was pushed, each item instead converts its rows from
+// the fixed-point sums (chunked rows are left to the finish launch).
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__restrict__ items, int64_t n_items,
-                                                                StepParams p) {
+                                                                StepParams p, PushPlan pp) {
     __shared__ float lds[kWaves][kGroupMax];
-    if (*p.skip) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
     if (wid >= n_items) return;
     const Item it = items[wid];
-    if (item_kind(it.meta) == kItemBlock) {
+    const int kind = (int)item_kind(it.meta);
+    if (*pp.flag) {
+        const int cnt = kind == (int)kItemGroup ? (int)item_nrows(it.meta)
+                        : kind == (int)kItemRow ? 1
+                        : (kind == (int)kItemBlock && wv == 0) ? 1 : 0;
+        if (lane < cnt) push_convert_row(p, pp, it.row0 + lane, p.seeds[0]);
+        return;
+    }
+    if (kind == (int)kItemBlock) {
         block_row_1<kFamily, false, WEIGHTED>(p, it, lane, wv, lds);
         return;
     }
     item_1<kFamily, false, WEIGHTED>(p, it, wid, lane, lds[wv]);
+}
+
+__global__ __launch_bounds__(kThreads) void gated_finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
+                                                                StepParams p, PushPlan pp) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (wid >= n_long) return;
+    const LongRow lr = longs[wid];
+    if (*pp.flag) {
+        if (lane == 0) push_convert_row(p, pp, lr.row, p.seeds[0]);
+        return;
+    }
+    finish_row<kFamily>(p, lr, lane);
 }
 
 // ------------------------------------------------------------ kt == 64
@@ -621,9 +656,11 @@ __device__ __forceinline__ long long wave_scan_incl(long long x, int lane) {
     return x;
 }
 
-// push_first_kernel for one seed (one wave), which also lays out the second
-// step's frontier F = out(s) + {s}: offs = exclusive prefix sums of outdeg
-// over F, ctrl = {W, |F|}, flag = (W <= wmax).
+// The first family step of one seed (one wave), kept compact: F = out(s) +
+// {s} (s appended when it has no self-loop), y1f[f] = y1 of F's f-th node
+// as a gathered value, and the second step's plan: offs = exclusive prefix
+// sums of outdeg over F, ctrl = {W, |F|}, flag = (W <= wmax).  An invalid
+// seed gives an empty plan with the flag clear.
 __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col,
                                        const float *a_w, PushPlan pp) {
     const int lane = threadIdx.x & 63;
@@ -649,7 +686,7 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
             const int32_t v = a_col[e];
             const float wt = a_w ? a_w[e] : p.inv[s];
             const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
-            p.zout[zrow(p, v)] = a_w ? y : y * p.inv[v];
+            pp.y1f[e - e0] = a_w ? y : y * p.inv[v];
             self |= (v == s);
             d = a_rowptr[v + 1] - a_rowptr[v];
         }
@@ -661,7 +698,7 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
     if (!__any(self)) {
         const long long ds = a_rowptr[s + 1] - e0;
         if (lane == 0) {
-            p.zout[zrow(p, s)] = a_w ? p.c : p.c * p.inv[s];
+            pp.y1f[nf] = a_w ? p.c : p.c * p.inv[s];
             pp.offs[nf + 1] = run + ds;
         }
         run += ds;
@@ -671,6 +708,31 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
         pp.ctrl[0] = run;
         pp.ctrl[1] = nf;
         *pp.flag = run <= pp.wmax ? 1 : 0;
+    }
+}
+
+// Dense y1 (as the gathered vector p.zout) for a second step that is pulled
+// (flag clear): entry v is y1f at v's position in the seed's sorted
+// out-neighbour list, the appended seed entry, or zero.
+__global__ void push_first_dense_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, PushPlan pp) {
+    if (*pp.flag) return;
+    const int32_t s = p.seeds[0];
+    const bool valid = s >= 0 && (int64_t)s < p.n;
+    const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        float val = 0.0f;
+        if (valid) {
+            int64_t lo = e0, hi = e1;  // first edge with a_col >= v
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (a_col[mid] < v) lo = mid + 1;
+                else hi = mid;
+            }
+            if (lo < e1 && a_col[lo] == v) val = pp.y1f[lo - e0];
+            else if (v == (int64_t)s) val = pp.y1f[e1 - e0];
+        }
+        p.zout[zrow(p, v)] = val;
     }
 }
 
@@ -708,23 +770,9 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
         const int32_t u = lo < outdeg_s ? a_col[es + lo] : s;
         const int64_t e = a_rowptr[u] + (t - olo);
         const int32_t v = a_col[e];
-        const float zu = p.zin[zrow(p, u)];
+        const float zu = pp.y1f[lo];
         const float term = a_w ? zu * a_w[e] : zu;
         atomicAdd(&pp.acc[v], __double2ull_rn((double)term * 0x1p62));
-    }
-}
-
-// y2 = c [v == s] + (1-c) acc[v] 2^-62 as the next gathered vector; clears acc.
-__global__ void push_convert_kernel(StepParams p, PushPlan pp) {
-    if (!*pp.flag) return;
-    const int32_t s = p.seeds[0];
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long a = pp.acc[v];
-        const float sum = (float)((double)a * 0x1p-62);
-        const float y = fmaf(p.omc, sum, v == (int64_t)s ? p.c : 0.0f);
-        p.zout[zrow(p, v)] = p.w ? y : y * p.inv[v];
-        if (a) pp.acc[v] = 0ull;
     }
 }
 
@@ -796,14 +844,6 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (s.n_items > 0) {
         int lg = 0;
         while ((1 << lg) < p.kt) ++lg;
-        if (p.skip) {
-            if (p.kt != 1 || mode != kFamily || first)
-                return fail(TPA_ERR_INVALID_ARG, "a gated step is a single-column non-first family step");
-            const int slot = profile_begin(120 + (p.w ? 1 : 0), st);
-            if (p.w) gated_step_kernel_1<true><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p);
-            else gated_step_kernel_1<false><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p);
-            profile_end(slot, st);
-        } else {
         const int slot = profile_begin(16 * lg + 4 * mode + 2 * (first ? 1 : 0) + (p.w ? 1 : 0), st);
         if (mode == kFamily) {
             if (first) launch_w<kFamily, true>(s, p, st);
@@ -815,7 +855,6 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
             launch_w<kStranger, false>(s, p, st);
         }
         profile_end(slot, st);
-        }
     }
     if (s.n_long > 0) {
         const int slot = profile_begin(127, st);
@@ -863,40 +902,58 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
 size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
-    return a + o + 256;
+    const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
+    return a + o + y + 256;
 }
 
 PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
     char *b = static_cast<char *>(base);
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
+    const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
     PushPlan pp;
     pp.acc = reinterpret_cast<unsigned long long *>(b);
     pp.offs = reinterpret_cast<int64_t *>(b + a);
-    pp.ctrl = reinterpret_cast<int64_t *>(b + a + o);
-    pp.flag = reinterpret_cast<int32_t *>(b + a + o + 64);
+    pp.y1f = reinterpret_cast<float *>(b + a + o);
+    pp.ctrl = reinterpret_cast<int64_t *>(b + a + o + y);
+    pp.flag = reinterpret_cast<int32_t *>(b + a + o + y + 64);
     pp.wmax = wmax;
     return pp;
 }
 
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
     if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
-    fill_zero_kernel<<<grid_1d(p.n), 256, 0, st>>>(p.zout, p.n);
     push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
+    push_first_dense_kernel<<<std::min<unsigned>(grid_1d(p.n), 2048), 256, 0, st>>>(p, g->a.rowptr, g->a.col, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
 
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
     if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
-    // grid-stride over the W edge slots: about 4 slots per thread up to the
-    // bound, more beyond 2^24 slots
-    const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (pp.wmax + 4 * 256 - 1) / (4 * 256)), 1 << 14);
+    // grid-stride over the W edge slots: about 16 slots per thread up to the bound
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (pp.wmax + 16 * 256 - 1) / (16 * 256)), 4096);
     const int slot = profile_begin(124, st);
     push_second_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr,
                                                          pp);
-    push_convert_kernel<<<grid_1d(p.n), 256, 0, st>>>(p, pp);
     profile_end(slot, st);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_gated_step(const Schedule &s, const StepParams &p, const PushPlan &pp, hipStream_t st) {
+    if (p.kt != 1 || p.node_block || !p.seeds || p.last)
+        return fail(TPA_ERR_INVALID_ARG, "a gated step is a single-seed non-last family step");
+    if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
+    if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
+        return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
+    if (s.n_items > 0) {
+        const int slot = profile_begin(120 + (p.w ? 1 : 0), st);
+        if (p.w) gated_step_kernel_1<true><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p, pp);
+        else gated_step_kernel_1<false><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p, pp);
+        profile_end(slot, st);
+    }
+    if (s.n_long > 0) gated_finish_kernel<<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

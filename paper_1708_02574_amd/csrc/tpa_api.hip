@@ -217,10 +217,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             }
             if (step == 2 && push2) {
                 TPA_TRY(launch_push_second(p, g, pp, st));
-                p.skip = pp.flag;
-                const tpa_status rc = launch_step(*s, kFamily, false, p, st);
-                p.skip = nullptr;
-                TPA_TRY(rc);
+                TPA_TRY(launch_gated_step(*s, p, pp, st));
                 continue;
             }
             // one-hot restart: the first step needs no gather

@@ -1,0 +1,185 @@
+"""Exact RWR (CPI windows), top-k selection and the accuracy harness on the
+GPU against the FP64 oracle.
+
+* tpa_cpi vs oracle.Graph.cpi on every window the harness uses, seeds and
+  dense restarts, uniform and logit weights: L1 <= 1e-5.
+* tpa_topk vs oracle.topk on the same float32 rows: identical indices and
+  values (the comparison is exact, so both sides decide in FP32).
+* the harness's per-part errors vs the same errors from oracle vectors, and
+  under the paper's bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tpa_inputs as ti
+
+pytestmark = pytest.mark.gpu
+
+c, S, T, EPS = ti.C, ti.S, ti.T, ti.EPS
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a HIP device"
+    return _t
+
+
+@pytest.fixture(scope="module")
+def tpa(torch):
+    import paper_1708_02574_amd as _tpa
+    _tpa.load_library()
+    return _tpa
+
+
+@pytest.fixture(scope="module")
+def rmat13(tpa):
+    scale, samples, seed = ti.GRAPHS["rmat13"]
+    og = oracle.Graph.rmat(scale, samples, seed)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(scale, samples, seed)
+    gg.preprocess(c, T)
+    return og, gg
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64)).sum())
+
+
+WINDOWS = [(0, -1), (0, S - 1), (S, T - 1), (T, -1), (0, 0), (3, 3), (7, 200)]
+
+
+@pytest.mark.parametrize("layout", [1, 0])
+def test_cpi_windows_seed(rmat13, torch, layout):
+    og, gg = rmat13
+    gg.set_gather_layout(bool(layout))
+    try:
+        for s in ti.draw_seeds(og.export()["padded"] == 0, 4, 61):
+            q = np.zeros(og.n)
+            q[s] = 1.0
+            for si, tj in WINDOWS:
+                r = gg.cpi(c, si, tj, EPS, seed=int(s)).cpu().numpy()
+                expect, _ = og.cpi(q, c, EPS, si, tj)
+                assert l1(r, expect) <= TOL, (s, si, tj)
+    finally:
+        gg.set_gather_layout(True)
+
+
+def test_cpi_dense_restart_and_weights(tpa, torch):
+    og = oracle.Graph.rmat(10, 12000, 41)
+    gg = tpa.Graph.rmat(10, 12000, 41)
+    theta = ti.draw_logits(og.m, 42)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    rng = np.random.default_rng(43)
+    q = rng.random(og.n)
+    q /= q.sum()
+    for si, tj in WINDOWS:
+        r = gg.cpi(c, si, tj, EPS, q=torch.from_numpy(q.astype(np.float32))).cpu().numpy()
+        expect, _ = og.cpi(q, c, EPS, si, tj)
+        assert l1(r, expect) <= TOL, (si, tj)
+    # exact RWR of a restart vector with norm 1/2: the break comes earlier
+    r = gg.cpi(c, 0, -1, EPS, q=torch.from_numpy((q / 2).astype(np.float32))).cpu().numpy()
+    expect, _ = og.cpi(q / 2, c, EPS, 0, -1)
+    assert l1(r, expect) <= TOL
+
+
+def test_cpi_windows_add_up_to_exact_rwr(rmat13, torch):
+    """The three exact parts add up to exact RWR: CPI(0, S-1) + CPI(S, T-1)
+    + CPI(T, inf) = CPI(0, inf) (the split of Section 3), whose mass is
+    1 - (1-c)^(K+1) (Lemma 2)."""
+    og, gg = rmat13
+    s = int(ti.draw_seeds(og.export()["padded"] == 0, 1, 62)[0])
+    parts = [gg.cpi(c, a, b, EPS, seed=s) for a, b in ((0, S - 1), (S, T - 1), (T, -1))]
+    whole = gg.cpi(c, 0, -1, EPS, seed=s)
+    assert l1((parts[0] + parts[1] + parts[2]).cpu().numpy(), whole.cpu().numpy()) <= 1e-6
+    mass = float(whole.double().sum())
+    assert abs(mass - (1 - (1 - c) ** 117)) < 1e-6
+
+
+def test_cpi_argument_errors(rmat13, tpa, torch):
+    og, gg = rmat13
+    for kw in ({"seed": og.n}, {"seed": 0, "s_iter": 3, "t_iter": 2}, {"seed": 0, "eps": 0.0},
+               {"seed": 0, "s_iter": -1}):
+        si = kw.pop("s_iter", 0)
+        tj = kw.pop("t_iter", -1)
+        eps = kw.pop("eps", EPS)
+        with pytest.raises(tpa.TPAError):
+            gg.cpi(c, si, tj, eps, **kw)
+    with pytest.raises(ValueError):
+        gg.cpi(c, 0, -1, EPS)
+
+
+@pytest.mark.parametrize("rows,n,k", [(1, 1, 1), (3, 9, 4), (5, 300, 7), (2, 300, 300), (4, 5000, 64),
+                                      (2, 70000, 1024), (3, 1024, 1024), (1, 100000, 1)])
+def test_topk_vs_oracle(tpa, torch, rows, n, k):
+    rng = np.random.default_rng(rows * 1000 + n + k)
+    pool = np.array([0.5, 0.25, 0.0, -0.0, 1e-7, np.nan, 3.0, -2.0, np.inf], np.float32)
+    vals = np.where(rng.random((rows, n)) < 0.5, rng.choice(pool, (rows, n)),
+                    rng.standard_normal((rows, n)).astype(np.float32))
+    idx, val = tpa.topk(torch.from_numpy(vals), k)
+    oi, ov = oracle.topk(vals, k)
+    assert np.array_equal(idx.cpu().numpy(), oi)
+    assert np.array_equal(val.cpu().numpy(), ov, equal_nan=True)
+
+
+def test_topk_on_rwr_rows(rmat13, tpa, torch):
+    og, gg = rmat13
+    seeds = torch.from_numpy(ti.draw_seeds(og.export()["padded"] == 0, 16, 63)).cuda()
+    R = gg.query(seeds, c, S, T)
+    for k in (1, 10, 500, 1024):
+        idx, val = tpa.topk(R, k)
+        oi, ov = oracle.topk(R.cpu().numpy(), k)
+        assert np.array_equal(idx.cpu().numpy(), oi), k
+        assert np.array_equal(val.cpu().numpy(), ov), k
+
+
+def test_topk_argument_errors(tpa, torch):
+    x = torch.zeros((2, 10), device="cuda")
+    for k in (0, 11, 1025):
+        with pytest.raises(tpa.TPAError):
+            tpa.topk(x, k)
+
+
+def test_row_l1_vs_numpy(tpa, torch):
+    rng = np.random.default_rng(64)
+    x = rng.standard_normal((3, 4097)).astype(np.float32)
+    y = rng.standard_normal((3, 4097)).astype(np.float32)
+    got = tpa.row_l1(torch.from_numpy(x), torch.from_numpy(y), a=0.75).cpu().numpy()
+    expect = np.abs(0.75 * x.astype(np.float64) - y.astype(np.float64)).sum(axis=1)
+    assert np.allclose(got, expect, rtol=1e-12, atol=0)
+
+
+def test_error_report_vs_oracle(rmat13, tpa, torch):
+    """The harness on rmat13: per-part L1 errors agree with the same errors
+    from oracle vectors and stay under the paper's bounds; recall values
+    equal those computed by the oracle's top-k on the GPU vectors."""
+    from paper_1708_02574_amd import accuracy
+    og, gg = rmat13
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, 5, 65)
+    rep = accuracy.error_report(gg, seeds, c, S, T, EPS, ks=(10, 100))
+    bounds = accuracy.error_bounds(c, S, T)
+    assert abs(bounds["tpa"] - 2 * (1 - c) ** S) < 1e-15
+    scale = oracle.neighbor_scale(c, S, T)
+    for row, s in zip(rep, seeds):
+        q = np.zeros(og.n)
+        q[s] = 1.0
+        exact, _ = og.cpi(q, c, EPS, 0, -1)
+        fam, _ = og.cpi(q, c, EPS, 0, S - 1)
+        nb, _ = og.cpi(q, c, EPS, S, T - 1)
+        st, _ = og.cpi(q, c, EPS, T, -1)
+        expect = {"neighbor": l1(scale * fam, nb), "stranger": l1(og.str, st),
+                  "tpa": l1(og.query(int(s), c, S, T), exact)}
+        for part in ("neighbor", "stranger", "tpa"):
+            assert abs(row["l1"][part] - expect[part]) <= 3 * TOL, (s, part)
+            assert row["l1"][part] <= bounds[part] + 1e-6, (s, part)
+        for k, rec in row["recall"].items():
+            assert 0.0 <= rec <= 1.0
+        r = gg.query(torch.tensor([int(s)], dtype=torch.int32).cuda(), c, S, T)[0].cpu().numpy()
+        ex = gg.cpi(c, 0, -1, EPS, seed=int(s)).cpu().numpy()
+        for k in (10, 100):
+            a = set(oracle.topk(r, k)[0][0].tolist())
+            b = set(oracle.topk(ex, k)[0][0].tolist())
+            assert row["recall"][k] == len(a & b) / k

@@ -413,6 +413,27 @@ def test_query_errors(tpa, torch):
     gg.query(s, c, S, T)  # still usable
 
 
+@pytest.mark.parametrize("limit", [-1, 0])
+def test_bad_single_seed_gives_nan_row(tpa, torch, limit):
+    """Seed tile 1 (pushed and pulled step 2): an out-of-range seed gives a
+    NaN row and the sticky error, and the next valid query is unaffected."""
+    gg = tpa.Graph.rmat(8, 2000, 1)
+    gg.preprocess(c, T)
+    gg.set_push_limit(limit)
+    try:
+        good = gg.query(torch.tensor([3], dtype=torch.int32), c, S, T)
+        for bad in (256, -1):
+            r = gg.query(torch.tensor([bad], dtype=torch.int32), c, S, T)
+            assert bool(torch.isnan(r).all())
+            with pytest.raises(tpa.TPAError):
+                gg.device_error()
+        again = gg.query(torch.tensor([3], dtype=torch.int32), c, S, T)
+        assert torch.equal(good, again)
+        gg.device_error()
+    finally:
+        gg.set_push_limit(-1)
+
+
 def test_bad_seed_gives_nan_row_and_sticky_error(tpa, torch):
     gg = tpa.Graph.rmat(8, 2000, 1)
     gg.preprocess(c, T)

@@ -346,3 +346,33 @@ def test_adjoint_matches_central_differences():
         Qm_ = Q.copy(); Qm_[j, v] -= h
         fd = (loss(theta, Qp) - loss(theta, Qm_)) / (2 * h)
         assert abs(fd - dq[j, v]) <= 1e-9 * max(1.0, abs(dq[j, v]))
+
+
+def test_topk_defining_properties():
+    """oracle.topk against the properties that fix a top-k list uniquely:
+    k entries; values non-increasing with NaN last; every unselected entry
+    no larger than the smallest selected one; among entries equal to the
+    cut value, the smallest indices are taken; equal values in index order."""
+    rng = np.random.default_rng(44)
+    for n, k in ((1, 1), (9, 4), (300, 7), (300, 300), (2000, 64)):
+        pool = np.array([0.5, 0.25, 0.0, -0.0, 1e-7, np.nan, 3.0], np.float32)
+        vals = np.where(rng.random((4, n)) < 0.6, rng.choice(pool, (4, n)),
+                        rng.random((4, n)).astype(np.float32))
+        idx, val = oracle.topk(vals, k)
+        for r in range(4):
+            row, sel = vals[r], idx[r]
+            assert len(set(sel.tolist())) == k
+            assert np.array_equal(val[r], row[sel], equal_nan=True)
+            key = np.where(np.isnan(row), -np.inf, row.astype(np.float64))
+            ks = key[sel]
+            assert np.all(ks[1:] <= ks[:-1])
+            rest = np.setdiff1d(np.arange(n), sel)
+            if len(rest):
+                assert key[rest].max() <= ks.min()
+            cut = ks[-1]
+            tied = np.flatnonzero(key == cut)
+            chosen = np.sort(sel[ks == cut])
+            assert np.array_equal(chosen, tied[:len(chosen)])
+            for v in np.unique(ks):
+                pos = sel[ks == v]
+                assert np.all(np.diff(pos) > 0)
