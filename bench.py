@@ -83,6 +83,35 @@ def cpu_baseline(scale: int, samples: int, seed: int, seeds, n_queries: int):
     }
 
 
+def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
+    """Untimed context for the JSON line: TPA's accuracy against exact RWR
+    on 4 seeds (the paper's error table and top-k recall, computed by the
+    library's kernels), and the adjoint's time for 64 seeds."""
+    from paper_1708_02574_amd import accuracy
+    print("bench: accuracy report and adjoint timing", file=sys.stderr, flush=True)
+    rep = accuracy.error_report(g, seeds_h[:4], C_RESTART, S_FAM, T_STR, 1e-9, ks=(10, 100, 500))
+    acc = {
+        "seeds": len(rep),
+        "l1_mean": {p: round(float(np.mean([r["l1"][p] for r in rep])), 5) for p in ("neighbor", "stranger", "tpa")},
+        "l1_bound": {p: round(v, 5) for p, v in accuracy.error_bounds(C_RESTART, S_FAM, T_STR).items()},
+        "recall_mean": {str(k): round(float(np.mean([r["recall"][k] for r in rep])), 4) for k in (10, 100, 500)},
+    }
+    ka = 64
+    gv = torch.from_numpy(np.random.default_rng(7).standard_normal((ka, g.n)).astype(np.float32)).cuda()
+    g.set_tuning(seed_tile=64)
+    g.backward(gv, C_RESTART, S_FAM, T_STR, seeds=seeds[:ka])  # warm-up
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    g.backward(gv, C_RESTART, S_FAM, T_STR, seeds=seeds[:ka])
+    b.record()
+    torch.cuda.synchronize()
+    g.set_tuning(seed_tile=0)
+    return {"accuracy": acc, "adjoint": {"seeds": ka, "ms": round(a.elapsed_time(b), 3),
+                                         "note": "gradients w.r.t. edge weights and restart vectors, "
+                                                 "stranger chain recomputed from checkpoints"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +120,8 @@ def main():
     ap.add_argument("--seeds", type=int, default=N_SEEDS)
     ap.add_argument("--cpu-queries", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the untimed accuracy report and adjoint timing")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -225,6 +256,8 @@ def main():
         },
         "checks": {"mass_max_err": mass_err, "plain_vs_batched_max_abs": max_diff},
     }
+    if not args.no_extras:
+        rec.update(extras(tpa, g, seeds, seeds_h, torch, np))
     if args.calibration_copy_mib > 0:
         src = torch.empty(args.calibration_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
