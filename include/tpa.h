@@ -276,8 +276,9 @@ tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
  * device for dense q.  s_iter = 0, t_iter = -1 gives exact RWR up to the
  * truncation (Theorem 1); [0, S-1], [S, T-1] and [T, -1] give the exact
  * family, neighbor and stranger parts.  out: float[n], the summed window
- * (Kahan-compensated FP32).  Needs no preprocessing.  Synchronous (it
- * allocates and frees its work vectors).  Errors: INVALID_ARG (not exactly
+ * (Kahan-compensated FP32).  Needs no preprocessing (it builds the gather
+ * layout of tpa_set_gather_layout if that is on and not built yet).
+ * Synchronous (it allocates and frees its work vectors).  Errors: INVALID_ARG (not exactly
  * one of seed >= 0 and q, seed >= n, c outside (0,1), s_iter < 0,
  * t_iter < -1, t_iter < s_iter, eps < 0, eps = 0 with t_iter = -1), OOM,
  * HIP. */

@@ -43,12 +43,15 @@ def error_report(g: Graph, seeds, c: float, S: int, T: int, eps: float = 1e-9, k
     out = []
     for s in [int(x) for x in seeds]:
         exact = g.cpi(c, 0, -1, eps, seed=s)
-        fam = g.cpi(c, 0, S - 1, eps, seed=s)
-        nb = g.cpi(c, S, T - 1, eps, seed=s)
         st = g.cpi(c, T, -1, eps, seed=s)
         r = g.query(torch.tensor([s], dtype=torch.int32, device="cuda"), c, S, T)[0]
+        nb_err = 0.0  # S == T: the neighbor part is empty
+        if S < T:
+            fam = g.cpi(c, 0, S - 1, eps, seed=s)
+            nb = g.cpi(c, S, T - 1, eps, seed=s)
+            nb_err = float(row_l1(fam, nb, a=scale)[0])
         err = {
-            "neighbor": float(row_l1(fam, nb, a=scale)[0]),
+            "neighbor": nb_err,
             "stranger": float(row_l1(stranger, st)[0]),
             "tpa": float(row_l1(r, exact)[0]),
         }
@@ -62,3 +65,86 @@ def error_report(g: Graph, seeds, c: float, S: int, T: int, eps: float = 1e-9, k
             rec[k] = len(a & b) / k
         out.append({"seed": s, "l1": err, "recall": rec})
     return out
+
+
+def st_sweep(g: Graph, seeds, c: float, pairs, eps: float = 1e-9, reps: int = 3) -> list[dict]:
+    """Errors against exact RWR and single-seed query time for each (S, T)
+    in pairs: the trade-off the paper discusses when selecting S and T and
+    measures in its study of the effects of the parameters (online time and
+    L1 error of r_TPA over S at T = 10; L1 errors of the neighbor part, the
+    stranger part and r_TPA over T at S = 5).  For each T the graph is
+    preprocessed again (the stranger part depends on T).  Each row holds
+    the mean and largest L1 error of r_TPA over the seeds, the mean L1
+    errors of r~_neighbor and r~_stranger against their exact parts, the
+    bound 2(1-c)^S, the best of `reps` timings of one single-seed query per
+    seed (microseconds per query) and the preprocessing time.  The graph is
+    left preprocessed with the last T of the sweep."""
+    import torch
+
+    seeds = [int(x) for x in seeds]
+    sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
+    exact = torch.stack([g.cpi(c, 0, -1, eps, seed=s) for s in seeds])
+    out = torch.empty_like(exact)
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    rows = []
+    for T in sorted({int(t) for _, t in pairs}):
+        a, b = ev(), ev()
+        a.record()
+        g.preprocess(c, T, eps)
+        b.record()
+        torch.cuda.synchronize()
+        pre_ms = a.elapsed_time(b)
+        stranger = g.stranger()
+        st_err = [float(row_l1(stranger, g.cpi(c, T, -1, eps, seed=s))[0]) for s in seeds]
+        for S in sorted({int(s) for s, t in pairs if int(t) == T}):
+            best = float("inf")
+            for _ in range(reps):
+                a.record()
+                for i in range(len(seeds)):
+                    g.query(sd[i:i + 1], c, S, T, out=out[i:i + 1])
+                b.record()
+                torch.cuda.synchronize()
+                best = min(best, a.elapsed_time(b))
+            err = row_l1(out, exact).cpu().tolist()
+            scale = ((1.0 - c) ** S - (1.0 - c) ** T) / (1.0 - (1.0 - c) ** S)
+            nb_err = [0.0] * len(seeds)
+            if S < T:
+                nb_err = [float(row_l1(g.cpi(c, 0, S - 1, eps, seed=s), g.cpi(c, S, T - 1, eps, seed=s),
+                                       a=scale)[0]) for s in seeds]
+            rows.append({"S": S, "T": T, "l1_mean": sum(err) / len(err), "l1_max": max(err),
+                         "l1_neighbor": sum(nb_err) / len(nb_err), "l1_stranger": sum(st_err) / len(st_err),
+                         "bound": 2 * (1.0 - c) ** S, "us_per_query": best * 1e3 / len(seeds),
+                         "preprocess_ms": pre_ms})
+    return rows
+
+
+def _main():
+    import argparse
+    import os
+    import sys
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import tpa_inputs as ti
+
+    ap = argparse.ArgumentParser(description="TPA accuracy vs exact RWR on a synthetic R-MAT graph")
+    ap.add_argument("--graph", default="rmat20", choices=sorted(ti.GRAPHS))
+    ap.add_argument("--seeds", type=int, default=16)
+    args = ap.parse_args()
+    scale, samples, gseed = ti.GRAPHS[args.graph]
+    g = Graph.rmat(scale, samples, gseed)
+    seeds = ti.draw_seeds((g.padded() == 0).cpu().numpy(), args.seeds, 1)
+    pairs = [(S, ti.T) for S in range(1, 11)] + [(ti.S, T) for T in (5, 6, 8, 12, 15, 20, 25, 30)]
+    print(f"{args.graph}: n={g.n} m={g.m}, {len(seeds)} seeds, c={ti.C}")
+    print(f"{'S':>3} {'T':>3} {'L1 TPA':>8} {'max':>8} {'bound':>7} {'L1 nbr':>8} {'L1 str':>8} "
+          f"{'us/query':>9} {'prep ms':>8}")
+    for r in st_sweep(g, seeds, ti.C, pairs, ti.EPS):
+        print(f"{r['S']:3d} {r['T']:3d} {r['l1_mean']:8.4f} {r['l1_max']:8.4f} {r['bound']:7.4f} "
+              f"{r['l1_neighbor']:8.4f} {r['l1_stranger']:8.4f} {r['us_per_query']:9.1f} "
+              f"{r['preprocess_ms']:8.2f}", flush=True)
+    torch.cuda.synchronize()
+
+
+if __name__ == "__main__":
+    _main()

@@ -226,6 +226,7 @@ extern "C" tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, doubl
     }
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
+    if (g->gather_layout && !g->weighted) TPA_TRY(ensure_zlayout(g, st));
     const bool hub = g->gather_layout && g->zperm && !g->weighted;
     float *tmp = nullptr;
     TPA_TRY(dalloc(&tmp, 3 * (size_t)n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));

@@ -339,28 +339,34 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
 
 // The pulled second family step of a single seed, gated by the push plan's
 // flag: when the step was pushed, each item instead converts its rows from
-// the fixed-point sums (chunked rows are left to the finish launch).
+// the fixed-point sums (chunked rows are left to the finish launch).  Blocks
+// stride over 4-item slots (one slot each at the launch's grid); block items
+// fill whole slots, so all 4 waves of a block meet the same barriers.
+
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__restrict__ items, int64_t n_items,
                                                                 StepParams p, PushPlan pp) {
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
-    if (wid >= n_items) return;
-    const Item it = items[wid];
-    const int kind = (int)item_kind(it.meta);
-    if (*pp.flag) {
-        const int cnt = kind == (int)kItemGroup ? (int)item_nrows(it.meta)
-                        : kind == (int)kItemRow ? 1
-                        : (kind == (int)kItemBlock && wv == 0) ? 1 : 0;
-        if (lane < cnt) push_convert_row(p, pp, it.row0 + lane, p.seeds[0]);
-        return;
+    const bool pushed = *pp.flag != 0;
+    const int64_t slots = (n_items + kWaves - 1) / kWaves;
+    for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
+        const int64_t wid = b * kWaves + wv;
+        if (wid >= n_items) continue;  // only in the last slot, which holds no block item
+        const Item it = items[wid];
+        const int kind = (int)item_kind(it.meta);
+        if (pushed) {
+            const int cnt = kind == (int)kItemGroup ? (int)item_nrows(it.meta)
+                            : kind == (int)kItemRow ? 1
+                            : (kind == (int)kItemBlock && wv == 0) ? 1 : 0;
+            if (lane < cnt) push_convert_row(p, pp, it.row0 + lane, p.seeds[0]);
+        } else if (kind == (int)kItemBlock) {
+            block_row_1<kFamily, false, WEIGHTED>(p, it, lane, wv, lds);
+            __syncthreads();  // wave 0 has read the quarter sums before the slot is reused
+        } else {
+            item_1<kFamily, false, WEIGHTED>(p, it, wid, lane, lds[wv]);
+        }
     }
-    if (kind == (int)kItemBlock) {
-        block_row_1<kFamily, false, WEIGHTED>(p, it, lane, wv, lds);
-        return;
-    }
-    item_1<kFamily, false, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
 __global__ __launch_bounds__(kThreads) void gated_finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
@@ -924,7 +930,7 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
     if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
     push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
-    push_first_dense_kernel<<<std::min<unsigned>(grid_1d(p.n), 2048), 256, 0, st>>>(p, g->a.rowptr, g->a.col, pp);
+    push_first_dense_kernel<<<std::min<unsigned>(grid_1d(p.n), 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
@@ -949,8 +955,9 @@ tpa_status launch_gated_step(const Schedule &s, const StepParams &p, const PushP
         return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
     if (s.n_items > 0) {
         const int slot = profile_begin(120 + (p.w ? 1 : 0), st);
-        if (p.w) gated_step_kernel_1<true><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p, pp);
-        else gated_step_kernel_1<false><<<blocks_for(s.n_items), kThreads, 0, st>>>(s.items, s.n_items, p, pp);
+        const unsigned grid = blocks_for(s.n_items);  // one slot per block: the pushed case converts in parallel
+        if (p.w) gated_step_kernel_1<true><<<grid, kThreads, 0, st>>>(s.items, s.n_items, p, pp);
+        else gated_step_kernel_1<false><<<grid, kThreads, 0, st>>>(s.items, s.n_items, p, pp);
         profile_end(slot, st);
     }
     if (s.n_long > 0) gated_finish_kernel<<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p, pp);

@@ -183,3 +183,24 @@ def test_error_report_vs_oracle(rmat13, tpa, torch):
             a = set(oracle.topk(r, k)[0][0].tolist())
             b = set(oracle.topk(ex, k)[0][0].tolist())
             assert row["recall"][k] == len(a & b) / k
+
+
+def test_st_sweep_agrees_with_error_report(tpa, torch):
+    """The S/T sweep's per-(S, T) errors equal the harness's per-seed
+    errors at the same parameters and respect the bound 2(1-c)^S."""
+    from paper_1708_02574_amd import accuracy
+    scale, samples, seed = ti.GRAPHS["rmat13"]
+    gg = tpa.Graph.rmat(scale, samples, seed)
+    seeds = ti.draw_seeds((gg.padded() == 0).cpu().numpy(), 3, 66)
+    pairs = [(1, 10), (3, 10), (5, 10), (5, 5), (5, 20)]
+    rows = accuracy.st_sweep(gg, seeds, c, pairs, EPS, reps=1)
+    assert [(r["S"], r["T"]) for r in rows] == [(5, 5), (1, 10), (3, 10), (5, 10), (5, 20)]
+    for r in rows:
+        gg.preprocess(c, r["T"], EPS)
+        rep = accuracy.error_report(gg, seeds, c, r["S"], r["T"], EPS, ks=(10,))
+        assert abs(r["l1_mean"] - np.mean([x["l1"]["tpa"] for x in rep])) <= 1e-9
+        assert abs(r["l1_stranger"] - np.mean([x["l1"]["stranger"] for x in rep])) <= 1e-9
+        nb = np.mean([x["l1"]["neighbor"] for x in rep]) if r["S"] < r["T"] else 0.0
+        assert abs(r["l1_neighbor"] - nb) <= 1e-9
+        assert r["l1_max"] <= r["bound"] + 1e-6
+        assert r["us_per_query"] > 0 and r["preprocess_ms"] > 0
