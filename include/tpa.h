@@ -237,6 +237,11 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * restores the default (m/8, at least 1024), 0 always pulls.  The pushed
  * sums are exact fixed-point additions of FP32 terms, so results are
  * reproducible but may differ from the pulled step in the last bits.
+ * The pull that follows a push (step 3 after a pushed step 2, step 2 after
+ * the pushed step 1 of a seed tile of 1 or 64) skips the gathers of rows
+ * the push left zero, using a bitmap the push fills; the skipped terms are
+ * exact zeros, so the sums are unchanged.  max_edges = 0 also turns this
+ * skip off.
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
 

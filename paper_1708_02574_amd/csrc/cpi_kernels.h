@@ -49,6 +49,12 @@ struct StepParams {
     float *acc = nullptr;
     float *comp = nullptr;
     int accumulate = 0;
+    // frontier skip (pull steps after a push): bit r of `bits` clear means
+    // row r of zin is all zero, so its gathers are skipped (their terms are
+    // exact zeros, so the sums are unchanged); applies when bits is set and
+    // bits_on is null or *bits_on != 0
+    const uint32_t *bits = nullptr;
+    const int32_t *bits_on = nullptr;
 };
 
 // Device state of the pushed first two family steps of a single seed
@@ -59,6 +65,8 @@ struct StepParams {
 // is all zero between queries.
 struct PushPlan {
     unsigned long long *acc = nullptr;  // [n], zero between queries
+    uint32_t *bits = nullptr;           // [ceil(n/32)]: rows of the pushed vector that may be non-zero
+    int64_t nwords = 0;
     int64_t *offs = nullptr;            // [max_outdeg + 2]
     float *y1f = nullptr;               // [max_outdeg + 1]
     int64_t *ctrl = nullptr;            // {W, |F|}
@@ -87,8 +95,11 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 
 // First family step from seeds (any tile width) pushed over each seed's
 // out-edges of A~: zout = y1 scaled as the gathered vector, zero elsewhere
-// (a fill launch, then one wave per (block, column) seed).
-tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st);
+// (a fill launch, then one wave per (block, column) seed).  When bits is
+// not null it is cleared first and receives the rows of zout that may be
+// non-zero.
+tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, uint32_t *bits,
+                             int64_t nwords, hipStream_t st);
 
 // Single seed (kt == 1, unpacked): the first step kept compact on F (y1f)
 // with the plan of the second step (offs, W, |F|, flag = W <= wmax); when
@@ -99,7 +110,8 @@ tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const
 // Second family step of a single seed pushed over the out-edges of F when
 // the plan's flag is set: the pulled sums of y2 = c e_s + (1-c) A~^T y1
 // accumulated in fixed point (order-independent, so bitwise reproducible)
-// into acc.  With the flag clear it returns at once.
+// into acc, and the rows of y2 that may be non-zero marked in bits (which
+// the plan's second launch cleared).  With the flag clear it returns at once.
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // The second family step proper (p.zin = dense y1, p.zout = y2 as the next

@@ -71,6 +71,18 @@ struct EpiPre {
 // Row of node v in the work vectors.
 __device__ __forceinline__ int64_t zrow(const StepParams &p, int64_t v) { return p.zperm ? p.zperm[v] : v; }
 
+// Frontier skip in force for this launch (see StepParams::bits).
+__device__ __forceinline__ bool frontier_on(const StepParams &p) { return p.bits && (!p.bits_on || *p.bits_on); }
+
+// Row u of the gathered vector may be non-zero.
+__device__ __forceinline__ bool row_live(const StepParams &p, int32_t u) {
+    return (p.bits[(uint32_t)u >> 5] >> ((uint32_t)u & 31u)) & 1u;
+}
+
+__device__ __forceinline__ void mark_row(uint32_t *bits, int64_t r) {
+    atomicOr(&bits[r >> 5], 1u << (r & 31));
+}
+
 template <int MODE>
 __device__ __forceinline__ EpiPre epi_load(const StepParams &p, int64_t v) {
     EpiPre q;
@@ -99,9 +111,19 @@ __device__ __forceinline__ EpiPre epi_readlane(const EpiPre &q, int r) {
     return o;
 }
 
+// Column j's seed when the caller loaded it ahead (plain seed lists), or
+// kSeedLookup to read it per row (packed graphs, dense restarts).
+constexpr int32_t kSeedLookup = INT32_MIN;
+
+__device__ __forceinline__ int32_t seed_ahead(const StepParams &p, int j) {
+    if (p.node_block || p.qdense) return kSeedLookup;
+    return j < p.ncols ? p.seeds[j] : -1;
+}
+
 // Epilogue for row v, column j, with pulled sum `sum` and operands q.
 template <int MODE>
-__device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j, float sum, const EpiPre &q) {
+__device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j, float sum, const EpiPre &q,
+                                          int32_t seed_pre = kSeedLookup) {
     if (MODE == kFamily) {
         if (j >= p.ncols) return;
         int32_t seed = -1;
@@ -109,7 +131,7 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
         if (p.qdense) {
             restart = p.c * p.qdense[(int64_t)j * p.n + v];
         } else {
-            seed = seed_of(p, v, j);
+            seed = seed_pre != kSeedLookup ? seed_pre : seed_of(p, v, j);
             restart = (v == (int64_t)seed) ? p.c : 0.0f;
         }
         const float y = fmaf(p.omc, sum, restart);
@@ -208,6 +230,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     const int32_t *col = p.col + it.e0;
+    const int32_t seed_pre = MODE == kFamily ? seed_ahead(p, 0) : kSeedLookup;
     if (kind == (int)kItemGroup) {
         constexpr int NS = kGroupMax / 64;
         const int nrows = (int)item_nrows(it.meta);
@@ -221,6 +244,11 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         }
         EpiPre q;
         if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
+        if (!FIRST && frontier_on(p)) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (u[s] >= 0 && !row_live(p, u[s])) u[s] = -1;  // a zero row: its term is 0
+        }
         float v[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
@@ -237,7 +265,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         if (lane < nrows && len <= 32) {
             float acc = 0.0f;
             for (int k = rel; k < rel_next; ++k) acc += my[k];
-            epi_store<MODE>(p, it.row0 + lane, 0, acc, q);
+            epi_store<MODE>(p, it.row0 + lane, 0, acc, q, seed_pre);
         }
         uint64_t big = __ballot(lane < nrows && len > 32);
         while (big) {
@@ -249,7 +277,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
             for (int k = b + lane; k < en; k += 64) t += my[k];
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) epi_store<MODE>(p, it.row0 + r, 0, t, qr);
+            if (lane == 0) epi_store<MODE>(p, it.row0 + r, 0, t, qr, seed_pre);
         }
         return;
     }
@@ -257,6 +285,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
     constexpr int UNR = 16;
     EpiPre q;
     if (kind == (int)kItemRow && lane == 0) q = epi_load<MODE>(p, it.row0);
+    const bool sparse = !FIRST && frontier_on(p);
     float s = 0.0f;
     for (int base = 0; base < nnz; base += 64 * UNR) {
         int32_t u[UNR];
@@ -264,6 +293,11 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         for (int k = 0; k < UNR; ++k) {
             const int e = base + k * 64 + lane;
             u[k] = e < nnz ? col[e] : -1;
+        }
+        if (sparse) {
+#pragma unroll
+            for (int k = 0; k < UNR; ++k)
+                if (u[k] >= 0 && !row_live(p, u[k])) u[k] = -1;
         }
         float v[UNR];
 #pragma unroll
@@ -276,7 +310,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
         if (kind == (int)kItemRow)
-            epi_store<MODE>(p, it.row0, 0, s, q);
+            epi_store<MODE>(p, it.row0, 0, s, q, seed_pre);
         else
             p.partials[wid] = s;
     }
@@ -294,6 +328,7 @@ __device__ __forceinline__ void block_row_1(const StepParams &p, const Item it, 
     if (wv == 0 && lane == 0) q = epi_load<MODE>(p, it.row0);
     const int32_t *col = p.col + it.e0;
     constexpr int UNR = 16;
+    const bool sparse = !FIRST && frontier_on(p);
     float s = 0.0f;
     for (int base = qb; base < qe; base += 64 * UNR) {
         int32_t u[UNR];
@@ -301,6 +336,11 @@ __device__ __forceinline__ void block_row_1(const StepParams &p, const Item it, 
         for (int k = 0; k < UNR; ++k) {
             const int e = base + k * 64 + lane;
             u[k] = e < qe ? col[e] : -1;
+        }
+        if (sparse) {
+#pragma unroll
+            for (int k = 0; k < UNR; ++k)
+                if (u[k] >= 0 && !row_live(p, u[k])) u[k] = -1;
         }
         float v[UNR];
 #pragma unroll
@@ -398,18 +438,20 @@ __device__ __forceinline__ float walk_value(const StepParams &p, int32_t u, floa
 }
 
 // Final output of the last family step for row v, column j (the fused
-// combine of Algorithm 3); NaN (and the sticky flag) for an invalid seed.
-__device__ __forceinline__ float family_out_value(const StepParams &p, int64_t v, int j, float sum) {
+// combine of Algorithm 3), with r~_stranger[v] in q.a; NaN (and the sticky
+// flag) for an invalid seed.
+__device__ __forceinline__ float family_out_value(const StepParams &p, int64_t v, int j, float sum, const EpiPre &q,
+                                                  int32_t seed_pre) {
     int32_t seed = -1;
     float restart;
     if (p.qdense) {
         restart = p.c * p.qdense[(int64_t)j * p.n + v];
     } else {
-        seed = seed_of(p, v, j);
+        seed = seed_pre != kSeedLookup ? seed_pre : seed_of(p, v, j);
         restart = (v == (int64_t)seed) ? p.c : 0.0f;
     }
     const float y = fmaf(p.omc, sum, restart);
-    if (p.qdense || seed_valid(p, v, seed)) return fmaf(p.alpha, y, p.str[v]);
+    if (p.qdense || seed_valid(p, v, seed)) return fmaf(p.alpha, y, q.a);
     *p.err = 1;
     return qnan();
 }
@@ -439,10 +481,16 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         if (!WEIGHTED && seed_plain >= 0 && (int64_t)seed_plain < p.n) cinv_plain = p.c * p.inv[seed_plain];
     }
     constexpr int U = 16;
+    const bool sparse = !FIRST && frontier_on(p);
+    // the epilogue's per-row operands are loaded ahead, one row per lane, and
+    // each lane's seed once: no memory round trip at a row boundary
+    const int32_t seed_pre = MODE == kFamily ? seed_ahead(p, lane) : kSeedLookup;
     if (kind == (int)kItemGroup) {
         const bool staged = MODE == kFamily && p.last;
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        EpiPre q;
+        if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
         int r = 0;
         int rend = __builtin_amdgcn_readlane(rel, 1);
         float acc = 0.0f;
@@ -450,26 +498,29 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
             const int cnt = min(64, nnz - base);
             const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
             const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
+            const uint64_t live = sparse ? __ballot(lane < cnt && row_live(p, colv)) : ~0ull;
             for (int t0 = 0; t0 < cnt; t0 += U) {
                 float v[U];
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
                     const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
-                    v[k] = walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain);
+                    v[k] = ((live >> (t0 + k)) & 1ull) ? walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain)
+                                                       : 0.0f;
                 }
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     if (t0 + k < cnt) {
                         const int e = base + t0 + k;
                         while (e >= rend) {
+                            const EpiPre qr = epi_readlane(q, r);
                             if (staged) {
                                 buf[(r % kStageRows) * kStageStride + lane] =
-                                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc) : 0.0f;
+                                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc, qr, seed_pre) : 0.0f;
                                 if (r % kStageRows == kStageRows - 1)
                                     stage_write(p, buf, it.row0 + r - (kStageRows - 1), kStageRows, lane);
                             } else {
-                                epilogue<MODE>(p, it.row0 + r, lane, acc);
+                                epi_store<MODE>(p, it.row0 + r, lane, acc, qr, seed_pre);
                             }
                             acc = 0.0f;
                             ++r;
@@ -481,13 +532,14 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
             }
         }
         for (; r < nrows; ++r) {
+            const EpiPre qr = epi_readlane(q, r);
             if (staged) {
                 buf[(r % kStageRows) * kStageStride + lane] =
-                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc) : 0.0f;
+                    lane < p.ncols ? family_out_value(p, it.row0 + r, lane, acc, qr, seed_pre) : 0.0f;
                 if (r % kStageRows == kStageRows - 1)
                     stage_write(p, buf, it.row0 + r - (kStageRows - 1), kStageRows, lane);
             } else {
-                epilogue<MODE>(p, it.row0 + r, lane, acc);
+                epi_store<MODE>(p, it.row0 + r, lane, acc, qr, seed_pre);
             }
             acc = 0.0f;
         }
@@ -496,18 +548,22 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         return;
     }
     // one row (or a chunk of one): U edges in flight, sequential per lane
+    EpiPre q1;
+    if (kind == (int)kItemRow) q1 = epi_load<MODE>(p, it.row0);
     float s = 0.0f;
     for (int base = 0; base < nnz; base += 64) {
         const int cnt = min(64, nnz - base);
         const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
         const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
+        const uint64_t live = sparse ? __ballot(lane < cnt && row_live(p, colv)) : ~0ull;
         for (int t0 = 0; t0 < cnt; t0 += U) {
             float v[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
                 const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
-                v[k] = walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain);
+                v[k] = ((live >> (t0 + k)) & 1ull) ? walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain)
+                                                   : 0.0f;
             }
 #pragma unroll
             for (int k = 0; k < U; ++k)
@@ -515,7 +571,7 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         }
     }
     if (kind == (int)kItemRow)
-        epilogue<MODE>(p, it.row0, lane, s);
+        epi_store<MODE>(p, it.row0, lane, s, q1, seed_pre);
     else
         p.partials[wid * 64 + lane] = s;
 }
@@ -560,19 +616,27 @@ __device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int6
     const int j = lane % KT, sub = lane / KT;
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
+    const int32_t seed_pre = MODE == kFamily ? seed_ahead(p, j) : kSeedLookup;
     if (kind == (int)kItemGroup) {
+        // row offsets and epilogue operands loaded ahead, one row per lane
         const int nrows = (int)item_nrows(it.meta);
+        const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        EpiPre q;
+        if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
         for (int r = 0; r < nrows; ++r) {
-            const int64_t row = it.row0 + r;
-            const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, p.rowptr[row], p.rowptr[row + 1], sub, j);
-            if (sub == 0) epilogue<MODE>(p, row, j, s);
+            const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel, r + 1);
+            const EpiPre qr = epi_readlane(q, r);
+            const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0 + b, it.e0 + en, sub, j);
+            if (sub == 0) epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
         }
         return;
     }
+    EpiPre q1;
+    if (kind == (int)kItemRow) q1 = epi_load<MODE>(p, it.row0);
     const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0, it.e0 + nnz, sub, j);
     if (sub == 0) {
         if (kind == (int)kItemRow)
-            epilogue<MODE>(p, it.row0, j, s);
+            epi_store<MODE>(p, it.row0, j, s, q1, seed_pre);
         else
             p.partials[wid * KT + j] = s;
     }
@@ -630,7 +694,7 @@ __global__ void fill_zero_kernel(float *z, int64_t n) {
 // y1 = c e_s + (1-c) c A~^T e_s is non-zero only at s and its out-neighbors
 // (one wave per (block, column) seed; the rest of zout was zero-filled).
 __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
-                                  int64_t nslots) {
+                                  int64_t nslots, uint32_t *bits) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (w >= nslots) return;
@@ -646,10 +710,16 @@ __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const i
         const int32_t v = a_col[e];
         const float wt = a_w ? a_w[e] : p.inv[s];
         const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
-        p.zout[zrow(p, v) * p.kt + j] = a_w ? y : y * p.inv[v];
+        const int64_t zr = zrow(p, v);
+        p.zout[zr * p.kt + j] = a_w ? y : y * p.inv[v];
+        if (bits) mark_row(bits, zr);
         self |= (v == s);
     }
-    if (!__any(self) && lane == 0) p.zout[zrow(p, s) * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
+    if (!__any(self) && lane == 0) {
+        const int64_t zr = zrow(p, s);
+        p.zout[zr * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
+        if (bits) mark_row(bits, zr);
+    }
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
@@ -717,11 +787,17 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
     }
 }
 
-// Dense y1 (as the gathered vector p.zout) for a second step that is pulled
-// (flag clear): entry v is y1f at v's position in the seed's sorted
-// out-neighbour list, the appended seed entry, or zero.
+// Flag set: clear the frontier bitmap for the pushed second step.  Flag
+// clear: dense y1 (as the gathered vector p.zout) for a second step that is
+// pulled: entry v is y1f at v's position in the seed's sorted out-neighbour
+// list, the appended seed entry, or zero.
 __global__ void push_first_dense_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, PushPlan pp) {
-    if (*pp.flag) return;
+    if (*pp.flag) {
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pp.nwords;
+             i += (int64_t)gridDim.x * blockDim.x)
+            pp.bits[i] = 0u;
+        return;
+    }
     const int32_t s = p.seeds[0];
     const bool valid = s >= 0 && (int64_t)s < p.n;
     const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
@@ -764,6 +840,7 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
     const int64_t es = a_rowptr[s];
     const int64_t outdeg_s = a_rowptr[s + 1] - es;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) mark_row(pp.bits, zrow(p, s));  // the restart term
     for (int64_t t = first + threadIdx.x; t < W; t += stride) {
         int64_t lo = 0, hi = nf;
         while (hi - lo > 1) {
@@ -778,7 +855,7 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
         const int32_t v = a_col[e];
         const float zu = pp.y1f[lo];
         const float term = a_w ? zu * a_w[e] : zu;
-        atomicAdd(&pp.acc[v], __double2ull_rn((double)term * 0x1p62));
+        if (atomicAdd(&pp.acc[v], __double2ull_rn((double)term * 0x1p62)) == 0ull) mark_row(pp.bits, zrow(p, v));
     }
 }
 
@@ -896,20 +973,26 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st) {
     return TPA_OK;
 }
 
-tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, hipStream_t st) {
+tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, uint32_t *bits,
+                             int64_t nwords, hipStream_t st) {
     const int64_t nslots = nblocks * p.ncols;
     fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
-    push_first_kernel<<<(unsigned)((nslots * 64 + 255) / 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col,
-                                                                            g->weighted ? g->a.w : nullptr, nslots);
+    if (bits) fill_zero_kernel<<<grid_1d(nwords), 256, 0, st>>>(reinterpret_cast<float *>(bits), nwords);
+    push_first_kernel<<<(unsigned)((nslots * 64 + 255) / 256), 256, 0, st>>>(
+        p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, nslots, bits);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
+
+namespace {
+size_t bits_bytes(int64_t n) { return (((size_t)(n + 31) / 32) * 4 + 255) & ~(size_t)255; }
+}  // namespace
 
 size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
     const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
-    return a + o + y + 256;
+    return a + o + y + 256 + bits_bytes(n);
 }
 
 PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
@@ -923,6 +1006,8 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
     pp.y1f = reinterpret_cast<float *>(b + a + o);
     pp.ctrl = reinterpret_cast<int64_t *>(b + a + o + y);
     pp.flag = reinterpret_cast<int32_t *>(b + a + o + y + 64);
+    pp.bits = reinterpret_cast<uint32_t *>(b + a + o + y + 256);
+    pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
     return pp;
 }

@@ -172,6 +172,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     // the seed's neighbourhood when it is small, pull otherwise (decided on
     // the device, so the launch sequence is fixed and capturable)
     const bool push2 = kt == 1 && !packed && !q && S >= 4 && pp.wmax > 0;
+    // pulls after a push skip the rows it left zero (seed tiles of 1 and 64)
+    const bool frontier = pp.wmax > 0 && (kt == 1 || kt == 64);
 
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     StepParams p;
@@ -212,13 +214,23 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             if (step == 1 && !q && !p.last) {
                 // one-hot restarts: x(1) lives on the seeds' out-edges; push it
                 if (push2) TPA_TRY(launch_push_first_plan(p, g, pp, st));
-                else TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, st));
+                else TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, frontier ? pp.bits : nullptr,
+                                               pp.nwords, st));
                 continue;
             }
             if (step == 2 && push2) {
                 TPA_TRY(launch_push_second(p, g, pp, st));
                 TPA_TRY(launch_gated_step(*s, p, pp, st));
                 continue;
+            }
+            // the step after a push gathers only the rows the push reached:
+            // step 3 after the pushed step 2 (when the device took the push),
+            // step 2 after a pushed step 1
+            p.bits = nullptr;
+            p.bits_on = nullptr;
+            if (frontier && !q && ((push2 && step == 3) || (!push2 && step == 2))) {
+                p.bits = pp.bits;
+                p.bits_on = push2 ? pp.flag : nullptr;
             }
             // one-hot restart: the first step needs no gather
             const bool first = step == 1 && !q;

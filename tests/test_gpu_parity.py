@@ -297,6 +297,29 @@ def test_second_step_push_weighted(tpa, torch):
     assert np.abs(res[0] - res[1]).max() <= 1e-6
 
 
+@pytest.mark.parametrize("kt,Sq", [(64, 5), (64, 3), (1, 3)])
+def test_frontier_skip_is_bitwise_neutral(rmat13, torch, kt, Sq):
+    """The pull after a pushed first step skips the rows the push left zero.
+    The skipped terms are exact zeros, so the results equal the unskipped
+    pull (push limit 0 turns the skip off) bit for bit, and match the
+    oracle."""
+    og, gg = rmat13
+    sd = seeds_for(og, 70 if kt == 64 else 6, 404)
+    seeds = torch.from_numpy(sd).cuda()
+    res = []
+    try:
+        gg.set_tuning(seed_tile=kt)
+        for limit in (-1, 0):
+            gg.set_push_limit(limit)
+            res.append(gg.query(seeds, c, Sq, T))
+    finally:
+        gg.set_push_limit(-1)
+        gg.set_tuning(0, 0)
+    assert torch.equal(res[0], res[1])
+    expect = np.stack([og.query(int(s), c, Sq, T) for s in sd])
+    assert np.all(l1_rows(res[0].cpu().numpy(), expect) <= TOL)
+
+
 # ---------------------------------------------------------------- gather layout
 @pytest.mark.parametrize("weighted", [False, True])
 def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
