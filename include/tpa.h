@@ -207,7 +207,7 @@ tpa_status tpa_query_graph_destroy(tpa_query_graph_t qg);
 
 /* Autotuner: times tpa_query on the caller's k seeds (device) for every
  * candidate seed tile (8..64, and 1 when k <= 4) and group edge budget
- * (128, 256, 512), keeps candidates whose first min(k, 8) outputs agree
+ * (128, 256, 512, and 1024 for seed tiles), keeps candidates whose first min(k, 8) outputs agree
  * with the single-vector path within L1 <= 1e-5 per seed, and stores the
  * fastest with tpa_set_tuning.  scratch_out is a float[k][n] device buffer
  * it may overwrite.  Outputs (host, nullable): best seed tile, edge budget,
@@ -223,8 +223,10 @@ tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
 
 /* Query tuning: seed-tile width kt (seeds per SpMM pass: 1, 2, 4, 8, 16,
  * 32 or 64; 0 = automatic) and the edge budget of a wave work item that
- * groups short rows (64..512, a multiple of 64; 0 = automatic; rows longer
- * than 8x the budget are split into chunks).  Applies to later calls. */
+ * groups short rows (64..1024, a multiple of 64; 0 = automatic, 512 for
+ * both the single vector and seed tiles; the single-vector step caps it at
+ * 512).  Longer rows are one wave item up to 2x (seed tiles) or 4x (single
+ * vector) the budget, then block items or chunks.  Applies to later calls. */
 tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item);
 tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
 

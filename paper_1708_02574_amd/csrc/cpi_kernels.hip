@@ -22,7 +22,7 @@
 //     long row's partials in chunk order and applies the epilogue.
 // Seed tile of 64 (kt == 64, one column per lane): the wave walks its
 //   item's edges in order with wave-uniform control; column ids are loaded
-//   64 at a time and broadcast with readlane, and 16 row gathers of 256 B
+//   64 at a time and broadcast with readlane, and 32 row gathers of 256 B
 //   (one per edge, contiguous across the lanes) are in flight at once.
 // Seed tiles of 2..32 (generic): lanes (sub, j) with 64/kt sub-groups add
 //   column j over every (64/kt)-th edge of a row; xor shuffles combine.
@@ -480,7 +480,7 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         seed_plain = p.seeds[lane];
         if (!WEIGHTED && seed_plain >= 0 && (int64_t)seed_plain < p.n) cinv_plain = p.c * p.inv[seed_plain];
     }
-    constexpr int U = 16;
+    constexpr int U = 32;  // row gathers in flight per wave
     const bool sparse = !FIRST && frontier_on(p);
     // the epilogue's per-row operands are loaded ahead, one row per lane, and
     // each lane's seed once: no memory round trip at a row boundary
@@ -920,7 +920,7 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (p.kt != 1 && p.kt != 2 && p.kt != 4 && p.kt != 8 && p.kt != 16 && p.kt != 32 && p.kt != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
-    if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
+    if (p.kt == 1 && s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
     if (p.kt != 1 && s.eb > s.el) return fail(TPA_ERR_INVALID_ARG, "block items need a single-column step");
     if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
         return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");

@@ -145,11 +145,12 @@ extern "C" tpa_status tpa_autotune(tpa_graph_t g, const int32_t *seeds, int64_t 
     for (int t : {8, 16, 32, 64})
         if (t <= 2 * k || t == 8) tiles.push_back(t);
     if (k == 1) tiles = {1};
-    const int ews[] = {128, 256, 512};
+    const int ews[] = {128, 256, 512, 1024};
     double best = 1e300;
     int bt = 0, be = 0;
     for (int t : tiles) {
         for (int ew : ews) {
+            if (t == 1 && ew > 512) continue;  // the single-vector step caps groups at 512 edges
             g->seed_tile = t;
             g->edges_per_item = ew;
             rc = run_query(g, seeds, nullptr, k, false, c, S, T, scratch_out, st, nullptr, 0);  // warm-up

@@ -45,7 +45,7 @@ void dfree(void *p) {
 namespace {
 
 constexpr int kDefaultEW1 = 512;   // group edge budget, single vector
-constexpr int kDefaultEW64 = 256;  // group edge budget, seed tiles
+constexpr int kDefaultEW64 = 512;  // group edge budget, seed tiles
 
 }  // namespace
 
@@ -67,7 +67,8 @@ int64_t stranger_last_iteration(double c, double eps) {
 // block items.
 SchedShape choose_shape(const tpa_graph *g, int kt) {
     if (kt == 1) {
-        const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW1;
+        // the single-vector step keeps a group's products in a 512-float LDS slice
+        const int ew = g->edges_per_item > 0 ? std::min(g->edges_per_item, kDefaultEW1) : kDefaultEW1;
         return {ew, 4 * ew, 16 * ew, 128 * ew};
     }
     const int ew = g->edges_per_item > 0 ? g->edges_per_item : kDefaultEW64;
@@ -350,8 +351,8 @@ extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per
     if (seed_tile != 0 && seed_tile != 1 && seed_tile != 2 && seed_tile != 4 && seed_tile != 8 &&
         seed_tile != 16 && seed_tile != 32 && seed_tile != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 0, 1, 2, 4, 8, 16, 32 or 64");
-    if (edges_per_item != 0 && (edges_per_item < 64 || edges_per_item > 512 || edges_per_item % 64))
-        return fail(TPA_ERR_INVALID_ARG, "edges per item must be 0 or a multiple of 64 in 64..512");
+    if (edges_per_item != 0 && (edges_per_item < 64 || edges_per_item > 1024 || edges_per_item % 64))
+        return fail(TPA_ERR_INVALID_ARG, "edges per item must be 0 or a multiple of 64 in 64..1024");
     g->seed_tile = seed_tile;
     g->edges_per_item = edges_per_item;
     return TPA_OK;

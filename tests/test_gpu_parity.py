@@ -138,8 +138,8 @@ def test_batched_queries(rmat13, torch, k, kt):
     assert np.all(l1_rows(R, expect) <= TOL)
 
 
-@pytest.mark.parametrize("ew", [64, 128, 512])
-@pytest.mark.parametrize("kt", [1, 4, 64])
+@pytest.mark.parametrize("ew", [64, 128, 512, 1024])
+@pytest.mark.parametrize("kt", [1, 4, 16, 64])
 def test_schedules_with_long_rows(rmat13, torch, ew, kt):
     """Small edges-per-item makes the hub rows of A~^T long (chunks + finish)."""
     og, gg = rmat13
@@ -153,7 +153,7 @@ def test_schedules_with_long_rows(rmat13, torch, ew, kt):
     assert np.all(l1_rows(R, expect) <= TOL)
 
 
-@pytest.mark.parametrize("ew,kt", [(64, 1), (512, 1), (64, 4), (128, 64)])
+@pytest.mark.parametrize("ew,kt", [(64, 1), (512, 1), (64, 4), (128, 64), (1024, 64), (1024, 1)])
 def test_hub_rows_blocks_and_chunks(tpa, torch, ew, kt):
     """A graph whose hub has 20000 in-edges: with small items it becomes a
     chunked row (finish pass); with the default single-vector shape it is a
