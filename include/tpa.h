@@ -174,8 +174,11 @@ tpa_status tpa_query_dense(tpa_graph_t g, const float *q, int64_t k, double c, i
  * exactly one).  Both CPI chains are differentiated: the family chain per
  * restart vector (x(0) = c q_j, S-1 steps) and the PageRank stranger chain
  * (x'(0) = c/n_g per block, K steps, its iterates checkpointed every
- * `checkpoint_every` steps and recomputed per segment; 0 = ceil(sqrt(K)),
- * negative = one segment).  Outputs (device, either may be NULL):
+ * `checkpoint_every` steps and recomputed per segment; negative = one
+ * segment, every iterate kept; 0 = automatic: every iterate kept when the
+ * K+1 vectors take at most a third of the free device memory, else
+ * checkpoints every ceil(sqrt(K)) steps).  Outputs (device, either may be
+ * NULL):
  *   grad_logits float[m], A~ order: dL/dtheta for row-softmax weights
  *               A~_uv = softmax_u(theta); with 1/outdeg weights it is the
  *               derivative at theta = 0;

@@ -57,6 +57,7 @@ struct AdjParams {
     int ncols = 1;
     int64_t n = 0;
     float *partials = nullptr;         // chunk partials [chunk items][kt]
+    const float *gT = nullptr;         // kt == 64: grad_out tile node-major [n][64]
 };
 
 __device__ __forceinline__ float g_of(const AdjParams &p, int64_t u, int j) {
@@ -234,6 +235,104 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_kt(const Item *__restrict
     }
 }
 
+// ------------------------------------------------------------ kt == 64
+// One wave per item, lane j = column j.  The item's edges are walked in
+// order, 64 column ids at a time, with 16 gathers of lambda(i) rows (256 B)
+// in flight.  The per-edge gradient terms sum_j (1-c) x_j(i-1)[u]
+// lambda_j(i)[v] of 16 edges are reduced through a 16 x 64 LDS tile (4
+// lanes per edge) and added to G with 16 neighbouring writes.  The row
+// operands (x(i-1) row, node-major loss-weight row) are fetched one row
+// ahead and 1/outdeg one row per lane, so a row boundary waits on nothing.
+constexpr int kAdjU = 16;
+constexpr int kAdjTile = 65;
+
+template <bool WEIGHTED, bool WITHG>
+__device__ __forceinline__ void adj_item_64(const AdjParams &p, const Item it, int64_t wid, int lane, float *tile) {
+    const int kind = (int)item_kind(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    const bool group = kind == (int)kItemGroup;
+    const bool chunk = kind == (int)kItemChunk;
+    const int nrows = group ? (int)item_nrows(it.meta) : 1;
+    const int64_t row0 = chunk ? (int64_t)p.longs[it.row0].row : (int64_t)it.row0;
+    const int rel = group ? (lane <= nrows ? (int)(p.rowptr[row0 + lane] - it.e0) : nnz) : (lane == 0 ? 0 : nnz);
+    const float inv_l = (!WEIGHTED && lane < nrows) ? p.inv[row0 + lane] : 0.0f;
+    int r = 0;
+    int rend = __builtin_amdgcn_readlane(rel, 1);
+    float xr = WITHG ? p.omc * p.xprev[row0 * 64 + lane] : 0.0f;
+    float gc = chunk ? 0.0f : p.gT[row0 * 64 + lane];
+    float xr_n = 0.0f, g_n = 0.0f;
+    if (nrows > 1) {
+        if (WITHG) xr_n = p.omc * p.xprev[(row0 + 1) * 64 + lane];
+        g_n = p.gT[(row0 + 1) * 64 + lane];
+    }
+    float acc = 0.0f;
+    auto close_row = [&]() {
+        if (chunk) {
+            p.partials[wid * 64 + lane] = acc;
+        } else {
+            const float sc = WEIGHTED ? acc : acc * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inv_l), r));
+            p.lam_out[(row0 + r) * 64 + lane] = fmaf(p.beta, gc, p.omc * sc);
+        }
+        acc = 0.0f;
+        ++r;
+        xr = xr_n;
+        gc = g_n;
+        if (r + 1 < nrows) {
+            if (WITHG) xr_n = p.omc * p.xprev[(row0 + r + 1) * 64 + lane];
+            g_n = p.gT[(row0 + r + 1) * 64 + lane];
+        }
+    };
+    const int ek = lane >> 2, part = lane & 3;  // tile reduction: 4 lanes per edge
+    for (int base = 0; base < nnz; base += 64) {
+        const int cnt = min(64, nnz - base);
+        const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
+        const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
+        for (int t0 = 0; t0 < cnt; t0 += kAdjU) {
+            float l[kAdjU];
+#pragma unroll
+            for (int k = 0; k < kAdjU; ++k) {
+                const int32_t v = __builtin_amdgcn_readlane(colv, t0 + k);
+                l[k] = p.lam_in[(int64_t)v * 64 + lane];
+            }
+#pragma unroll
+            for (int k = 0; k < kAdjU; ++k) {
+                if (t0 + k < cnt) {
+                    const int e = base + t0 + k;
+                    while (e >= rend) {
+                        close_row();
+                        rend = __builtin_amdgcn_readlane(rel, r + 1);
+                    }
+                    const float wk =
+                        WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 1.0f;
+                    acc += WEIGHTED ? wk * l[k] : l[k];
+                    if (WITHG) tile[k * kAdjTile + lane] = xr * l[k];
+                }
+            }
+            if (WITHG) {
+                wave_sync();
+                float d = 0.0f;
+#pragma unroll
+                for (int c2 = 0; c2 < 16; ++c2) d += tile[ek * kAdjTile + part * 16 + c2];
+                d += __shfl_xor(d, 1, 64);
+                d += __shfl_xor(d, 2, 64);
+                if (part == 0 && t0 + ek < cnt) p.G[it.e0 + base + t0 + ek] += d;
+                wave_sync();
+            }
+        }
+    }
+    while (r < nrows) close_row();
+}
+
+template <bool WEIGHTED, bool WITHG>
+__global__ __launch_bounds__(kThreads) void adj_kernel_64(const Item *__restrict__ items, int64_t n_items,
+                                                          AdjParams p) {
+    __shared__ float tile[kWaves][kAdjU * kAdjTile];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items) return;
+    adj_item_64<WEIGHTED, WITHG>(p, items[wid], wid, lane, tile[wv]);
+}
+
 __global__ __launch_bounds__(kThreads) void adj_finish_kernel(const LongRow *__restrict__ longs, int64_t n_long,
                                                               AdjParams p) {
     const int lane = threadIdx.x & 63;
@@ -264,32 +363,56 @@ __global__ void gsum_kernel(const float *grad_out, int64_t k, int64_t n, float *
     }
 }
 
-// lambda(N) tile: lam[v][j] = beta * g(v, j)
+// lambda(N) tile: lam[v][j] = beta * g(v, j), and, when p.gT is set, the
+// node-major copy gT[v][j] = g(v, j).  One block per 64 nodes; for seed
+// tiles the seed-major g is transposed through LDS so that both the reads
+// (along v) and the writes (along j) are coalesced.
 __global__ void lam_init_kernel(AdjParams p, float *lam) {
-    const int64_t total = p.n * (int64_t)p.kt;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t v = i / p.kt;
-        const int j = (int)(i - v * p.kt);
-        lam[i] = p.beta * g_of(p, v, j);
+    __shared__ float tile[64][65];
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int kt = p.kt;
+    if (kt == 1) {
+        for (int i = threadIdx.x; i < 64; i += blockDim.x)
+            if (v0 + i < p.n) lam[v0 + i] = p.beta * p.gvec[v0 + i];
+        return;
+    }
+    for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
+        const int j = i / 64, vv = i % 64;
+        tile[vv][j] = (j < p.ncols && v0 + vv < p.n) ? p.gvec[(int64_t)j * p.g_stride + v0 + vv] : 0.0f;
+    }
+    __syncthreads();
+    float *gT = const_cast<float *>(p.gT);
+    for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
+        const int vv = i / kt, j = i % kt;
+        if (v0 + vv < p.n) {
+            lam[(v0 + vv) * kt + j] = p.beta * tile[vv][j];
+            if (gT) gT[(v0 + vv) * kt + j] = tile[vv][j];
+        }
     }
 }
 
-// grad_q[col0 + j][v] = c * lambda(0)[v][j]
+// grad_q[col0 + j][v] = c * lambda(0)[v][j], transposed through LDS (one
+// block per 64 nodes).
 __global__ void gradq_kernel(const float *lam, int64_t n, int kt, int ncols, float c, int64_t col0, float *gq) {
-    const int64_t total = n * (int64_t)ncols;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int j = (int)(i / n);
-        const int64_t v = i - (int64_t)j * n;
-        gq[(col0 + j) * n + v] = c * lam[v * kt + j];
+    __shared__ float tile[64][65];
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
+        const int vv = i / kt, j = i % kt;
+        tile[vv][j] = v0 + vv < n ? lam[(v0 + vv) * kt + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * ncols; i += blockDim.x) {
+        const int j = i / 64, vv = i % 64;
+        if (v0 + vv < n) gq[(col0 + j) * n + v0 + vv] = c * tile[vv][j];
     }
 }
 
-// z = x (explicit weights) or x / outdeg (uniform)
-__global__ void scale_kernel(const float *x, const float *inv, int use_inv, int64_t n, float *z) {
+// z = x (explicit weights) or x / outdeg (uniform), at row zperm[v] of the
+// gather layout when zperm is set
+__global__ void scale_kernel(const float *x, const float *inv, int use_inv, int64_t n, const int32_t *zperm,
+                             float *z) {
     for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
-        z[v] = use_inv ? x[v] * inv[v] : x[v];
+        z[zperm ? zperm[v] : v] = use_inv ? x[v] * inv[v] : x[v];
 }
 
 // Row softmax backward, in place on G: waves stride over the rows of A~.
@@ -335,7 +458,10 @@ void launch_adj_kt(const Schedule &s, const AdjParams &p, hipStream_t st) {
         case 8: TPA_ADJ_CASE(8) break;
         case 16: TPA_ADJ_CASE(16) break;
         case 32: TPA_ADJ_CASE(32) break;
-        case 64: TPA_ADJ_CASE(64) break;
+        case 64:
+            if (w) adj_kernel_64<true, WG><<<grid, kThreads, 0, st>>>(it, ni, p);
+            else adj_kernel_64<false, WG><<<grid, kThreads, 0, st>>>(it, ni, p);
+            break;
         default: break;
     }
 #undef TPA_ADJ_CASE
@@ -389,6 +515,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     if (!grad_logits && !grad_q) return TPA_OK;
     if (packed && (!seeds || !g->node_block)) return fail(TPA_ERR_INVALID_ARG, "packed needs seeds and a packed graph");
     const int64_t n = g->n, m = g->m, K = g->K;
+    // forward recomputation in the gather layout of the query path
+    const bool hub = g->gather_layout && g->zperm && !g->weighted;
     const float omc = (float)(1.0 - c);
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     const float alpha = (float)((1.0 - pT) / (1.0 - pS));
@@ -404,7 +532,14 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
         // ---- stranger chain, checkpointed ----
         int64_t C = checkpoint_every;
-        if (C == 0) C = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)K)));
+        if (C == 0) {
+            // automatic: keep every iterate (no recomputation) when they take at
+            // most a third of the free device memory, else every ceil(sqrt(K))
+            size_t free_b = 0, total_b = 0;
+            const bool fits = hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+                              (double)(K + 1) * (double)n * sizeof(float) <= (double)free_b / 3.0;
+            C = fits ? K : std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)K)));
+        }
         if (C < 0 || C > K) C = K;
         const int64_t nck = (K + C - 1) / C;
         float *gs, *ck, *seg, *z0, *z1, *lam0, *lam1, *comp, *part_f, *part_a;
@@ -420,10 +555,11 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         // forward pass: checkpoints x'(0), x'(C), ...
-        TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, nullptr, st));
         StepParams fp;
+        fp.zperm = hub ? g->zperm : nullptr;
+        TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, fp.zperm, st));
         fp.rowptr = g->t.rowptr;
-        fp.col = g->t.col;
+        fp.col = hub ? g->t_colz : g->t.col;
         fp.w = g->weighted ? g->t.w : nullptr;
         fp.inv = g->inv_deg;
         fp.partials = part_f;
@@ -455,14 +591,14 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         ap.n = n;
         ap.partials = part_a;
         ap.beta = (K >= T) ? 1.0f : 0.0f;
-        lam_init_kernel<<<grid_1d(n), 256, 0, st>>>(ap, lam0);
+        lam_init_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(ap, lam0);
         float *lc = lam0, *ln = lam1;
         for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
             const int64_t lo = sgi * C, hi = std::min<int64_t>(lo + C, K);
             // recompute x'(lo+1 .. hi-1) into seg[1..]; seg slot 0 is the checkpoint
             float *x_lo = ck + (size_t)sgi * n;
             if (hi - lo > 1) {
-                scale_kernel<<<grid_1d(n), 256, 0, st>>>(x_lo, g->inv_deg, g->weighted ? 0 : 1, n, z0);
+                scale_kernel<<<grid_1d(n), 256, 0, st>>>(x_lo, g->inv_deg, g->weighted ? 0 : 1, n, fp.zperm, z0);
                 float *a = z0, *b = z1;
                 for (int64_t i = lo + 1; i < hi; ++i) {
                     fp.zin = a;
@@ -491,8 +627,9 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &sfk, false));
     TPA_TRY(get_schedule(g, adj_shape_k, st, &sak, true));
     const int nit = std::max(S - 1, 1);  // stored iterates x(0..S-2)
-    float *xf, *z0, *z1, *lam0, *lam1, *part_f, *part_a;
+    float *xf, *z0, *z1, *lam0, *lam1, *part_f, *part_a, *gT = nullptr;
     TPA_TRY(sc.get(&xf, (size_t)nit * n * kt, st));
+    if (kt == 64) TPA_TRY(sc.get(&gT, (size_t)n * kt, st));
     TPA_TRY(sc.get(&z0, (size_t)n * kt, st));
     TPA_TRY(sc.get(&z1, (size_t)n * kt, st));
     TPA_TRY(sc.get(&lam0, (size_t)n * kt, st));
@@ -501,7 +638,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(sc.get(&part_a, (size_t)sak->n_chunk_items * kt, st));
     StepParams fp;
     fp.rowptr = g->t.rowptr;
-    fp.col = g->t.col;
+    fp.zperm = hub ? g->zperm : nullptr;
     fp.w = g->weighted ? g->t.w : nullptr;
     fp.inv = g->inv_deg;
     fp.partials = part_f;
@@ -519,6 +656,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     ap.longs = sak->longs;
     ap.G = grad_logits;
     ap.g_stride = n;
+    ap.gT = gT;
     ap.omc = omc;
     ap.kt = kt;
     ap.n = n;
@@ -539,13 +677,14 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             fp.zin = zc;
             fp.zout = zn;
             fp.xs_out = xf + (size_t)i * n * kt;
+            fp.col = (i == 1 && !q) ? g->t.col : (hub ? g->t_colz : g->t.col);  // first steps read node ids
             TPA_TRY(launch_step(*sfk, kPlain, i == 1 && !q, fp, st));
             std::swap(zc, zn);
         }
         ap.gvec = grad_out + base * n;
         ap.ncols = ncols;
         ap.beta = alpha;
-        lam_init_kernel<<<grid_1d(n * kt), 256, 0, st>>>(ap, lam0);
+        lam_init_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(ap, lam0);
         float *lc = lam0, *ln = lam1;
         for (int i = S - 1; i >= 1; --i) {
             ap.xprev = grad_logits ? xf + (size_t)(i - 1) * n * kt : nullptr;
@@ -556,7 +695,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             TPA_TRY(adj_step(*sak, ap, st));
             std::swap(lc, ln);
         }
-        if (grad_q) gradq_kernel<<<grid_1d(n * ncols), 256, 0, st>>>(lc, n, kt, ncols, (float)c, base, grad_q);
+        if (grad_q) gradq_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(lc, n, kt, ncols, (float)c, base, grad_q);
     }
     if (grad_logits) {
         const unsigned sgrid = (unsigned)std::min<int64_t>((n * 64 + 255) / 256, 1 << 20);
