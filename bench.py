@@ -108,8 +108,8 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
     torch.cuda.synchronize()
     g.set_tuning(seed_tile=0)
     return {"accuracy": acc, "adjoint": {"seeds": ka, "ms": round(a.elapsed_time(b), 3),
-                                         "note": "gradients w.r.t. edge weights and restart vectors, "
-                                                 "stranger chain recomputed from checkpoints"}}
+                                         "note": "gradients w.r.t. edge logits and restart vectors "
+                                                 "(both CPI chains, 64-seed tile)"}}
 
 
 def main():
