@@ -61,10 +61,11 @@ struct StepParams {
 // (kt == 1).  The frontier of step 2 is F = out(s) + {s} (s appended when
 // it has no self-loop); y1f holds y1 on F as gathered values, offs[f] the
 // exclusive prefix sum of outdeg over F, so the push touches W = offs[|F|]
-// edges of A~.  acc holds y2's pulled sums as fixed point (2^62 units) and
+// edges of A~.  acc holds y2 in gathered form (scaled by 1/outdeg for
+// uniform weights), indexed by gather row, as fixed point (2^62 units); it
 // is all zero between queries.
 struct PushPlan {
-    unsigned long long *acc = nullptr;  // [n], zero between queries
+    unsigned long long *acc = nullptr;  // [n] by gather row, zero between queries
     uint32_t *bits = nullptr;           // [ceil(n/32)]: rows of the pushed vector that may be non-zero
     int64_t nwords = 0;
     int64_t *offs = nullptr;            // [max_outdeg + 2]
@@ -108,10 +109,11 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // Second family step of a single seed pushed over the out-edges of F when
-// the plan's flag is set: the pulled sums of y2 = c e_s + (1-c) A~^T y1
+// the plan's flag is set: the terms of (1-c) A~^T y1, in gathered form,
 // accumulated in fixed point (order-independent, so bitwise reproducible)
-// into acc, and the rows of y2 that may be non-zero marked in bits (which
-// the plan's second launch cleared).  With the flag clear it returns at once.
+// into acc, which the plan seeded with the restart term c e_s; the rows of
+// y2 that may be non-zero are marked in bits (which the plan's second
+// launch cleared).  With the flag clear it returns at once.
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // The second family step proper (p.zin = dense y1, p.zout = y2 as the next

@@ -214,14 +214,13 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
     finish_row<MODE>(p, longs[wid], lane);
 }
 
-// Row v of the pushed second step: y2 = c [v == s] + (1-c) acc[v] 2^-62,
-// stored as the next gathered vector; acc[v] is cleared for the next query.
-__device__ __forceinline__ void push_convert_row(const StepParams &p, const PushPlan &pp, int64_t v, int32_t s) {
-    const unsigned long long a = pp.acc[v];
-    const float sum = (float)((double)a * 0x1p-62);
-    const float y = fmaf(p.omc, sum, v == (int64_t)s ? p.c : 0.0f);
-    p.zout[zrow(p, v)] = p.w ? y : y * p.inv[v];
-    if (a) pp.acc[v] = 0ull;
+// Gather row r of the pushed second step: acc[r] holds the row's gathered
+// value (y2 scaled by 1/outdeg for uniform weights) in 2^62 fixed point, the
+// restart term included; it is cleared for the next query.
+__device__ __forceinline__ void push_convert_row(const StepParams &p, const PushPlan &pp, int64_t r) {
+    const unsigned long long a = pp.acc[r];
+    p.zout[r] = (float)((double)a * 0x1p-62);
+    if (a) pp.acc[r] = 0ull;
 }
 
 // ------------------------------------------------------------ kt == 1
@@ -377,30 +376,31 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     item_1<MODE, FIRST, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
-// The pulled second family step of a single seed, gated by the push plan's
-// flag: when the step was pushed, each item instead converts its rows from
-// the fixed-point sums (chunked rows are left to the finish launch).  Blocks
-// stride over 4-item slots (one slot each at the launch's grid); block items
-// fill whole slots, so all 4 waves of a block meet the same barriers.
+// The second family step of a single seed, gated by the push plan's flag:
+// when the step was pushed, the launch converts the fixed-point sums of
+// every gather row; otherwise it pulls the step over A~^T.  Blocks stride
+// over 4-item slots (one slot each at the launch's grid); block items fill
+// whole slots, so all 4 waves of a block meet the same barriers.
 
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__restrict__ items, int64_t n_items,
                                                                 StepParams p, PushPlan pp) {
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool pushed = *pp.flag != 0;
+    if (*pp.flag) {
+        // pushed: convert every gather row, coalesced, no work items
+        for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.n;
+             r += (int64_t)gridDim.x * blockDim.x)
+            push_convert_row(p, pp, r);
+        return;
+    }
     const int64_t slots = (n_items + kWaves - 1) / kWaves;
     for (int64_t b = blockIdx.x; b < slots; b += gridDim.x) {
         const int64_t wid = b * kWaves + wv;
         if (wid >= n_items) continue;  // only in the last slot, which holds no block item
         const Item it = items[wid];
         const int kind = (int)item_kind(it.meta);
-        if (pushed) {
-            const int cnt = kind == (int)kItemGroup ? (int)item_nrows(it.meta)
-                            : kind == (int)kItemRow ? 1
-                            : (kind == (int)kItemBlock && wv == 0) ? 1 : 0;
-            if (lane < cnt) push_convert_row(p, pp, it.row0 + lane, p.seeds[0]);
-        } else if (kind == (int)kItemBlock) {
+        if (kind == (int)kItemBlock) {
             block_row_1<kFamily, false, WEIGHTED>(p, it, lane, wv, lds);
             __syncthreads();  // wave 0 has read the quarter sums before the slot is reused
         } else {
@@ -414,12 +414,8 @@ __global__ __launch_bounds__(kThreads) void gated_finish_kernel(const LongRow *_
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (wid >= n_long) return;
-    const LongRow lr = longs[wid];
-    if (*pp.flag) {
-        if (lane == 0) push_convert_row(p, pp, lr.row, p.seeds[0]);
-        return;
-    }
-    finish_row<kFamily>(p, lr, lane);
+    if (*pp.flag) return;  // the step launch converted every row
+    finish_row<kFamily>(p, longs[wid], lane);
 }
 
 // ------------------------------------------------------------ kt == 64
@@ -783,7 +779,10 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
     if (lane == 0) {
         pp.ctrl[0] = run;
         pp.ctrl[1] = nf;
-        *pp.flag = run <= pp.wmax ? 1 : 0;
+        const bool push = run <= pp.wmax;
+        *pp.flag = push ? 1 : 0;
+        // the restart term of y2 (acc is all zero between queries)
+        if (push) pp.acc[zrow(p, s)] = __double2ull_rn((double)(a_w ? p.c : p.c * p.inv[s]) * 0x1p62);
     }
 }
 
@@ -822,8 +821,9 @@ constexpr int kPushLdsOffs = 2048;  // frontier offsets searched in LDS up to th
 
 // Second family step pushed from F: thread t takes edge slots t, t + T, ...
 // (T threads), finds its frontier node by binary search over offs and adds
-// its term to acc[v] in 2^62 fixed point.  Every term is in [0, 1] and the
-// terms add up to (1-c)-weighted mass below 1, so the sum cannot overflow.
+// its term, already in gathered form, to acc[zrow(v)] in 2^62 fixed point.
+// Every term is in [0, 1] and the terms add up to at most the mass of y2,
+// below 1, so the sum cannot overflow.
 __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const int64_t *a_rowptr,
                                                           const int32_t *a_col, const float *a_w, PushPlan pp) {
     __shared__ long long soffs[kPushLdsOffs + 1];
@@ -854,8 +854,11 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
         const int64_t e = a_rowptr[u] + (t - olo);
         const int32_t v = a_col[e];
         const float zu = pp.y1f[lo];
-        const float term = a_w ? zu * a_w[e] : zu;
-        if (atomicAdd(&pp.acc[v], __double2ull_rn((double)term * 0x1p62)) == 0ull) mark_row(pp.bits, zrow(p, v));
+        // (1-c) x1 term of row v, as its gathered value (times 1/outdeg(v)
+        // for uniform weights)
+        const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
+        const int64_t zr = zrow(p, v);
+        if (atomicAdd(&pp.acc[zr], __double2ull_rn((double)term * 0x1p62)) == 0ull) mark_row(pp.bits, zr);
     }
 }
 
