@@ -320,6 +320,8 @@ tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStrea
         dfree(flag);
         dfree(pos);
         dfree(sorted);
+    } else {
+        dfree(keys);  // no edges: only the dangling self-loops below
     }
     // out-degrees, dangling self-loops, A~ row offsets
     int32_t *deg = nullptr;
