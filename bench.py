@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 WORKLOAD = "rmat20"
 PROFILE_PERIOD = 16
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_1_family_rmat20_traffic.json")
+TRAFFIC_FILE_64 = os.path.join(ROOT, "profiles", "step_kernel_64_family_rmat20_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1708_02574_amd", "csrc", "cpi_kernels.hip")
 
 
@@ -49,11 +50,18 @@ def algorithmic_bytes_family_step(n: int, m: int) -> int:
     return 4 * m + 8 * (n + 1) + 12 * n
 
 
-def traffic_from_profile(n_launch_bytes: int):
+def algorithmic_bytes_tile_step(n: int, m: int, kt: int = 64) -> int:
+    """Compulsory HBM bytes of one family CPI step over a seed tile of kt
+    columns (node-major): column ids 4m, row offsets 8(n+1), the gathered
+    tile read once 4kt n, 1/outdeg 4n, the next tile written 4kt n."""
+    return 4 * m + 8 * (n + 1) + (8 * kt + 4) * n
+
+
+def traffic_from_profile(path: str = TRAFFIC_FILE):
     """HBM bytes per launch from the committed PMC summary, or None when it
     is missing or was taken on a different version of the kernel source."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
@@ -196,6 +204,7 @@ def main():
     ms_step = total_ms / args.steps
     code = tpa.profile_code(1, 0, False, False)
     launches, kms = tpa.profile_read(code)
+    launches64, kms64 = tpa.profile_read(tpa.profile_code(64, 0, False, False))
     tpa.profile_enable(False)
 
     # sanity: every r_TPA has mass 1 - (1-c)^(K+1) (Lemma 2 + closed-form K)
@@ -213,7 +222,11 @@ def main():
     avg_launch_ms = kms / max(launches, 1)
     alg = algorithmic_bytes_family_step(n, m)
     achieved = alg / (avg_launch_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(alg)
+    traffic = traffic_from_profile(TRAFFIC_FILE)
+    avg64_ms = kms64 / max(launches64, 1)
+    alg64 = algorithmic_bytes_tile_step(n, m)
+    achieved64 = alg64 / (avg64_ms * 1e-3) / 1e9 if launches64 else 0.0
+    traffic64 = traffic_from_profile(TRAFFIC_FILE_64)
 
     rec = {
         "metric": "TPA query GTEPS & seeds/s, batched vs 1-seed, at L1 <=1e-5 vs FP64 oracle",
@@ -253,6 +266,19 @@ def main():
             "algorithmic_bytes_per_launch": alg,
             "avg_launch_us": round(avg_launch_ms * 1e3, 2),
             "launches_timed": launches,
+        },
+        "roofline_batched": {
+            "kernel": "step_kernel_64<family, non-first, 1/outdeg> (64-seed tile CPI step)",
+            "bound": "hbm",
+            "achieved": round(achieved64, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved64 / HBM_PEAK_GBS, 4),
+            "traffic": traffic64,
+            "traffic_GBps": round(traffic64 / (avg64_ms * 1e-3) / 1e9, 1) if traffic64 and launches64 else None,
+            "algorithmic_bytes_per_launch": alg64,
+            "avg_launch_us": round(avg64_ms * 1e3, 2),
+            "launches_timed": launches64,
         },
         "checks": {"mass_max_err": mass_err, "plain_vs_batched_max_abs": max_diff},
     }
