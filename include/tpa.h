@@ -305,7 +305,9 @@ tpa_status tpa_topk(const float *vals, int64_t rows, int64_t n, int k, int32_t *
 
 /* Per-row L1 distance out[r] = sum_v |a x[r][v] - y[r][v]| (row-major
  * [rows][n] FP32 inputs, double[rows] output), summed in FP64 in a fixed
- * order.  Errors: INVALID_ARG (negative sizes, NULL), INDEX_OVERFLOW, HIP. */
+ * order (deterministic).  Synchronous (it frees a scratch buffer).
+ * Errors: INVALID_ARG (negative sizes, NULL), INDEX_OVERFLOW (more than
+ * 65535 rows), OOM, HIP. */
 tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, int64_t n, double a, double *out,
                       hipStream_t stream);
 

@@ -47,12 +47,18 @@ __global__ void l1_norm_kernel(const float *q, int64_t n, double *out) {
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// One block per row: sum_v |a x[v] - y[v]| in FP64 with a fixed-order tree.
-__global__ void row_l1_scaled_kernel(const float *x, const float *y, int64_t n, double a, double *out) {
+// Per-row L1 distance in two fixed-order passes: block (row, b) of a
+// [rows x kL1Parts] grid reduces part b of the row into part[row][b]; then
+// one thread per row adds its parts in order.  Deterministic for a given n.
+constexpr int kL1Parts = 64;
+
+__global__ void row_l1_parts_kernel(const float *x, const float *y, int64_t n, double a, double *part) {
     __shared__ double red[256];
-    const int64_t row = blockIdx.x;
+    const int64_t row = blockIdx.y;
+    const int64_t per = (n + kL1Parts - 1) / kL1Parts;
+    const int64_t b0 = (int64_t)blockIdx.x * per, b1 = min(n, b0 + per);
     double s = 0.0;
-    for (int64_t v = threadIdx.x; v < n; v += blockDim.x)
+    for (int64_t v = b0 + threadIdx.x; v < b1; v += blockDim.x)
         s += fabs(a * (double)x[row * n + v] - (double)y[row * n + v]);
     red[threadIdx.x] = s;
     __syncthreads();
@@ -60,7 +66,15 @@ __global__ void row_l1_scaled_kernel(const float *x, const float *y, int64_t n, 
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[row] = red[0];
+    if (threadIdx.x == 0) part[row * kL1Parts + blockIdx.x] = red[0];
+}
+
+__global__ void row_l1_sum_kernel(const double *part, int64_t rows, double *out) {
+    const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    double s = 0.0;
+    for (int b = 0; b < kL1Parts; ++b) s += part[row * kL1Parts + b];
+    out[row] = s;
 }
 
 // ------------------------------------------------------------------ top-k
@@ -74,6 +88,22 @@ __device__ __forceinline__ uint32_t order_key(float f) {
 
 constexpr int kTopkThreads = 1024;
 constexpr int kTopkMax = 1024;
+
+// hist[bin] += 1 for every active lane.  Lanes of a wave that share a bin
+// (common in the top digits, where most values share an exponent) are
+// counted with one atomic; after four shared bins the rest add one by one.
+__device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin, bool active) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(active);
+    for (int it = 0; it < 4 && pending; ++it) {
+        const int leader = __builtin_ctzll(pending);
+        const uint32_t b = __builtin_amdgcn_readlane(bin, leader);
+        const uint64_t same = __ballot(active && bin == b) & pending;
+        if (lane == leader) atomicAdd(&hist[b], (uint32_t)__popcll(same));
+        pending &= ~same;
+    }
+    if ((pending >> lane) & 1ull) atomicAdd(&hist[bin], 1u);
+}
 
 // One block per row.  A most-significant-digit-first radix select (four 8-bit
 // digits) finds the key K of the k-th largest entry; the entries above K are
@@ -100,9 +130,19 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
         for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
         const uint32_t prefix = s_prefix;
-        for (int64_t v = tid; v < n; v += blockDim.x) {
-            const uint32_t key = order_key(row[v]);
-            if ((key & mask_hi) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        constexpr int UL = 8;  // loads in flight per thread
+        for (int64_t base = 0; base < n; base += (int64_t)blockDim.x * UL) {  // same trip count in every lane
+            uint32_t key[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int64_t v = base + (int64_t)u * blockDim.x + tid;
+                key[u] = v < n ? order_key(row[v]) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int64_t v = base + (int64_t)u * blockDim.x + tid;
+                hist_add(hist, (key[u] >> shift) & 255u, v < n && (key[u] & mask_hi) == prefix);
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -122,38 +162,52 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
     if (tid == 0) s_count = 0u;
     __syncthreads();
     // entries above K (fewer than k of them), in any order
-    for (int64_t v = tid; v < n; v += blockDim.x) {
-        const uint32_t key = order_key(row[v]);
-        if (key > K) {
-            const uint32_t pos = atomicAdd(&s_count, 1u);
-            skey[pos] = key;
-            sidx[pos] = (int32_t)v;
+    {
+        constexpr int UL = 8;
+        for (int64_t base = 0; base < n; base += (int64_t)blockDim.x * UL) {
+            uint32_t key[UL];
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int64_t v = base + (int64_t)u * blockDim.x + tid;
+                key[u] = v < n ? order_key(row[v]) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < UL; ++u) {
+                const int64_t v = base + (int64_t)u * blockDim.x + tid;
+                if (v < n && key[u] > K) {
+                    const uint32_t pos = atomicAdd(&s_count, 1u);
+                    skey[pos] = key[u];
+                    sidx[pos] = (int32_t)v;
+                }
+            }
         }
     }
     __syncthreads();
     const uint32_t above = s_count;
-    // entries equal to K, in index order, block-wide ordered compaction
-    uint32_t taken = 0u;
-    for (int64_t base = 0; base < n && taken < take_eq; base += blockDim.x) {
-        const int64_t v = base + tid;
-        const uint32_t f = (v < n && order_key(row[v]) == K) ? 1u : 0u;
-        scan[tid] = f;
+    // entries equal to K, the take_eq with the lowest indices: thread t owns
+    // the contiguous segment [t*seg, (t+1)*seg), counts its equal entries,
+    // and one block scan of the counts gives each segment its first rank
+    const int64_t seg = (n + blockDim.x - 1) / blockDim.x;
+    const int64_t s0 = (int64_t)tid * seg, s1 = min(n, s0 + seg);
+    uint32_t mine = 0u;
+    for (int64_t v = s0; v < s1; ++v) mine += order_key(row[v]) == K ? 1u : 0u;
+    scan[tid] = mine;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const uint32_t t = tid >= off ? scan[tid - off] : 0u;
         __syncthreads();
-        for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-            const uint32_t t = tid >= off ? scan[tid - off] : 0u;
-            __syncthreads();
-            scan[tid] += t;
-            __syncthreads();
-        }
-        const uint32_t incl = scan[tid];
-        const uint32_t total = scan[blockDim.x - 1];
-        if (f && taken + incl <= take_eq) {
-            skey[above + taken + incl - 1] = K;
-            sidx[above + taken + incl - 1] = (int32_t)v;
-        }
+        scan[tid] += t;
         __syncthreads();
-        taken += total;
     }
+    uint32_t rank = scan[tid] - mine;  // equal entries before this segment
+    for (int64_t v = s0; v < s1 && rank < take_eq; ++v) {
+        if (order_key(row[v]) == K) {
+            skey[above + rank] = K;
+            sidx[above + rank] = (int32_t)v;
+            ++rank;
+        }
+    }
+    __syncthreads();
     // bitonic sort of the k pairs (padded to a power of two)
     int p2 = 1;
     while (p2 < k) p2 <<= 1;
@@ -280,8 +334,16 @@ extern "C" tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, i
     if (rows < 0 || n < 0) return fail(TPA_ERR_INVALID_ARG, "negative size");
     if (rows == 0) return TPA_OK;
     if (!x || !y || !out) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
-    if (rows > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many rows for one launch");
-    row_l1_scaled_kernel<<<(unsigned)rows, 256, 0, st>>>(x, y, n, a, out);
-    TPA_TRY_HIP(hipGetLastError());
+    if (rows > 65535) return fail(TPA_ERR_INDEX_OVERFLOW, "at most 65535 rows per call");
+    double *part = nullptr;
+    TPA_TRY(dalloc(&part, (size_t)rows * kL1Parts, st));
+    row_l1_parts_kernel<<<dim3(kL1Parts, (unsigned)rows), 256, 0, st>>>(x, y, n, a, part);
+    row_l1_sum_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(part, rows, out);
+    const hipError_t e = hipGetLastError();
+    // the buffer is freed after the kernels that use it have run
+    const hipError_t e2 = hipStreamSynchronize(st);
+    dfree(part);
+    TPA_TRY_HIP(e);
+    TPA_TRY_HIP(e2);
     return TPA_OK;
 }
