@@ -103,17 +103,17 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
                              int64_t nwords, hipStream_t st);
 
 // Single seed (kt == 1, unpacked): the first step kept compact on F (y1f)
-// with the plan of the second step (offs, W, |F|, flag = W <= wmax); when
-// the flag is clear, a second launch also writes y1 densely to p.zout for
-// the pulled second step.
+// with the plan of the second step (offs, W, |F|, flag = W <= wmax), in one
+// launch whose other blocks clear the frontier bitmap.
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // Second family step of a single seed pushed over the out-edges of F when
 // the plan's flag is set: the terms of (1-c) A~^T y1, in gathered form,
 // accumulated in fixed point (order-independent, so bitwise reproducible)
 // into acc, which the plan seeded with the restart term c e_s; the rows of
-// y2 that may be non-zero are marked in bits (which the plan's second
-// launch cleared).  With the flag clear it returns at once.
+// y2 that may be non-zero are marked in bits (which the plan's launch
+// cleared).  With the flag clear it writes y1 densely to p.zin instead, for
+// the pulled second step.
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // The second family step proper (p.zin = dense y1, p.zout = y2 as the next

@@ -728,14 +728,22 @@ __device__ __forceinline__ long long wave_scan_incl(long long x, int lane) {
     return x;
 }
 
-// The first family step of one seed (one wave), kept compact: F = out(s) +
-// {s} (s appended when it has no self-loop), y1f[f] = y1 of F's f-th node
-// as a gathered value, and the second step's plan: offs = exclusive prefix
-// sums of outdeg over F, ctrl = {W, |F|}, flag = (W <= wmax).  An invalid
-// seed gives an empty plan with the flag clear.
-__global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col,
-                                       const float *a_w, PushPlan pp) {
+// The first family step of one seed (block 0, one wave), kept compact: F =
+// out(s) + {s} (s appended when it has no self-loop), y1f[f] = y1 of F's
+// f-th node as a gathered value, and the second step's plan: offs =
+// exclusive prefix sums of outdeg over F, ctrl = {W, |F|}, flag =
+// (W <= wmax).  An invalid seed gives an empty plan with the flag clear.
+// The launch's other blocks clear the frontier bitmap.
+__global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr,
+                                                             const int32_t *a_col, const float *a_w, PushPlan pp) {
     const int lane = threadIdx.x & 63;
+    if (blockIdx.x > 0) {
+        // the other blocks clear the frontier bitmap for the second step
+        for (int64_t i = (blockIdx.x - 1) * (int64_t)blockDim.x + threadIdx.x; i < pp.nwords;
+             i += (int64_t)(gridDim.x - 1) * blockDim.x)
+            pp.bits[i] = 0u;
+        return;
+    }
     const int32_t s = p.seeds[0];
     if (s < 0 || (int64_t)s >= p.n) {
         if (lane == 0) {
@@ -786,37 +794,6 @@ __global__ void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr, co
     }
 }
 
-// Flag set: clear the frontier bitmap for the pushed second step.  Flag
-// clear: dense y1 (as the gathered vector p.zout) for a second step that is
-// pulled: entry v is y1f at v's position in the seed's sorted out-neighbour
-// list, the appended seed entry, or zero.
-__global__ void push_first_dense_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, PushPlan pp) {
-    if (*pp.flag) {
-        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pp.nwords;
-             i += (int64_t)gridDim.x * blockDim.x)
-            pp.bits[i] = 0u;
-        return;
-    }
-    const int32_t s = p.seeds[0];
-    const bool valid = s >= 0 && (int64_t)s < p.n;
-    const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
-    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
-         v += (int64_t)gridDim.x * blockDim.x) {
-        float val = 0.0f;
-        if (valid) {
-            int64_t lo = e0, hi = e1;  // first edge with a_col >= v
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (a_col[mid] < v) lo = mid + 1;
-                else hi = mid;
-            }
-            if (lo < e1 && a_col[lo] == v) val = pp.y1f[lo - e0];
-            else if (v == (int64_t)s) val = pp.y1f[e1 - e0];
-        }
-        p.zout[zrow(p, v)] = val;
-    }
-}
-
 constexpr int kPushLdsOffs = 2048;  // frontier offsets searched in LDS up to this size
 
 // Second family step pushed from F: thread t takes edge slots t, t + T, ...
@@ -827,7 +804,32 @@ constexpr int kPushLdsOffs = 2048;  // frontier offsets searched in LDS up to th
 __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const int64_t *a_rowptr,
                                                           const int32_t *a_col, const float *a_w, PushPlan pp) {
     __shared__ long long soffs[kPushLdsOffs + 1];
-    if (!*pp.flag) return;
+    if (!*pp.flag) {
+        // step 2 will be pulled: y1 densely, as the gathered vector that the
+        // step reads (p.zin of the step-2 launches).  Entry v is y1f at v's
+        // position in the seed's sorted out-neighbour list, the appended
+        // seed entry, or zero.
+        float *y1 = const_cast<float *>(p.zin);
+        const int32_t s = p.seeds[0];
+        const bool valid = s >= 0 && (int64_t)s < p.n;
+        const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
+        for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
+             v += (int64_t)gridDim.x * blockDim.x) {
+            float val = 0.0f;
+            if (valid) {
+                int64_t lo = e0, hi = e1;  // first edge with a_col >= v
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a_col[mid] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo < e1 && a_col[lo] == v) val = pp.y1f[lo - e0];
+                else if (v == (int64_t)s) val = pp.y1f[e1 - e0];
+            }
+            y1[zrow(p, v)] = val;
+        }
+        return;
+    }
     const int64_t W = pp.ctrl[0];
     const int64_t nf = pp.ctrl[1];
     const int64_t first = (int64_t)blockIdx.x * blockDim.x;
@@ -1017,8 +1019,9 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
 
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
     if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
-    push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
-    push_first_dense_kernel<<<std::min<unsigned>(grid_1d(p.n), 256), 256, 0, st>>>(p, g->a.rowptr, g->a.col, pp);
+    const unsigned clear_blocks = (unsigned)std::min<int64_t>((pp.nwords + 255) / 256, 1024);
+    push_first_plan_kernel<<<1 + clear_blocks, 64, 0, st>>>(p, g->a.rowptr, g->a.col,
+                                                            g->weighted ? g->a.w : nullptr, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
