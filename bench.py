@@ -120,6 +120,88 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
                                                  "(both CPI chains, 64-seed tile)"}}
 
 
+def _time_ms(torch, fn, reps=3):
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    return best
+
+
+def other_configs(tpa, torch, np) -> dict:
+    """The other workloads on the same GPU (best of 3 after a warm-up, inputs
+    resident): 1024 seeds on 2^22 nodes with the autotuner's choice replayed
+    from a hipGraph; the uneven batch of 256 R-MAT graphs (4 seeds each,
+    logit weights) forward and adjoint; the 2^27-node, 2^31-sample graph's
+    preprocessing, 16-seed query and 4-seed adjoint."""
+    import tpa_inputs as ti
+    res = {}
+    # 2^22 nodes, 1024 seeds, autotuned, captured
+    print("bench: rmat22 batched (autotune + capture)", file=sys.stderr, flush=True)
+    scale, samples, gseed = ti.GRAPHS["rmat22"]
+    g = tpa.Graph.rmat(scale, samples, gseed)
+    g.preprocess(C_RESTART, T_STR)
+    sd = torch.from_numpy(ti.draw_seeds((g.padded() == 0).cpu().numpy(), 1024, 2)).cuda()
+    out = torch.empty((1024, g.n), dtype=torch.float32, device="cuda")
+    tile, ew, _ = g.autotune(sd, C_RESTART, S_FAM, T_STR, scratch_out=out)
+    g.reserve(1024)
+    qg = g.capture_query(C_RESTART, S_FAM, T_STR, out, seeds=sd)
+    qg.launch()
+    torch.cuda.synchronize()
+    ms = _time_ms(torch, qg.launch)
+    qg.close()
+    res["rmat22_batched"] = {"n": g.n, "m": g.m, "seeds": 1024, "seed_tile": tile, "edges_per_item": ew,
+                             "captured_ms": round(ms, 3), "seeds_per_s": round(1024 / (ms * 1e-3), 1),
+                             "gteps": round(1024 * (S_FAM - 1) * g.m / (ms * 1e-3) / 1e9, 1)}
+    del g, out, qg
+    torch.cuda.empty_cache()
+    # uneven 256-graph batch with logits: forward and adjoint
+    print("bench: uneven 256-graph batch", file=sys.stderr, flush=True)
+    sizes = ti.block_sizes(256, 2024)
+    gs = [tpa.Graph.rmat(sc, smp, s_, n_nodes=ng) for sc, ng, smp, s_ in ti.block_rmat_params(sizes, 2024)]
+    pk = tpa.Graph.pack(gs)
+    del gs
+    off = pk.block_offsets()
+    pk.set_logits(torch.from_numpy(ti.draw_logits(pk.m, 2025)).cuda())
+    t_pre = _time_ms(torch, lambda: pk.preprocess(C_RESTART, T_STR), reps=1)
+    padded = pk.padded().cpu().numpy()
+    seeds = np.stack([off[b] + ti.draw_seeds(padded[off[b]:off[b + 1]] == 0, 4, 3000 + b)
+                      for b in range(256)]).astype(np.int32)
+    sdp = torch.from_numpy(seeds).cuda()
+    W = torch.from_numpy(ti.draw_loss_weights((4, pk.n), 2026)).cuda()
+    pk.query_packed(sdp, C_RESTART, S_FAM, T_STR)
+    fwd = _time_ms(torch, lambda: pk.query_packed(sdp, C_RESTART, S_FAM, T_STR))
+    pk.backward(W, C_RESTART, S_FAM, T_STR, seeds=sdp, packed=True)
+    bwd = _time_ms(torch, lambda: pk.backward(W, C_RESTART, S_FAM, T_STR, seeds=sdp, packed=True), reps=2)
+    res["uneven_batch"] = {"graphs": 256, "N": pk.n, "m": pk.m, "seeds_per_graph": 4,
+                           "preprocess_ms": round(t_pre, 3), "query_ms": round(fwd, 3),
+                           "backward_ms": round(bwd, 3)}
+    del pk, W, sdp
+    torch.cuda.empty_cache()
+    # billion-edge graph
+    print("bench: rmat27 (2^31 samples)", file=sys.stderr, flush=True)
+    scale, samples, gseed = ti.GRAPHS["rmat27"]
+    g = tpa.Graph.rmat(scale, samples, gseed)
+    g.preprocess(C_RESTART, T_STR)
+    t_pre = _time_ms(torch, lambda: g.preprocess(C_RESTART, T_STR), reps=1)
+    sd = torch.from_numpy(ti.draw_seeds((g.padded() == 0).cpu().numpy(), 16, 27)).cuda()
+    g.set_tuning(seed_tile=16)
+    out = torch.empty((16, g.n), dtype=torch.float32, device="cuda")
+    g.query(sd, C_RESTART, S_FAM, T_STR, out=out)
+    q16 = _time_ms(torch, lambda: g.query(sd, C_RESTART, S_FAM, T_STR, out=out), reps=2)
+    g.set_tuning(0, 0)
+    W = torch.from_numpy(ti.draw_loss_weights((4, g.n), 28)).cuda()
+    bwd = _time_ms(torch, lambda: g.backward(W, C_RESTART, S_FAM, T_STR, seeds=sd[:4]), reps=1)
+    res["rmat27"] = {"n": g.n, "m": g.m, "preprocess_ms": round(t_pre, 1),
+                     "preprocess_gteps": round(116 * g.m / (t_pre * 1e-3) / 1e9, 1),
+                     "query16_ms": round(q16, 2), "backward4_ms": round(bwd, 1)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +212,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the untimed accuracy report and adjoint timing")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="also time the other workloads (untimed in the step): 2^22-node batched query with "
+                         "autotune and hipGraph capture, the uneven 256-graph batch with its adjoint, and the "
+                         "billion-edge graph")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="after timing, run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -284,6 +370,10 @@ def main():
     }
     if not args.no_extras:
         rec.update(extras(tpa, g, seeds, seeds_h, torch, np))
+    if args.all_configs:
+        del out_plain, out_batch, g
+        torch.cuda.empty_cache()
+        rec["configs"] = other_configs(tpa, torch, np)
     if args.calibration_copy_mib > 0:
         src = torch.empty(args.calibration_copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
