@@ -250,18 +250,20 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
 
-/* Memory order of the vectors a CPI step gathers (internal work buffers),
- * for graphs with 1/outdeg weights.  hub_first = 1 (default): node v's
+/* Memory order of the vectors a CPI step gathers (internal work buffers).
+ * hub_first = 1 (default): node v's
  * entries sit at the rank of v by descending out-degree (ties by id), so
  * the most gathered entries, those of high out-degree sources, share cache
  * lines, and each row of A~^T is summed in ascending rank, so the lanes
  * that read the first edges of neighbouring rows hit the same lines.  The
- * re-sorted column ids are a second int32[m] array (plus int32[n] ranks),
- * built by tpa_preprocess, or here when the graph is already preprocessed.
- * hub_first = 0 keeps node order, A~^T's own edge order and no extra
- * memory.  The two orders give the same sums up to FP32 rounding (each row
- * is added in a different order).  Graphs with logit weights always use
- * node order.  Synchronous when it builds.  Errors: INVALID_ARG, OOM, HIP. */
+ * re-sorted column ids and each entry's position in its original row are
+ * two more int32[m] arrays (plus int32[n] ranks); graphs with logit
+ * weights also keep their weights in that order (float[m], refreshed by
+ * tpa_preprocess after tpa_graph_set_logits).  Built by tpa_preprocess, or
+ * here when the graph is already preprocessed.  hub_first = 0 keeps node
+ * order, A~^T's own edge order and no extra memory.  The two orders give
+ * the same sums up to FP32 rounding (each row is added in a different
+ * order).  Synchronous when it builds.  Errors: INVALID_ARG, OOM, HIP. */
 tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first);
 tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
 tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);

@@ -393,8 +393,8 @@ class Graph:
 
     def set_gather_layout(self, hub_first: bool = True):
         """Order of the gathered work vectors and of each row's edge sum:
-        hub-first (default, 1/outdeg weights only) or node order; results
-        agree up to FP32 rounding."""
+        hub-first (default) or node order; results agree up to FP32
+        rounding."""
         _call("tpa_set_gather_layout", self._h, int(bool(hub_first)))
 
     def get_gather_layout(self) -> bool:

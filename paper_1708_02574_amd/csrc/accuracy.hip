@@ -280,8 +280,11 @@ extern "C" tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, doubl
     }
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
-    if (g->gather_layout && !g->weighted) TPA_TRY(ensure_zlayout(g, st));
-    const bool hub = g->gather_layout && g->zperm && !g->weighted;
+    if (g->gather_layout) {
+        TPA_TRY(ensure_zlayout(g, st));
+        TPA_TRY(ensure_wz(g, st));
+    }
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     float *tmp = nullptr;
     TPA_TRY(dalloc(&tmp, 3 * (size_t)n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));
     float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
@@ -294,7 +297,7 @@ extern "C" tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, doubl
     p.rowptr = g->t.rowptr;
     p.col = hub ? g->t_colz : g->t.col;
     p.zperm = hub ? g->zperm : nullptr;
-    p.w = g->weighted ? g->t.w : nullptr;
+    p.w = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
     p.omc = (float)(1.0 - c);

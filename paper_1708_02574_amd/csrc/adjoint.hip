@@ -516,7 +516,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     if (packed && (!seeds || !g->node_block)) return fail(TPA_ERR_INVALID_ARG, "packed needs seeds and a packed graph");
     const int64_t n = g->n, m = g->m, K = g->K;
     // forward recomputation in the gather layout of the query path
-    const bool hub = g->gather_layout && g->zperm && !g->weighted;
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    const float *w_gather = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
     const float omc = (float)(1.0 - c);
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     const float alpha = (float)((1.0 - pT) / (1.0 - pS));
@@ -560,7 +561,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, fp.zperm, st));
         fp.rowptr = g->t.rowptr;
         fp.col = hub ? g->t_colz : g->t.col;
-        fp.w = g->weighted ? g->t.w : nullptr;
+        fp.w = w_gather;
         fp.inv = g->inv_deg;
         fp.partials = part_f;
         fp.omc = omc;
@@ -677,7 +678,9 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             fp.zin = zc;
             fp.zout = zn;
             fp.xs_out = xf + (size_t)i * n * kt;
-            fp.col = (i == 1 && !q) ? g->t.col : (hub ? g->t_colz : g->t.col);  // first steps read node ids
+            const bool first = i == 1 && !q;  // first steps read node ids and A~^T's own weight order
+            fp.col = first ? g->t.col : (hub ? g->t_colz : g->t.col);
+            fp.w = first ? (g->weighted ? g->t.w : nullptr) : w_gather;
             TPA_TRY(launch_step(*sfk, kPlain, i == 1 && !q, fp, st));
             std::swap(zc, zn);
         }

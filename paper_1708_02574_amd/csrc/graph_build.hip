@@ -422,13 +422,28 @@ __global__ void map_cols_kernel(const int32_t *col, int64_t m, const int32_t *ra
         out[e] = rank[col[e]];
 }
 
-__global__ void row_col_keys_kernel(const int64_t *rowptr, int64_t n, const int32_t *colz, uint64_t *keys) {
+__global__ void row_col_keys_kernel(const int64_t *rowptr, int64_t n, const int32_t *colz, uint64_t *keys,
+                                    int32_t *loc) {
     const int lane = threadIdx.x & 63;
     const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t v = w0; v < n; v += nw)
-        for (int64_t e = rowptr[v] + lane; e < rowptr[v + 1]; e += 64)
+        for (int64_t e = rowptr[v] + lane; e < rowptr[v + 1]; e += 64) {
             keys[e] = ((uint64_t)v << 32) | (uint32_t)colz[e];
+            loc[e] = (int32_t)(e - rowptr[v]);
+        }
+}
+
+// Weights of A~^T in the re-sorted row order: wz[e'] = w[rowptr[v] + loc[e']].
+__global__ void gather_row_w_kernel(const int64_t *rowptr, int64_t n, const int32_t *loc, const float *w,
+                                    float *wz) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = w0; v < n; v += nw) {
+        const int64_t b = rowptr[v];
+        for (int64_t e = b + lane; e < rowptr[v + 1]; e += 64) wz[e] = w[b + loc[e]];
+    }
 }
 
 __global__ void low32_kernel(const uint64_t *keys, int64_t m, int32_t *out) {
@@ -477,29 +492,62 @@ tpa_status ensure_zlayout(tpa_graph *g, hipStream_t st) {
     e = hipStreamSynchronize(st);
     cleanup();
     // each row's edges in ascending hub rank: the first edges of every row
-    // then read the same few cache lines of the gathered vector
+    // then read the same few cache lines of the gathered vector; each edge's
+    // position in its row of A~^T is kept (loc) to re-sort per-edge weights
+    int32_t *loc = nullptr;
     if (e == hipSuccess) {
-        uint64_t *keys = nullptr, *sorted = nullptr;
-        rc = dalloc(&keys, m, st);
-        if (rc == TPA_OK) {
-            row_col_keys_kernel<<<grid_for(n * 64), kBlock, 0, st>>>(g->t.rowptr, n, colz, keys);
-            rc = sort_keys(keys, m, 32 + g->bits, st, &sorted);
+        uint64_t *k2a = nullptr, *k2b = nullptr;
+        int32_t *l2b = nullptr;
+        void *tmp2 = nullptr;
+        if ((rc = dalloc(&k2a, m, st)) == TPA_OK && (rc = dalloc(&k2b, m, st)) == TPA_OK &&
+            (rc = dalloc(&loc, m, st)) == TPA_OK && (rc = dalloc(&l2b, m, st)) == TPA_OK) {
+            row_col_keys_kernel<<<grid_for(n * 64), kBlock, 0, st>>>(g->t.rowptr, n, colz, k2a, loc);
+            rocprim::double_buffer<uint64_t> kb2(k2a, k2b);
+            rocprim::double_buffer<int32_t> lb2(loc, l2b);
+            size_t bytes2 = 0;
+            e = rocprim::radix_sort_pairs(nullptr, bytes2, kb2, lb2, (size_t)m, 0u, (unsigned)(32 + g->bits), st);
+            if (e == hipSuccess) rc = dmalloc(&tmp2, std::max<size_t>(bytes2, 16), st);
+            if (e == hipSuccess && rc == TPA_OK)
+                e = rocprim::radix_sort_pairs(tmp2, bytes2, kb2, lb2, (size_t)m, 0u, (unsigned)(32 + g->bits), st);
+            if (e == hipSuccess && rc == TPA_OK) {
+                low32_kernel<<<grid_for(m), kBlock, 0, st>>>(kb2.current(), m, colz);
+                e = hipStreamSynchronize(st);
+            }
+            // keep the sorted positions, free the other buffer
+            int32_t *keep = lb2.current();
+            int32_t *other = lb2.alternate();
+            loc = keep;
+            dfree(other);
+        } else {
+            dfree(l2b);
         }
-        if (rc == TPA_OK) {
-            low32_kernel<<<grid_for(m), kBlock, 0, st>>>(sorted, m, colz);
-            e = hipStreamSynchronize(st);
-        }
-        if (sorted) dfree(sorted);
-        else dfree(keys);
-        if (rc != TPA_OK) { dfree(rank); dfree(colz); return rc; }
+        dfree(k2a);
+        dfree(k2b);
+        dfree(tmp2);
+        if (e != hipSuccess && rc == TPA_OK) rc = fail(TPA_ERR_HIP, std::string("row sort: ") + hipGetErrorString(e));
+        if (rc != TPA_OK) { dfree(rank); dfree(colz); dfree(loc); return rc; }
     }
     if (e != hipSuccess) {
         dfree(rank);
         dfree(colz);
+        dfree(loc);
         return fail(TPA_ERR_HIP, std::string("gather layout: ") + hipGetErrorString(e));
     }
     g->zperm = rank;
     g->t_colz = colz;
+    g->t_locz = loc;
+    g->t_wz_valid = false;
+    return TPA_OK;
+}
+
+// Per-edge weights in the gather layout's row order, after the weights
+// change (weighted graphs only).
+tpa_status ensure_wz(tpa_graph *g, hipStream_t st) {
+    if (!g->weighted || !g->t_locz || g->t_wz_valid) return TPA_OK;
+    if (!g->t_wz) TPA_TRY(dalloc(&g->t_wz, g->m, st));
+    gather_row_w_kernel<<<grid_for(g->n * 64), kBlock, 0, st>>>(g->t.rowptr, g->n, g->t_locz, g->t.w, g->t_wz);
+    TPA_TRY_HIP(hipGetLastError());
+    g->t_wz_valid = true;
     return TPA_OK;
 }
 
@@ -604,9 +652,11 @@ void graph_release(tpa_graph *g) {
     dfree(g->a.rowptr); dfree(g->a.col); dfree(g->a.w);
     dfree(g->t.rowptr); dfree(g->t.col); dfree(g->t.w);
     dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
-    dfree(g->zperm); dfree(g->t_colz);
+    dfree(g->zperm); dfree(g->t_colz); dfree(g->t_locz); dfree(g->t_wz);
     g->zperm = nullptr;
     g->t_colz = nullptr;
+    g->t_locz = nullptr;
+    g->t_wz = nullptr;
     dfree(g->str); dfree(g->ws); dfree(g->dev_err);
     for (auto &kv : g->sched_t) kv.second.release();
     for (auto &kv : g->sched_a) kv.second.release();
@@ -852,5 +902,6 @@ extern "C" tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hi
     gather_w_kernel<<<grid_for(g->m), kBlock, 0, st>>>(g->a.w, g->t2a, g->m, g->t.w);
     TPA_TRY_HIP(hipGetLastError());
     g->weighted = true;
+    g->t_wz_valid = false;
     return TPA_OK;
 }

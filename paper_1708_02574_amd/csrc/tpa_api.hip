@@ -179,15 +179,17 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     StepParams p;
     p.rowptr = g->t.rowptr;
-    p.w = g->weighted ? g->t.w : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
     p.err = g->dev_err;
-    // gathered vectors in hub-first rows (first steps read node ids: t.col)
-    const bool hub = g->gather_layout && g->zperm && !g->weighted;
+    // gathered vectors in hub-first rows (first steps read node ids: t.col
+    // and t.w in A~^T's own order)
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     p.zperm = hub ? g->zperm : nullptr;
     const int32_t *col_gather = hub ? g->t_colz : g->t.col;
+    const float *w_gather = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
     p.col = col_gather;
+    p.w = w_gather;
     p.omc = (float)(1.0 - c);
     p.c = (float)c;
     p.kt = kt;
@@ -236,6 +238,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             // one-hot restart: the first step needs no gather
             const bool first = step == 1 && !q;
             p.col = first ? g->t.col : col_gather;
+            p.w = first ? (g->weighted ? g->t.w : nullptr) : w_gather;
             TPA_TRY(launch_step(*s, kFamily, first, p, st));
         }
     }
@@ -271,8 +274,11 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     const int64_t K = stranger_last_iteration(c, eps);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
-    if (g->gather_layout && !g->weighted) TPA_TRY(ensure_zlayout(g, st));
-    const bool hub = g->gather_layout && g->zperm && !g->weighted;
+    if (g->gather_layout) {
+        TPA_TRY(ensure_zlayout(g, st));
+        TPA_TRY(ensure_wz(g, st));
+    }
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
     float *tmp = nullptr;
     const size_t n = (size_t)g->n;
@@ -283,7 +289,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     p.rowptr = g->t.rowptr;
     p.col = hub ? g->t_colz : g->t.col;
     p.zperm = hub ? g->zperm : nullptr;
-    p.w = g->weighted ? g->t.w : nullptr;
+    p.w = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
     p.inv = g->inv_deg;
     p.partials = part;
     p.omc = (float)(1.0 - c);
@@ -368,7 +374,11 @@ extern "C" tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_p
 extern "C" tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first) {
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     if (hub_first != 0 && hub_first != 1) return fail(TPA_ERR_INVALID_ARG, "hub_first must be 0 or 1");
-    if (hub_first && g->preprocessed && !g->weighted) TPA_TRY(ensure_zlayout(g, nullptr));
+    if (hub_first && g->preprocessed) {
+        TPA_TRY(ensure_zlayout(g, nullptr));
+        TPA_TRY(ensure_wz(g, nullptr));
+        TPA_TRY_HIP(hipStreamSynchronize(nullptr));
+    }
     g->gather_layout = hub_first;
     return TPA_OK;
 }

@@ -116,12 +116,16 @@ struct tpa_graph {
     tpa::Csr a;                             // A~   (rows = sources)
     tpa::Csr t;                             // A~^T (rows = destinations)
     int64_t *t2a = nullptr;                 // A~^T entry -> A~ entry (lazy)
-    // gather layout of the CPI work vectors (uniform weights only): node v's
-    // entries sit at row zperm[v] (rank of v by descending out-degree, ties
-    // by id); t_colz holds zperm[t.col] with each row of A~^T re-sorted in
-    // ascending rank (built at preprocessing)
+    // gather layout of the CPI work vectors: node v's entries sit at row
+    // zperm[v] (rank of v by descending out-degree, ties by id); t_colz holds
+    // zperm[t.col] with each row of A~^T re-sorted in ascending rank, t_locz
+    // each entry's position in its original row, and t_wz the per-edge
+    // weights in that order (logit weights; rebuilt at preprocessing)
     int32_t *zperm = nullptr;               // n
     int32_t *t_colz = nullptr;              // m
+    int32_t *t_locz = nullptr;              // m
+    float *t_wz = nullptr;                  // m, weighted graphs
+    bool t_wz_valid = false;
     int gather_layout = 1;                  // 1 = hub-first order, 0 = node order
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
@@ -165,8 +169,10 @@ tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStrea
 tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out,
                         bool over_a = false);
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
-// Build zperm and t_colz (synchronises `stream`); no-op when present.
+// Build zperm, t_colz and t_locz (synchronises `stream`); no-op when present.
 tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
+// Build t_wz from the current weights when the graph is weighted.
+tpa_status ensure_wz(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

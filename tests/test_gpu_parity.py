@@ -325,9 +325,9 @@ def test_frontier_skip_is_bitwise_neutral(rmat13, torch, kt, Sq):
 def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
     """Hub-first and node-order work vectors: stranger vector, single-seed
     queries (pushed and pulled step 2, S = 2 with a pulled first step), seed
-    tiles 4 and 64 and dense restart vectors all match the oracle, and agree
-    with each other to FP32 rounding (bit for bit with logit weights, which
-    always use node order)."""
+    tiles 4 and 64 and dense restart vectors all match the oracle and agree
+    with each other to FP32 rounding, with 1/outdeg and with logit weights
+    (whose per-edge weights follow the re-sorted rows)."""
     og = oracle.Graph.rmat(12, 60000, 31)
     gg = tpa.Graph.rmat(12, 60000, 31)
     if weighted:
@@ -368,10 +368,7 @@ def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
     for i, (a, b, e) in enumerate(zip(res[0], res[1], expect)):
         assert np.all(l1_rows(a.cpu().numpy(), e) <= TOL), i
         assert np.all(l1_rows(b.cpu().numpy(), e) <= TOL), i
-        if weighted:
-            assert torch.equal(a, b), i
-        else:
-            assert float((a - b).abs().max()) <= 1e-6, i
+        assert float((a - b).abs().max()) <= 1e-6, i
 
 
 # ---------------------------------------------------------------- packed
