@@ -24,8 +24,11 @@
 //   item's edges in order with wave-uniform control; column ids are loaded
 //   64 at a time and broadcast with readlane, and 32 row gathers of 256 B
 //   (one per edge, contiguous across the lanes) are in flight at once.
-// Seed tiles of 2..32 (generic): lanes (sub, j) with 64/kt sub-groups add
-//   column j over every (64/kt)-th edge of a row; xor shuffles combine.
+// Seed tiles of 2..32 (generic): lanes (sub, j) form 64/kt sub-groups of kt
+//   lanes (lane j = column j).  Each sub-group sums one short row of a group
+//   item, edges in order with 4 gathers in flight; rows longer than 32
+//   edges, and row or chunk items, are summed by the whole wave, sub-groups
+//   striding over the edges, and xor shuffles combine.
 // Every sum is taken in a fixed order: results are bitwise reproducible.
 
 #include <cmath>
@@ -607,8 +610,39 @@ __device__ __forceinline__ float range_sum_kt(const StepParams &p, int64_t e0, i
     return s;
 }
 
+// One row summed by one sub-group of KT lanes (lane j = column j), its
+// edges in order with 4 gathers in flight.
+template <int KT, bool FIRST, bool WEIGHTED>
+__device__ __forceinline__ float row_sum_kt(const StepParams &p, int64_t e0, int64_t e1, int j) {
+    constexpr int UNR = 4;
+    float s = 0.0f;
+    for (int64_t base = e0; base < e1; base += UNR) {
+        int32_t u[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) u[k] = base + k < e1 ? p.col[base + k] : -1;
+        float v[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) v[k] = u[k] >= 0 ? edge_value<FIRST, WEIGHTED, KT>(p, base + k, u[k], j) : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) s += v[k];
+    }
+    return s;
+}
+
+__device__ __forceinline__ EpiPre epi_shfl(const EpiPre &q, int r) {
+    EpiPre o;
+    o.a = __shfl(q.a, r, 64);
+    o.b = __shfl(q.b, r, 64);
+    o.c = __shfl(q.c, r, 64);
+    o.zi = __shfl(q.zi, r, 64);
+    return o;
+}
+
+constexpr int kShortRowKt = 32;  // rows up to this many edges take one sub-group
+
 template <int KT, int MODE, bool FIRST, bool WEIGHTED>
 __device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int64_t wid, int lane) {
+    constexpr int SUBS = 64 / KT;
     const int j = lane % KT, sub = lane / KT;
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
@@ -617,9 +651,25 @@ __device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int6
         // row offsets and epilogue operands loaded ahead, one row per lane
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
         EpiPre q;
         if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
-        for (int r = 0; r < nrows; ++r) {
+        // short rows: SUBS rows at a time, one per sub-group
+        for (int rb = 0; rb < nrows; rb += SUBS) {
+            const int r = min(rb + sub, 63);
+            const int b = __shfl(rel, r, 64), en = __shfl(rel_next, r, 64);
+            const bool mine = rb + sub < nrows && en - b <= kShortRowKt;
+            const EpiPre qr = epi_shfl(q, r);
+            if (mine) {
+                const float s = row_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0 + b, it.e0 + en, j);
+                epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
+            }
+        }
+        // longer rows: the whole wave, sub-groups striding over the edges
+        uint64_t big = __ballot(lane < nrows && rel_next - rel > kShortRowKt);
+        while (big) {
+            const int r = __builtin_ctzll(big);
+            big &= big - 1;
             const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel, r + 1);
             const EpiPre qr = epi_readlane(q, r);
             const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0 + b, it.e0 + en, sub, j);
