@@ -184,27 +184,34 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
     }
     __syncthreads();
     const uint32_t above = s_count;
-    // entries equal to K, the take_eq with the lowest indices: thread t owns
-    // the contiguous segment [t*seg, (t+1)*seg), counts its equal entries,
-    // and one block scan of the counts gives each segment its first rank
-    const int64_t seg = (n + blockDim.x - 1) / blockDim.x;
-    const int64_t s0 = (int64_t)tid * seg, s1 = min(n, s0 + seg);
-    uint32_t mine = 0u;
-    for (int64_t v = s0; v < s1; ++v) mine += order_key(row[v]) == K ? 1u : 0u;
-    scan[tid] = mine;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        const uint32_t t = tid >= off ? scan[tid - off] : 0u;
+    // entries equal to K, the take_eq with the lowest indices: wave w owns the
+    // contiguous segment [w*seg, (w+1)*seg) and walks it 64 entries at a
+    // time (coalesced); a scan of the per-wave counts gives each segment its
+    // first rank, and ballots rank the entries inside a chunk
+    {
+        const int wv = tid >> 6, lane = tid & 63;
+        const int nw = (int)blockDim.x >> 6;
+        const int64_t seg = ((n + nw - 1) / nw + 63) & ~(int64_t)63;
+        const int64_t s0 = (int64_t)wv * seg, s1 = min(n, s0 + seg);
+        uint32_t cnt = 0u;
+        for (int64_t v0 = s0; v0 < s1; v0 += 64) {
+            const int64_t v = v0 + lane;
+            cnt += (uint32_t)__popcll(__ballot(v < s1 && order_key(row[v]) == K));
+        }
+        if (lane == 0) scan[wv] = cnt;
         __syncthreads();
-        scan[tid] += t;
-        __syncthreads();
-    }
-    uint32_t rank = scan[tid] - mine;  // equal entries before this segment
-    for (int64_t v = s0; v < s1 && rank < take_eq; ++v) {
-        if (order_key(row[v]) == K) {
-            skey[above + rank] = K;
-            sidx[above + rank] = (int32_t)v;
-            ++rank;
+        uint32_t rank = 0u;
+        for (int w = 0; w < wv; ++w) rank += scan[w];
+        for (int64_t v0 = s0; v0 < s1 && rank < take_eq; v0 += 64) {
+            const int64_t v = v0 + lane;
+            const bool eq = v < s1 && order_key(row[v]) == K;
+            const uint64_t m = __ballot(eq);
+            const uint32_t r = rank + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            if (eq && r < take_eq) {
+                skey[above + r] = K;
+                sidx[above + r] = (int32_t)v;
+            }
+            rank += (uint32_t)__popcll(m);
         }
     }
     __syncthreads();
