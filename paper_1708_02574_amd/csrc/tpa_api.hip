@@ -222,8 +222,16 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                 continue;
             }
             if (step == 2 && push2) {
-                TPA_TRY(launch_push_second(p, g, pp, st));
-                TPA_TRY(launch_gated_step(*s, p, pp, st));
+                tpa_status rc = launch_push_second(p, g, pp, st);
+                if (rc == TPA_OK) rc = launch_gated_step(*s, p, pp, st);
+                if (rc != TPA_OK) {
+                    // the conversion that clears acc may not have run: restore
+                    // the all-zero push state before reporting the error
+                    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+                        (void)clear_push_state(g, ws, st);
+                    return rc;
+                }
                 continue;
             }
             // the step after a push gathers only the rows the push reached:
