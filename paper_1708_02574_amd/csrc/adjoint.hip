@@ -89,12 +89,17 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
         int32_t v[NS];
+        float gold[NS];  // G of the item's edges, read together with the column ids
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int e = s * 64 + lane;
             v[s] = e < nnz ? col[e] : -1;
+            gold[s] = (WITHG && e < nnz) ? p.G[it.e0 + e] : 0.0f;
         }
         const float xr = (WITHG && lane < nrows) ? p.omc * p.xprev[it.row0 + lane] : 0.0f;
+        // epilogue operands of row (row0 + lane), loaded ahead
+        const float gu = lane < nrows ? p.gvec[it.row0 + lane] : 0.0f;
+        const float iu = (!WEIGHTED && lane < nrows) ? p.inv[it.row0 + lane] : 0.0f;
         float l[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) l[s] = v[s] >= 0 ? p.lam_in[v[s]] : 0.0f;
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         for (int s = 0; s < NS; ++s) {
             const int e = s * 64 + lane;
             if (s * 64 < nnz) {
-                if (WITHG && e < nnz) p.G[it.e0 + e] += mx[e] * l[s];
+                if (WITHG && e < nnz) p.G[it.e0 + e] = gold[s] + mx[e] * l[s];
                 my[e] = (WEIGHTED && e < nnz) ? p.w[it.e0 + e] * l[s] : l[s];
             }
         }
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         if (lane < nrows && len <= 32) {
             float acc = 0.0f;
             for (int k = rel; k < rel_next; ++k) acc += my[k];
-            adj_epilogue(p, it.row0 + lane, 0, acc);
+            p.lam_out[it.row0 + lane] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? acc : acc * iu));
         }
         uint64_t big = __ballot(lane < nrows && len > 32);
         while (big) {
@@ -139,21 +144,28 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
             for (int k = b + lane; k < en; k += 64) t += my[k];
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) adj_epilogue(p, it.row0 + r, 0, t);
+            const float gr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gu), r));
+            const float ir = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(iu), r));
+            if (lane == 0) p.lam_out[it.row0 + r] = fmaf(p.beta, gr, p.omc * (WEIGHTED ? t : t * ir));
         }
         return;
     }
     // one row or one chunk of a long row
     const int64_t row = kind == (int)kItemRow ? (int64_t)it.row0 : (int64_t)p.longs[it.row0].row;
     const float xr = WITHG ? p.omc * p.xprev[row] : 0.0f;
+    const bool whole = kind == (int)kItemRow;
+    const float gu = whole ? p.gvec[row] : 0.0f;
+    const float iu = (whole && !WEIGHTED) ? p.inv[row] : 0.0f;
     constexpr int UNR = 16;
     float s = 0.0f;
     for (int base = 0; base < nnz; base += 64 * UNR) {
         int32_t v[UNR];
+        float gold[UNR];
 #pragma unroll
         for (int k = 0; k < UNR; ++k) {
             const int e = base + k * 64 + lane;
             v[k] = e < nnz ? col[e] : -1;
+            gold[k] = (WITHG && e < nnz) ? p.G[it.e0 + e] : 0.0f;
         }
         float l[UNR];
 #pragma unroll
@@ -162,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         for (int k = 0; k < UNR; ++k) {
             const int e = base + k * 64 + lane;
             if (v[k] >= 0) {
-                if (WITHG) p.G[it.e0 + e] += xr * l[k];
+                if (WITHG) p.G[it.e0 + e] = gold[k] + xr * l[k];
                 s += WEIGHTED ? p.w[it.e0 + e] * l[k] : l[k];
             }
         }
@@ -170,8 +182,8 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
-        if (kind == (int)kItemRow)
-            adj_epilogue(p, row, 0, s);
+        if (whole)
+            p.lam_out[row] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? s : s * iu));
         else
             p.partials[wid] = s;
     }
