@@ -61,14 +61,15 @@ struct StepParams {
 // (kt == 1).  The frontier of step 2 is F = out(s) + {s} (s appended when
 // it has no self-loop); y1f holds y1 on F as gathered values, offs[f] the
 // exclusive prefix sum of outdeg over F, so the push touches W = offs[|F|]
-// edges of A~.  acc holds y2 in gathered form (scaled by 1/outdeg for
-// uniform weights), indexed by gather row, as fixed point (2^62 units); it
-// is all zero between queries.
+// edges of A~, and est[f] the first A~ edge of F's f-th node.  acc holds y2
+// in gathered form (scaled by 1/outdeg for uniform weights), indexed by
+// gather row, as fixed point (2^62 units); it is all zero between queries.
 struct PushPlan {
     unsigned long long *acc = nullptr;  // [n] by gather row, zero between queries
     uint32_t *bits = nullptr;           // [ceil(n/32)]: rows of the pushed vector that may be non-zero
     int64_t nwords = 0;
     int64_t *offs = nullptr;            // [max_outdeg + 2]
+    int64_t *est = nullptr;             // [max_outdeg + 1]
     float *y1f = nullptr;               // [max_outdeg + 1]
     int64_t *ctrl = nullptr;            // {W, |F|}
     int32_t *flag = nullptr;            // 1: step 2 is pushed (the gated step converts acc)
@@ -103,22 +104,22 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
                              int64_t nwords, hipStream_t st);
 
 // Single seed (kt == 1, unpacked): the first step kept compact on F (y1f)
-// with the plan of the second step (offs, W, |F|, flag = W <= wmax), in one
-// launch whose other blocks clear the frontier bitmap.
+// with the plan of the second step (offs, est, W, |F|, flag = W <= wmax),
+// one wave.
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // Second family step of a single seed pushed over the out-edges of F when
 // the plan's flag is set: the terms of (1-c) A~^T y1, in gathered form,
 // accumulated in fixed point (order-independent, so bitwise reproducible)
-// into acc, which the plan seeded with the restart term c e_s; the rows of
-// y2 that may be non-zero are marked in bits (which the plan's launch
-// cleared).  With the flag clear it writes y1 densely to p.zin instead, for
-// the pulled second step.
+// into acc, which the plan seeded with the restart term c e_s.  With the
+// flag clear it writes y1 densely to p.zin instead, for the pulled second
+// step.
 tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // The second family step proper (p.zin = dense y1, p.zout = y2 as the next
 // gathered vector): with the flag set every row is converted from acc (and
-// acc cleared); with it clear the step is pulled over A~^T as usual.
+// acc cleared) and bits receives the rows of y2 that are non-zero; with it
+// clear the step is pulled over A~^T as usual.
 tpa_status launch_gated_step(const Schedule &s, const StepParams &p, const PushPlan &pp, hipStream_t st);
 
 // S == 1: out = alpha*c*[v == seed] + r~_stranger (no CPI step).

@@ -200,9 +200,20 @@ __device__ __forceinline__ void finish_row(const StepParams &p, const LongRow &l
         for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
         if (lane == 0) epilogue<MODE>(p, lr.row, 0, t);
     } else {
+        // column j's partials in chunk order, 16 loads in flight per round
+        constexpr int R = 16;
         for (int j = lane; j < kt; j += 64) {
+            const float *pj = p.partials + (int64_t)lr.first_item * kt + j;
             float t = 0.0f;
-            for (int i = 0; i < lr.nchunks; ++i) t += p.partials[((int64_t)lr.first_item + i) * kt + j];
+            int i = 0;
+            for (; i + R <= lr.nchunks; i += R) {
+                float v[R];
+#pragma unroll
+                for (int k = 0; k < R; ++k) v[k] = pj[(int64_t)(i + k) * kt];
+#pragma unroll
+                for (int k = 0; k < R; ++k) t += v[k];
+            }
+            for (; i < lr.nchunks; ++i) t += pj[(int64_t)i * kt];
             epilogue<MODE>(p, lr.row, j, t);
         }
     }
@@ -219,11 +230,13 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
 
 // Gather row r of the pushed second step: acc[r] holds the row's gathered
 // value (y2 scaled by 1/outdeg for uniform weights) in 2^62 fixed point, the
-// restart term included; it is cleared for the next query.
-__device__ __forceinline__ void push_convert_row(const StepParams &p, const PushPlan &pp, int64_t r) {
+// restart term included; it is cleared for the next query.  Returns whether
+// the row is non-zero.
+__device__ __forceinline__ bool push_convert_row(const StepParams &p, const PushPlan &pp, int64_t r) {
     const unsigned long long a = pp.acc[r];
     p.zout[r] = (float)((double)a * 0x1p-62);
     if (a) pp.acc[r] = 0ull;
+    return a != 0ull;
 }
 
 // ------------------------------------------------------------ kt == 1
@@ -391,10 +404,18 @@ __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__re
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (*pp.flag) {
-        // pushed: convert every gather row, coalesced, no work items
+        // pushed: convert every gather row, coalesced, no work items; each
+        // wave covers 64 aligned rows per round and writes their two words
+        // of the frontier bitmap (rows past n are left clear)
         for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.n;
-             r += (int64_t)gridDim.x * blockDim.x)
-            push_convert_row(p, pp, r);
+             r += (int64_t)gridDim.x * blockDim.x) {
+            const uint64_t live = __ballot(push_convert_row(p, pp, r));
+            if (lane == 0) {
+                const int64_t w0 = r >> 5;
+                pp.bits[w0] = (uint32_t)live;
+                if (w0 + 1 < pp.nwords) pp.bits[w0 + 1] = (uint32_t)(live >> 32);
+            }
+        }
         return;
     }
     const int64_t slots = (n_items + kWaves - 1) / kWaves;
@@ -781,19 +802,12 @@ __device__ __forceinline__ long long wave_scan_incl(long long x, int lane) {
 // The first family step of one seed (block 0, one wave), kept compact: F =
 // out(s) + {s} (s appended when it has no self-loop), y1f[f] = y1 of F's
 // f-th node as a gathered value, and the second step's plan: offs =
-// exclusive prefix sums of outdeg over F, ctrl = {W, |F|}, flag =
-// (W <= wmax).  An invalid seed gives an empty plan with the flag clear.
-// The launch's other blocks clear the frontier bitmap.
+// exclusive prefix sums of outdeg over F, est = the first A~ edge of each
+// node of F, ctrl = {W, |F|}, flag = (W <= wmax).  An invalid seed gives an
+// empty plan with the flag clear.
 __global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr,
                                                              const int32_t *a_col, const float *a_w, PushPlan pp) {
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x > 0) {
-        // the other blocks clear the frontier bitmap for the second step
-        for (int64_t i = (blockIdx.x - 1) * (int64_t)blockDim.x + threadIdx.x; i < pp.nwords;
-             i += (int64_t)(gridDim.x - 1) * blockDim.x)
-            pp.bits[i] = 0u;
-        return;
-    }
     const int32_t s = p.seeds[0];
     if (s < 0 || (int64_t)s >= p.n) {
         if (lane == 0) {
@@ -818,7 +832,9 @@ __global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const
             const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
             pp.y1f[e - e0] = a_w ? y : y * p.inv[v];
             self |= (v == s);
-            d = a_rowptr[v + 1] - a_rowptr[v];
+            const int64_t rb = a_rowptr[v];
+            d = a_rowptr[v + 1] - rb;
+            pp.est[e - e0] = rb;
         }
         const long long incl = wave_scan_incl(d, lane);
         if (on) pp.offs[e - e0 + 1] = run + incl;
@@ -830,6 +846,7 @@ __global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const
         if (lane == 0) {
             pp.y1f[nf] = a_w ? p.c : p.c * p.inv[s];
             pp.offs[nf + 1] = run + ds;
+            pp.est[nf] = e0;
         }
         run += ds;
         ++nf;
@@ -844,17 +861,24 @@ __global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const
     }
 }
 
-constexpr int kPushLdsOffs = 2048;  // frontier offsets searched in LDS up to this size
+constexpr int kPushLdsOffs = 2048;  // frontier plan searched in LDS up to this size
 
 // Second family step pushed from F: thread t takes edge slots t, t + T, ...
-// (T threads), finds its frontier node by binary search over offs and adds
-// its term, already in gathered form, to acc[zrow(v)] in 2^62 fixed point.
-// Every term is in [0, 1] and the terms add up to at most the mass of y2,
-// below 1, so the sum cannot overflow.
+// (T threads), finds its frontier node f by binary search over offs, so its
+// edge is est[f] + t - offs[f], and adds the edge's term, already in
+// gathered form, to acc[zrow(v)] in 2^62 fixed point.  Every term is in
+// [0, 1] and the terms add up to at most the mass of y2, below 1, so the sum
+// cannot overflow.  No atomic result is waited for: the conversion that
+// follows finds the non-zero rows.
 __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const int64_t *a_rowptr,
                                                           const int32_t *a_col, const float *a_w, PushPlan pp) {
     __shared__ long long soffs[kPushLdsOffs + 1];
-    if (!*pp.flag) {
+    __shared__ long long sest[kPushLdsOffs];
+    __shared__ float sy[kPushLdsOffs];
+    const int32_t flag = *pp.flag;
+    const int64_t W = pp.ctrl[0];
+    const int64_t nf = pp.ctrl[1];
+    if (!flag) {
         // step 2 will be pulled: y1 densely, as the gathered vector that the
         // step reads (p.zin of the step-2 launches).  Entry v is y1f at v's
         // position in the seed's sorted out-neighbour list, the appended
@@ -880,19 +904,18 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
         }
         return;
     }
-    const int64_t W = pp.ctrl[0];
-    const int64_t nf = pp.ctrl[1];
     const int64_t first = (int64_t)blockIdx.x * blockDim.x;
     if (first >= W) return;
     const bool in_lds = nf <= kPushLdsOffs;
-    if (in_lds)
+    if (in_lds) {
         for (int64_t i = threadIdx.x; i <= nf; i += blockDim.x) soffs[i] = pp.offs[i];
+        for (int64_t i = threadIdx.x; i < nf; i += blockDim.x) {
+            sest[i] = pp.est[i];
+            sy[i] = pp.y1f[i];
+        }
+    }
     __syncthreads();
-    const int32_t s = p.seeds[0];
-    const int64_t es = a_rowptr[s];
-    const int64_t outdeg_s = a_rowptr[s + 1] - es;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) mark_row(pp.bits, zrow(p, s));  // the restart term
     for (int64_t t = first + threadIdx.x; t < W; t += stride) {
         int64_t lo = 0, hi = nf;
         while (hi - lo > 1) {
@@ -902,15 +925,13 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
             else hi = mid;
         }
         const long long olo = in_lds ? soffs[lo] : pp.offs[lo];
-        const int32_t u = lo < outdeg_s ? a_col[es + lo] : s;
-        const int64_t e = a_rowptr[u] + (t - olo);
+        const int64_t e = (in_lds ? sest[lo] : pp.est[lo]) + (t - olo);
+        const float zu = in_lds ? sy[lo] : pp.y1f[lo];
         const int32_t v = a_col[e];
-        const float zu = pp.y1f[lo];
         // (1-c) x1 term of row v, as its gathered value (times 1/outdeg(v)
         // for uniform weights)
         const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
-        const int64_t zr = zrow(p, v);
-        if (atomicAdd(&pp.acc[zr], __double2ull_rn((double)term * 0x1p62)) == 0ull) mark_row(pp.bits, zr);
+        atomicAdd(&pp.acc[zrow(p, v)], __double2ull_rn((double)term * 0x1p62));
     }
 }
 
@@ -1047,7 +1068,7 @@ size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
     const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
-    return a + o + y + 256 + bits_bytes(n);
+    return a + 2 * o + y + 256 + bits_bytes(n);
 }
 
 PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
@@ -1058,10 +1079,11 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
     PushPlan pp;
     pp.acc = reinterpret_cast<unsigned long long *>(b);
     pp.offs = reinterpret_cast<int64_t *>(b + a);
-    pp.y1f = reinterpret_cast<float *>(b + a + o);
-    pp.ctrl = reinterpret_cast<int64_t *>(b + a + o + y);
-    pp.flag = reinterpret_cast<int32_t *>(b + a + o + y + 64);
-    pp.bits = reinterpret_cast<uint32_t *>(b + a + o + y + 256);
+    pp.est = reinterpret_cast<int64_t *>(b + a + o);
+    pp.y1f = reinterpret_cast<float *>(b + a + 2 * o);
+    pp.ctrl = reinterpret_cast<int64_t *>(b + a + 2 * o + y);
+    pp.flag = reinterpret_cast<int32_t *>(b + a + 2 * o + y + 64);
+    pp.bits = reinterpret_cast<uint32_t *>(b + a + 2 * o + y + 256);
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
     return pp;
@@ -1069,9 +1091,7 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
 
 tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
     if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
-    const unsigned clear_blocks = (unsigned)std::min<int64_t>((pp.nwords + 255) / 256, 1024);
-    push_first_plan_kernel<<<1 + clear_blocks, 64, 0, st>>>(p, g->a.rowptr, g->a.col,
-                                                            g->weighted ? g->a.w : nullptr, pp);
+    push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
