@@ -297,6 +297,33 @@ def test_second_step_push_weighted(tpa, torch):
     assert np.abs(res[0] - res[1]).max() <= 1e-6
 
 
+@pytest.mark.parametrize("nn,scale,samples", [(3000, 12, 48000), (37, 6, 300), (64, 6, 500)])
+def test_pushed_frontier_on_ragged_node_counts(tpa, torch, nn, scale, samples):
+    """The conversion after a pushed step 2 writes the frontier bitmap one
+    64-row round at a time; node counts that leave a partial last round
+    (3000 = 46*64 + 56, 37 < 64) or fill it exactly (64) must mark every
+    non-zero row.  A skipped live row would drop its terms from step 3, so
+    the pushed queries must match the pulled ones (no push, no skip) to
+    FP32 rounding element by element, and the oracle in L1."""
+    og = oracle.Graph.rmat(scale, samples, 0xF00 + nn, n_nodes=nn)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(scale, samples, 0xF00 + nn, n_nodes=nn)
+    gg.preprocess(c, T)
+    seeds = [int(s) for s in seeds_for(og, 12, 505)] + [nn - 1, 0]
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    res = []
+    try:
+        for limit in (og.m, 0):
+            gg.set_push_limit(limit)
+            res.append(run_single(gg, torch, sd, S, list(range(len(seeds)))).cpu().numpy().astype(np.float64))
+    finally:
+        gg.set_push_limit(-1)
+    pushed, pulled = res
+    assert np.all(np.abs(pushed - pulled) <= 1e-4 * np.abs(pulled) + 1e-9)
+    expect = np.stack([og.query(s, c, S, T) for s in seeds])
+    assert np.all(l1_rows(pushed, expect) <= TOL)
+
+
 @pytest.mark.parametrize("kt,Sq", [(64, 5), (64, 3), (1, 3)])
 def test_frontier_skip_is_bitwise_neutral(rmat13, torch, kt, Sq):
     """The pull after a pushed first step skips the rows the push left zero.
