@@ -96,10 +96,11 @@ tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStrea
 tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 
 // First family step from seeds (any tile width) pushed over each seed's
-// out-edges of A~: zout = y1 scaled as the gathered vector, zero elsewhere
-// (a fill launch, then one wave per (block, column) seed).  When bits is
-// not null it is cleared first and receives the rows of zout that may be
-// non-zero.
+// out-edges of A~: zout = y1 scaled as the gathered vector (one wave per
+// (block, column) seed).  Without bits every other entry of zout is zeroed
+// by a fill.  With bits, it is cleared, receives the rows of zout that may
+// be non-zero, and only those rows are zeroed and written: the others are
+// left as they were, for a pull that skips them.
 tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, uint32_t *bits,
                              int64_t nwords, hipStream_t st);
 

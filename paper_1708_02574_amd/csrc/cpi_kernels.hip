@@ -82,10 +82,6 @@ __device__ __forceinline__ bool row_live(const StepParams &p, int32_t u) {
     return (p.bits[(uint32_t)u >> 5] >> ((uint32_t)u & 31u)) & 1u;
 }
 
-__device__ __forceinline__ void mark_row(uint32_t *bits, int64_t r) {
-    atomicOr(&bits[r >> 5], 1u << (r & 31));
-}
-
 template <int MODE>
 __device__ __forceinline__ EpiPre epi_load(const StepParams &p, int64_t v) {
     EpiPre q;
@@ -757,19 +753,59 @@ __global__ void fill_zero_kernel(float *z, int64_t n) {
         z[i] = 0.0f;
 }
 
-// First family step from one-hot seeds, pushed over each seed's out-edges:
-// y1 = c e_s + (1-c) c A~^T e_s is non-zero only at s and its out-neighbors
-// (one wave per (block, column) seed; the rest of zout was zero-filled).
-__global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
-                                  int64_t nslots, uint32_t *bits) {
+// Seed of pushed slot w = (block, column), or -1 when the slot holds no
+// valid seed of its block.
+__device__ __forceinline__ int32_t push_slot_seed(const StepParams &p, int64_t w, int &j) {
+    const int64_t b = w / p.ncols;
+    j = (int)(w - b * p.ncols);
+    const int32_t s = p.seeds[b * (p.node_block ? p.seed_stride : 0) + j];
+    if (s < 0 || (int64_t)s >= p.n) return -1;
+    if (p.node_block && p.node_block[s] != b) return -1;
+    return s;
+}
+
+// Claim gather row zr of y1 in the frontier bitmap; the first claimant
+// zeroes the row's kt entries.
+__device__ __forceinline__ void claim_row(const StepParams &p, uint32_t *bits, int64_t zr) {
+    const uint32_t bit = 1u << (zr & 31);
+    if (atomicOr(&bits[zr >> 5], bit) & bit) return;
+    float *row = p.zout + zr * p.kt;
+    if ((p.kt & 3) == 0) {
+        for (int j = 0; j < p.kt; j += 4) *reinterpret_cast<float4 *>(row + j) = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        for (int j = 0; j < p.kt; ++j) row[j] = 0.0f;
+    }
+}
+
+// Rows of y1 for seed tiles with the frontier skip on: every seed row and
+// out-neighbour row is marked in bits (cleared before) and zeroed once, so
+// the push that follows writes into zeroed rows and no unmarked row of
+// zout is ever read (the pull after it skips them).  One wave per slot.
+__global__ void push_first_rows_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, int64_t nslots,
+                                       uint32_t *bits) {
     const int lane = threadIdx.x & 63;
     const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (w >= nslots) return;
-    const int64_t b = w / p.ncols;
-    const int j = (int)(w - b * p.ncols);
-    const int32_t s = p.seeds[b * (p.node_block ? p.seed_stride : 0) + j];
-    if (s < 0 || (int64_t)s >= p.n) return;
-    if (p.node_block && p.node_block[s] != b) return;
+    int j = 0;
+    const int32_t s = push_slot_seed(p, w, j);
+    if (s < 0) return;
+    const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
+    for (int64_t e = e0 + lane; e < e1; e += 64) claim_row(p, bits, zrow(p, a_col[e]));
+    if (lane == 0) claim_row(p, bits, zrow(p, s));
+}
+
+// First family step from one-hot seeds, pushed over each seed's out-edges:
+// y1 = c e_s + (1-c) c A~^T e_s is non-zero only at s and its out-neighbors
+// (one wave per (block, column) seed; the rest of zout was zero-filled, or,
+// with the frontier skip, the rows written here were zeroed).
+__global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
+                                  int64_t nslots) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    if (w >= nslots) return;
+    int j = 0;
+    const int32_t s = push_slot_seed(p, w, j);
+    if (s < 0) return;
     const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
     const float cw = p.c * p.omc;
     bool self = false;
@@ -779,13 +815,11 @@ __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const i
         const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
         const int64_t zr = zrow(p, v);
         p.zout[zr * p.kt + j] = a_w ? y : y * p.inv[v];
-        if (bits) mark_row(bits, zr);
         self |= (v == s);
     }
     if (!__any(self) && lane == 0) {
         const int64_t zr = zrow(p, s);
         p.zout[zr * p.kt + j] = a_w ? p.c : p.c * p.inv[s];
-        if (bits) mark_row(bits, zr);
     }
 }
 
@@ -1052,10 +1086,14 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st) {
 tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, uint32_t *bits,
                              int64_t nwords, hipStream_t st) {
     const int64_t nslots = nblocks * p.ncols;
-    fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
-    if (bits) fill_zero_kernel<<<grid_1d(nwords), 256, 0, st>>>(reinterpret_cast<float *>(bits), nwords);
-    push_first_kernel<<<(unsigned)((nslots * 64 + 255) / 256), 256, 0, st>>>(
-        p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, nslots, bits);
+    const unsigned slot_grid = (unsigned)((nslots * 64 + 255) / 256);
+    if (bits) {
+        fill_zero_kernel<<<grid_1d(nwords), 256, 0, st>>>(reinterpret_cast<float *>(bits), nwords);
+        push_first_rows_kernel<<<slot_grid, 256, 0, st>>>(p, g->a.rowptr, g->a.col, nslots, bits);
+    } else {
+        fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
+    }
+    push_first_kernel<<<slot_grid, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, nslots);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }
