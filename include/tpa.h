@@ -300,8 +300,13 @@ tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, double c, int s_
 /* The k largest entries of each row of vals (row-major [rows][n]), ordered
  * by value descending and, among equal values, index ascending; NaN ranks
  * below every number.  idx_out int32[rows][k], val_out float[rows][k].
- * 1 <= k <= min(n, 1024).  Errors: INVALID_ARG (sizes, NULL), INDEX_OVERFLOW
- * (n or rows above 2^31 - 1), HIP. */
+ * 1 <= k <= min(n, 1024).  Rows are cut into segments of max(4096, 16k)
+ * entries, each keeping its k best, until one segment is left; when that
+ * takes more than one pass the candidate lists live in a device buffer
+ * allocated and freed here, and the call synchronises the stream.  Errors:
+ * INVALID_ARG (sizes, NULL), INDEX_OVERFLOW (n or rows above 2^31 - 1, or
+ * rows times segments above 2^31 - 1), OOM, CAPTURE (a buffer would be
+ * allocated during stream capture), HIP. */
 tpa_status tpa_topk(const float *vals, int64_t rows, int64_t n, int k, int32_t *idx_out, float *val_out,
                     hipStream_t stream);
 

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "cpi_kernels.h"
 #include "tpa_internal.h"
@@ -86,7 +87,6 @@ __device__ __forceinline__ uint32_t order_key(float f) {
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-constexpr int kTopkThreads = 1024;
 constexpr int kTopkMax = 1024;
 
 // hist[bin] += 1 for every active lane.  Lanes of a wave that share a bin
@@ -105,43 +105,76 @@ __device__ __forceinline__ void hist_add(uint32_t *hist, uint32_t bin, bool acti
     if ((pending >> lane) & 1ull) atomicAdd(&hist[bin], 1u);
 }
 
-// One block per row.  A most-significant-digit-first radix select (four 8-bit
-// digits) finds the key K of the k-th largest entry; the entries above K are
-// taken, then those equal to K in index order until k are chosen; a bitonic
-// sort orders the k pairs by (key descending, index ascending).
-__global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, int64_t n, int k, int32_t *idx_out,
-                                                            float *val_out) {
+// One stage of the top-k selection.  Every input row is cut into segments
+// of `seg` entries (seg >= k) and one block takes one segment.  Entry i of
+// row r has key order_key(vals[r*len + i]) and index i on the first stage,
+// keys/idx[r*len + i] on later ones.  A block writes its segment's
+// min(k, segment length) best entries, sorted by (key descending, index
+// ascending), at position segment*k of its output row (row length
+// out_len), or, on the last stage (one segment per row), the final k
+// indices and their values from the original rows.
+struct TopkStage {
+    const float *vals = nullptr;
+    const uint32_t *keys = nullptr;
+    const int32_t *idx = nullptr;
+    int64_t len = 0;
+    int64_t seg = 0;
+    int64_t nseg = 0;
+    int k = 0;
+    uint32_t *out_keys = nullptr;
+    int32_t *out_idx = nullptr;
+    int64_t out_len = 0;
+    const float *orig = nullptr;  // original rows [rows][n]
+    int64_t n = 0;
+    int32_t *idx_out = nullptr;
+    float *val_out = nullptr;
+};
+
+__device__ __forceinline__ uint32_t stage_key(const TopkStage &t, int64_t at) {
+    return t.vals ? order_key(t.vals[at]) : t.keys[at];
+}
+
+// Per block: a most-significant-digit-first radix select (four 8-bit digits)
+// finds the key K of the segment's kk-th best entry; the entries above K are
+// taken, then those equal to K in position order until kk are chosen (on
+// every stage, equal keys sit in index order: segments cover increasing
+// index ranges and each candidate list is sorted); a bitonic sort orders
+// the kk pairs.
+template <int NT>
+__global__ __launch_bounds__(NT) void topk_stage_kernel(TopkStage t) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t s_prefix, s_need, s_count;
     __shared__ uint32_t skey[kTopkMax];
     __shared__ int32_t sidx[kTopkMax];
-    __shared__ uint32_t scan[kTopkThreads];
+    __shared__ uint32_t scan[NT / 64];
     const int tid = threadIdx.x;
-    const float *row = vals + (int64_t)blockIdx.x * n;
+    const int64_t r = (int64_t)blockIdx.x / t.nseg, sg = (int64_t)blockIdx.x - r * t.nseg;
+    const int64_t b0 = sg * t.seg;
+    const int64_t m = min(t.len - b0, t.seg);  // entries of this segment
+    const int kk = (int)min<int64_t>(t.k, m);
+    const int64_t at0 = r * t.len + b0;        // first entry of the segment
     if (tid == 0) {
         s_prefix = 0u;
-        s_need = (uint32_t)k;
+        s_need = (uint32_t)kk;
     }
-    // radix select: after digit d, s_prefix holds the top d digits of K and
-    // s_need the number of entries still to take among those with that prefix
+    constexpr int UL = 8;  // loads in flight per thread
     for (int d = 0; d < 4; ++d) {
         const int shift = 24 - 8 * d;
         const uint32_t mask_hi = d == 0 ? 0u : (0xffffffffu << (shift + 8));
         for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0u;
         __syncthreads();
         const uint32_t prefix = s_prefix;
-        constexpr int UL = 8;  // loads in flight per thread
-        for (int64_t base = 0; base < n; base += (int64_t)blockDim.x * UL) {  // same trip count in every lane
+        for (int64_t base = 0; base < m; base += (int64_t)blockDim.x * UL) {  // same trip count in every lane
             uint32_t key[UL];
 #pragma unroll
             for (int u = 0; u < UL; ++u) {
                 const int64_t v = base + (int64_t)u * blockDim.x + tid;
-                key[u] = v < n ? order_key(row[v]) : 0u;
+                key[u] = v < m ? stage_key(t, at0 + v) : 0u;
             }
 #pragma unroll
             for (int u = 0; u < UL; ++u) {
                 const int64_t v = base + (int64_t)u * blockDim.x + tid;
-                hist_add(hist, (key[u] >> shift) & 255u, v < n && (key[u] & mask_hi) == prefix);
+                hist_add(hist, (key[u] >> shift) & 255u, v < m && (key[u] & mask_hi) == prefix);
             }
         }
         __syncthreads();
@@ -158,45 +191,42 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
         __syncthreads();
     }
     const uint32_t K = s_prefix;
-    const uint32_t take_eq = s_need;  // entries equal to K to take, lowest indices first
+    const uint32_t take_eq = s_need;  // entries equal to K to take, first positions first
     if (tid == 0) s_count = 0u;
     __syncthreads();
-    // entries above K (fewer than k of them), in any order
-    {
-        constexpr int UL = 8;
-        for (int64_t base = 0; base < n; base += (int64_t)blockDim.x * UL) {
-            uint32_t key[UL];
+    // entries above K (fewer than kk of them), in any order
+    for (int64_t base = 0; base < m; base += (int64_t)blockDim.x * UL) {
+        uint32_t key[UL];
 #pragma unroll
-            for (int u = 0; u < UL; ++u) {
-                const int64_t v = base + (int64_t)u * blockDim.x + tid;
-                key[u] = v < n ? order_key(row[v]) : 0u;
-            }
+        for (int u = 0; u < UL; ++u) {
+            const int64_t v = base + (int64_t)u * blockDim.x + tid;
+            key[u] = v < m ? stage_key(t, at0 + v) : 0u;
+        }
 #pragma unroll
-            for (int u = 0; u < UL; ++u) {
-                const int64_t v = base + (int64_t)u * blockDim.x + tid;
-                if (v < n && key[u] > K) {
-                    const uint32_t pos = atomicAdd(&s_count, 1u);
-                    skey[pos] = key[u];
-                    sidx[pos] = (int32_t)v;
-                }
+        for (int u = 0; u < UL; ++u) {
+            const int64_t v = base + (int64_t)u * blockDim.x + tid;
+            if (v < m && key[u] > K) {
+                const uint32_t pos = atomicAdd(&s_count, 1u);
+                skey[pos] = key[u];
+                sidx[pos] = t.vals ? (int32_t)(b0 + v) : t.idx[at0 + v];
             }
         }
     }
     __syncthreads();
     const uint32_t above = s_count;
-    // entries equal to K, the take_eq with the lowest indices: wave w owns the
-    // contiguous segment [w*seg, (w+1)*seg) and walks it 64 entries at a
-    // time (coalesced); a scan of the per-wave counts gives each segment its
-    // first rank, and ballots rank the entries inside a chunk
+    // entries equal to K, the take_eq at the first positions: wave w owns the
+    // contiguous part [w*part, (w+1)*part) and walks it 64 entries at a time
+    // (coalesced); a scan of the per-wave counts gives each part its first
+    // rank, and ballots rank the entries inside a chunk
     {
         const int wv = tid >> 6, lane = tid & 63;
         const int nw = (int)blockDim.x >> 6;
-        const int64_t seg = ((n + nw - 1) / nw + 63) & ~(int64_t)63;
-        const int64_t s0 = (int64_t)wv * seg, s1 = min(n, s0 + seg);
+        const int64_t part = ((m + nw - 1) / nw + 63) & ~(int64_t)63;
+        const int64_t s0 = (int64_t)wv * part, s1 = min(m, s0 + part);
         uint32_t cnt = 0u;
         for (int64_t v0 = s0; v0 < s1; v0 += 64) {
             const int64_t v = v0 + lane;
-            cnt += (uint32_t)__popcll(__ballot(v < s1 && order_key(row[v]) == K));
+            cnt += (uint32_t)__popcll(__ballot(v < s1 && stage_key(t, at0 + v) == K));
         }
         if (lane == 0) scan[wv] = cnt;
         __syncthreads();
@@ -204,22 +234,22 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
         for (int w = 0; w < wv; ++w) rank += scan[w];
         for (int64_t v0 = s0; v0 < s1 && rank < take_eq; v0 += 64) {
             const int64_t v = v0 + lane;
-            const bool eq = v < s1 && order_key(row[v]) == K;
-            const uint64_t m = __ballot(eq);
-            const uint32_t r = rank + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            if (eq && r < take_eq) {
-                skey[above + r] = K;
-                sidx[above + r] = (int32_t)v;
+            const bool eq = v < s1 && stage_key(t, at0 + v) == K;
+            const uint64_t mk = __ballot(eq);
+            const uint32_t rk = rank + (uint32_t)__popcll(mk & ((1ull << lane) - 1ull));
+            if (eq && rk < take_eq) {
+                skey[above + rk] = K;
+                sidx[above + rk] = t.vals ? (int32_t)(b0 + v) : t.idx[at0 + v];
             }
-            rank += (uint32_t)__popcll(m);
+            rank += (uint32_t)__popcll(mk);
         }
     }
     __syncthreads();
-    // bitonic sort of the k pairs (padded to a power of two)
+    // bitonic sort of the kk pairs (padded to a power of two)
     int p2 = 1;
-    while (p2 < k) p2 <<= 1;
+    while (p2 < kk) p2 <<= 1;
     for (int i = tid; i < p2; i += blockDim.x)
-        if (i >= k) {
+        if (i >= kk) {
             skey[i] = 0u;
             sidx[i] = INT32_MAX;
         }
@@ -245,10 +275,18 @@ __global__ __launch_bounds__(kTopkThreads) void topk_kernel(const float *vals, i
             __syncthreads();
         }
     }
-    for (int i = tid; i < k; i += blockDim.x) {
-        const int32_t v = sidx[i];
-        idx_out[(int64_t)blockIdx.x * k + i] = v;
-        val_out[(int64_t)blockIdx.x * k + i] = row[v];
+    if (t.idx_out) {
+        for (int i = tid; i < kk; i += blockDim.x) {
+            const int32_t v = sidx[i];
+            t.idx_out[r * t.k + i] = v;
+            t.val_out[r * t.k + i] = t.orig[r * t.n + v];
+        }
+    } else {
+        const int64_t o = r * t.out_len + sg * t.k;
+        for (int i = tid; i < kk; i += blockDim.x) {
+            t.out_keys[o + i] = skey[i];
+            t.out_idx[o + i] = sidx[i];
+        }
     }
 }
 
@@ -333,10 +371,70 @@ extern "C" tpa_status tpa_topk(const float *vals, int64_t rows, int64_t n, int k
     if (rows == 0) return TPA_OK;
     if (!vals || !idx_out || !val_out) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
     if (n > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "rows longer than 2^31 - 1");
-    if (rows > INT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many rows for one launch");
-    topk_kernel<<<(unsigned)rows, kTopkThreads, 0, st>>>(vals, n, k, idx_out, val_out);
-    TPA_TRY_HIP(hipGetLastError());
-    return TPA_OK;
+    // stages: segments of seg >= 16 k entries, each keeping its k best, so
+    // every stage shrinks the rows at least 16-fold; the last stage has one
+    // segment per row
+    const int64_t seg = std::max<int64_t>(4096, 16 * (int64_t)k);
+    std::vector<int64_t> lens{n};
+    while (lens.back() > seg) {
+        const int64_t len = lens.back(), nseg = (len + seg - 1) / seg;
+        lens.push_back((nseg - 1) * k + std::min<int64_t>(k, len - (nseg - 1) * seg));
+    }
+    for (size_t i = 0; i < lens.size(); ++i) {
+        const int64_t nseg = (lens[i] + seg - 1) / seg;
+        if (rows > INT32_MAX / nseg) return fail(TPA_ERR_INDEX_OVERFLOW, "too many rows for one launch");
+    }
+    // candidate lists of the intermediate stages (keys, then indices), in
+    // one allocation
+    std::vector<uint32_t *> bufs(lens.size() > 1 ? lens.size() - 1 : 0, nullptr);
+    uint32_t *work = nullptr;
+    tpa_status rc = TPA_OK;
+    if (!bufs.empty()) {
+        size_t total = 0;
+        for (size_t i = 1; i < lens.size(); ++i) total += 2 * (size_t)rows * (size_t)lens[i];
+        rc = dalloc(&work, total, st);
+        size_t off = 0;
+        for (size_t i = 1; rc == TPA_OK && i < lens.size(); ++i) {
+            bufs[i - 1] = work + off;
+            off += 2 * (size_t)rows * (size_t)lens[i];
+        }
+    }
+    for (size_t i = 0; i < lens.size() && rc == TPA_OK; ++i) {
+        TopkStage t;
+        if (i == 0) {
+            t.vals = vals;
+        } else {
+            t.keys = bufs[i - 1];
+            t.idx = reinterpret_cast<const int32_t *>(bufs[i - 1] + (size_t)rows * lens[i]);
+        }
+        t.len = lens[i];
+        t.seg = seg;
+        t.nseg = (lens[i] + seg - 1) / seg;
+        t.k = k;
+        if (i + 1 < lens.size()) {
+            t.out_keys = bufs[i];
+            t.out_idx = reinterpret_cast<int32_t *>(bufs[i] + (size_t)rows * lens[i + 1]);
+            t.out_len = lens[i + 1];
+        } else {
+            t.orig = vals;
+            t.n = n;
+            t.idx_out = idx_out;
+            t.val_out = val_out;
+        }
+        // wide blocks when there are few segments, narrow ones when many
+        // fill the device
+        const unsigned grid = (unsigned)(rows * t.nseg);
+        if (grid >= 512) topk_stage_kernel<256><<<grid, 256, 0, st>>>(t);
+        else topk_stage_kernel<1024><<<grid, 1024, 0, st>>>(t);
+        if (hipGetLastError() != hipSuccess) rc = fail(TPA_ERR_HIP, "top-k launch failed");
+    }
+    if (work) {
+        const hipError_t e = hipStreamSynchronize(st);
+        dfree(work);
+        TPA_TRY(rc);
+        TPA_TRY_HIP(e);
+    }
+    return rc;
 }
 
 extern "C" tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, int64_t n, double a, double *out,

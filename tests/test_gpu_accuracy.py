@@ -113,7 +113,8 @@ def test_cpi_argument_errors(rmat13, tpa, torch):
 
 
 @pytest.mark.parametrize("rows,n,k", [(1, 1, 1), (3, 9, 4), (5, 300, 7), (2, 300, 300), (4, 5000, 64),
-                                      (2, 70000, 1024), (3, 1024, 1024), (1, 100000, 1)])
+                                      (2, 70000, 1024), (3, 1024, 1024), (1, 100000, 1),
+                                      (2, 49252, 1024), (1, 300000, 1024), (2, 300000, 10)])
 def test_topk_vs_oracle(tpa, torch, rows, n, k):
     rng = np.random.default_rng(rows * 1000 + n + k)
     pool = np.array([0.5, 0.25, 0.0, -0.0, 1e-7, np.nan, 3.0, -2.0, np.inf], np.float32)
@@ -123,6 +124,25 @@ def test_topk_vs_oracle(tpa, torch, rows, n, k):
     oi, ov = oracle.topk(vals, k)
     assert np.array_equal(idx.cpu().numpy(), oi)
     assert np.array_equal(val.cpu().numpy(), ov, equal_nan=True)
+
+
+@pytest.mark.parametrize("n,k", [(70000, 1000), (300000, 1024), (5000, 17)])
+def test_topk_ties_keep_index_order_across_stages(tpa, torch, n, k):
+    """Rows larger than one segment are reduced in stages; among equal
+    values the smaller indices must survive every stage: a constant row
+    gives indices 0..k-1, and a row of one value with a few larger ones
+    gives those first, then the smallest remaining indices."""
+    const = np.full((1, n), 0.5, np.float32)
+    idx, val = tpa.topk(torch.from_numpy(const), k)
+    assert np.array_equal(idx.cpu().numpy()[0], np.arange(k))
+    assert np.all(val.cpu().numpy() == np.float32(0.5))
+    x = np.full((1, n), 0.25, np.float32)
+    big = np.array([n - 1, n // 2, 7], np.int64)
+    x[0, big] = [3.0, 2.0, 1.0]
+    idx, _ = tpa.topk(torch.from_numpy(x), k)
+    bigset = set(big.tolist())
+    rest = [i for i in range(k) if i not in bigset][:k - 3]
+    assert np.array_equal(idx.cpu().numpy()[0], np.concatenate([big, rest]))
 
 
 def test_topk_on_rwr_rows(rmat13, tpa, torch):
