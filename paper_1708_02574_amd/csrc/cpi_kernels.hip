@@ -400,16 +400,42 @@ __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__re
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (*pp.flag) {
-        // pushed: convert every gather row, coalesced, no work items; each
-        // wave covers 64 aligned rows per round and writes their two words
-        // of the frontier bitmap (rows past n are left clear)
-        for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < p.n;
-             r += (int64_t)gridDim.x * blockDim.x) {
-            const uint64_t live = __ballot(push_convert_row(p, pp, r));
-            if (lane == 0) {
-                const int64_t w0 = r >> 5;
-                pp.bits[w0] = (uint32_t)live;
-                if (w0 + 1 < pp.nwords) pp.bits[w0 + 1] = (uint32_t)(live >> 32);
+        // pushed: convert every gather row, coalesced, no work items.  A wave
+        // takes 256-row spans: lane i converts rows 4i..4i+3 (two 16-byte
+        // loads, one 16-byte store), and lanes 0..7 write the span's eight
+        // words of the frontier bitmap, word w from the 4 bits of lanes
+        // 8w..8w+7 (rows past n are left clear).
+        const bool vec = (reinterpret_cast<uintptr_t>(p.zout) & 15) == 0;
+        const int64_t first = ((int64_t)blockIdx.x * kWaves + wv) * 256;
+        const int64_t step = (int64_t)gridDim.x * kWaves * 256;
+        for (int64_t base = first; base < p.n; base += step) {  // wave-uniform trip count
+            const int64_t r0 = base + 4 * lane;
+            uint32_t live4 = 0u;  // bit k: row r0 + k is non-zero
+            if (vec && r0 + 3 < p.n) {
+                ulonglong2 *a = reinterpret_cast<ulonglong2 *>(pp.acc + r0);
+                const ulonglong2 lo = a[0], hi = a[1];
+                *reinterpret_cast<float4 *>(p.zout + r0) =
+                    make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
+                                (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
+                if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
+                if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
+                live4 = (lo.x != 0ull ? 1u : 0u) | (lo.y != 0ull ? 2u : 0u) | (hi.x != 0ull ? 4u : 0u) |
+                        (hi.y != 0ull ? 8u : 0u);
+            } else {
+                for (int k = 0; k < 4; ++k)
+                    if (r0 + k < p.n && push_convert_row(p, pp, r0 + k)) live4 |= 1u << k;
+            }
+            uint64_t b[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) b[k] = __ballot((live4 >> k) & 1u);
+            if (lane < 8) {
+                uint32_t word = 0u;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) word |= (uint32_t)((b[k] >> (8 * lane + j)) & 1ull) << (4 * j + k);
+                const int64_t w = (base >> 5) + lane;
+                if (w < pp.nwords) pp.bits[w] = word;
             }
         }
         return;
