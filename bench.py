@@ -94,7 +94,9 @@ def cpu_baseline(scale: int, samples: int, seed: int, seeds, n_queries: int):
 def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
     """Untimed context for the JSON line: TPA's accuracy against exact RWR
     on 4 seeds (the paper's error table and top-k recall, computed by the
-    library's kernels), and the adjoint's time for 64 seeds."""
+    library's kernels), the adjoint's time for 64 seeds, and the times of
+    the other device operations: exact RWR of one seed (CPI to eps), top-k
+    of one row, and a batch of 64 dense restart vectors."""
     from paper_1708_02574_amd import accuracy
     print("bench: accuracy report and adjoint timing", file=sys.stderr, flush=True)
     rep = accuracy.error_report(g, seeds_h[:4], C_RESTART, S_FAM, T_STR, 1e-9, ks=(10, 100, 500))
@@ -115,9 +117,24 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
     b.record()
     torch.cuda.synchronize()
     g.set_tuning(seed_tile=0)
-    return {"accuracy": acc, "adjoint": {"seeds": ka, "ms": round(a.elapsed_time(b), 3),
-                                         "note": "gradients w.r.t. edge logits and restart vectors "
-                                                 "(both CPI chains, 64-seed tile)"}}
+    adj_ms = a.elapsed_time(b)
+    s0 = int(seeds_h[0])
+    exact_ms = _time_ms(torch, lambda: g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0))
+    row = g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0)
+    topk_ms = _time_ms(torch, lambda: tpa.topk(row, 100))
+    qd = torch.from_numpy(np.random.default_rng(8).random((64, g.n)).astype(np.float32)).cuda()
+    qd /= qd.sum(dim=1, keepdim=True)
+    outd = torch.empty_like(qd)
+    g.query_dense(qd, C_RESTART, S_FAM, T_STR, out=outd)  # warm-up
+    dense_ms = _time_ms(torch, lambda: g.query_dense(qd, C_RESTART, S_FAM, T_STR, out=outd))
+    return {"accuracy": acc,
+            "adjoint": {"seeds": ka, "ms": round(adj_ms, 3),
+                        "note": "gradients w.r.t. edge logits and restart vectors (both CPI chains, 64-seed tile)"},
+            "ops_ms": {"exact_rwr_one_seed": round(exact_ms, 3), "topk_k100_one_row": round(topk_ms, 3),
+                       "dense_restart_64": round(dense_ms, 3),
+                       "note": "exact RWR = CPI from x(0) = c e_s until c(1-c)^i < 1e-9 (tpa_cpi, synchronous); "
+                               "top-k of one n-entry row (tpa_topk); TPA for 64 dense restart vectors "
+                               "(tpa_query_dense, seed tiles of 16)"}}
 
 
 def _time_ms(torch, fn, reps=3):
