@@ -134,7 +134,7 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
                        "dense_restart_64": round(dense_ms, 3),
                        "note": "exact RWR = CPI from x(0) = c e_s until c(1-c)^i < 1e-9 (tpa_cpi, synchronous); "
                                "top-k of one n-entry row (tpa_topk); TPA for 64 dense restart vectors "
-                               "(tpa_query_dense, seed tiles of 16)"}}
+                               "(tpa_query_dense, automatic seed tile: 64)"}}
 
 
 def _time_ms(torch, fn, reps=3):

@@ -225,7 +225,8 @@ tpa_status tpa_autotune(tpa_graph_t g, const int32_t *seeds, int64_t k, double c
 tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
 
 /* Query tuning: seed-tile width kt (seeds per SpMM pass: 1, 2, 4, 8, 16,
- * 32 or 64; 0 = automatic) and the edge budget of a wave work item that
+ * 32 or 64; 0 = automatic: the next power of two up to 16 for k <= 32
+ * columns, 64 above) and the edge budget of a wave work item that
  * groups short rows (64..1024, a multiple of 64; 0 = automatic, 512 for
  * both the single vector and seed tiles; the single-vector step caps it at
  * 512).  Longer rows are one wave item up to 2x (seed tiles) or 4x (single

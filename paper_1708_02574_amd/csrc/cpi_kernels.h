@@ -44,6 +44,8 @@ struct StepParams {
     int64_t out_col0 = 0;
     int32_t *err = nullptr;            // sticky error flag (invalid seed)
     const float *qdense = nullptr;     // dense restart vectors, seed-major [*, n] (tile offset applied)
+    const float *qT = nullptr;         // the tile's c*q node-major [n][kt] (zero past ncols), when
+                                       // qdense is set on a family query
     float *xs_out = nullptr;           // plain mode: iterate store [n][kt]
     // stranger
     float *acc = nullptr;
@@ -90,7 +92,13 @@ tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, flo
 
 // z0 = c*Q^T tile (node-major, scaled by 1/outdeg for uniform weights) and,
 // when x0 is set, the unscaled x(0) = c*Q tile; columns >= ncols are zero.
+// Reads p.qT when set, else the seed-major p.qdense.
 tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStream_t st);
+
+// qT = c*Q^T for the tile's dense restarts (node-major [n][kt], columns >=
+// ncols zero), through an LDS-tiled transpose: every step's epilogue then
+// reads its restart term with the row's other columns.
+tpa_status launch_dense_transpose(const StepParams &p, float *qT, hipStream_t st);
 
 // x(0) = c*e_seed tile for seed lists (node-major), columns >= ncols zero.
 tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);

@@ -128,7 +128,7 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
         int32_t seed = -1;
         float restart;
         if (p.qdense) {
-            restart = p.c * p.qdense[(int64_t)j * p.n + v];
+            restart = p.qT[v * p.kt + j];
         } else {
             seed = seed_pre != kSeedLookup ? seed_pre : seed_of(p, v, j);
             restart = (v == (int64_t)seed) ? p.c : 0.0f;
@@ -487,7 +487,7 @@ __device__ __forceinline__ float family_out_value(const StepParams &p, int64_t v
     int32_t seed = -1;
     float restart;
     if (p.qdense) {
-        restart = p.c * p.qdense[(int64_t)j * p.n + v];
+        restart = p.qT[v * p.kt + j];
     } else {
         seed = seed_pre != kSeedLookup ? seed_pre : seed_of(p, v, j);
         restart = (v == (int64_t)seed) ? p.c : 0.0f;
@@ -758,9 +758,30 @@ __global__ void dense_init_kernel(StepParams p, float *z0, float *x0) {
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = i / p.kt;
         const int j = (int)(i - v * p.kt);
-        const float x = j < p.ncols ? p.c * p.qdense[(int64_t)j * p.n + v] : 0.0f;
+        const float x = p.qT ? p.qT[i] : (j < p.ncols ? p.c * p.qdense[(int64_t)j * p.n + v] : 0.0f);
         z0[zrow(p, v) * p.kt + j] = p.w ? x : x * p.inv[v];
         if (x0) x0[i] = x;
+    }
+}
+
+// Tile transpose of the dense restarts: a block takes 64 nodes, reads each
+// column's run of 64 entries (coalesced) into LDS and writes the 64 x kt
+// node-major block (coalesced).
+constexpr int kTransNodes = 64;
+
+__global__ __launch_bounds__(256) void dense_transpose_kernel(StepParams p, float *qT) {
+    __shared__ float tile[64][kTransNodes + 1];
+    const int64_t v0 = (int64_t)blockIdx.x * kTransNodes;
+    const int t = threadIdx.x & 63, r = threadIdx.x >> 6;
+    for (int j = r; j < p.kt; j += 4) {
+        const int64_t v = v0 + t;
+        tile[j][t] = (j < p.ncols && v < p.n) ? p.c * p.qdense[(int64_t)j * p.n + v] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t nv = min((int64_t)kTransNodes, p.n - v0);
+    for (int i = threadIdx.x; i < nv * p.kt; i += blockDim.x) {
+        const int vl = i / p.kt, j = i - vl * p.kt;
+        qT[(v0 + vl) * p.kt + j] = tile[j][vl];
     }
 }
 
@@ -1099,6 +1120,15 @@ tpa_status launch_stranger_init(const tpa_graph *g, float c, int include_x0, flo
 
 tpa_status launch_dense_init(const StepParams &p, float *z0, float *x0, hipStream_t st) {
     dense_init_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p, z0, x0);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_dense_transpose(const StepParams &p, float *qT, hipStream_t st) {
+    if (!p.qdense || !qT || p.kt < 1 || p.kt > 64) return fail(TPA_ERR_INVALID_ARG, "dense transpose needs q and kt <= 64");
+    const int64_t blocks = (p.n + kTransNodes - 1) / kTransNodes;
+    if (blocks > UINT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many nodes for one launch");
+    if (blocks > 0) dense_transpose_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, qT);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

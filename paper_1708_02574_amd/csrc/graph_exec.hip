@@ -61,7 +61,7 @@ extern "C" tpa_status tpa_query_graph_create(tpa_graph_t g, const int32_t *seeds
     if ((seeds == nullptr) == (q == nullptr)) return fail(TPA_ERR_INVALID_ARG, "pass exactly one of seeds and q");
     if (!g->preprocessed) return fail(TPA_ERR_NOT_PREPROCESSED, "tpa_preprocess has not run on this graph");
     // schedules and workspace exist before capture (their set-up synchronises)
-    const size_t bytes = query_workspace_bytes(g, k, st);
+    const size_t bytes = query_workspace_bytes(g, k, q != nullptr, st);
     if (bytes == 0) return fail(TPA_ERR_HIP, "could not build the work schedule");
     tpa_query_graph *qg = new tpa_query_graph();
     qg->g = g;

@@ -75,9 +75,14 @@ SchedShape choose_shape(const tpa_graph *g, int kt) {
     return {ew, 2 * ew, ew, 0};
 }
 
+// Automatic seed tile: the next power of two up to 16 for small batches;
+// beyond 32 columns the 64-column walk (one column per lane) is fastest for
+// both seed lists and dense restarts (measured on R-MAT 2^20: 64 seeds in
+// 1.6 ms against 2.9 ms with tiles of 16).
 int choose_kt(const tpa_graph *g, int64_t k) {
     if (g->seed_tile > 0) return g->seed_tile;
     if (k <= 1) return 1;
+    if (k > 32) return 64;
     int kt = 2;
     while (kt < k && kt < 16) kt <<= 1;
     return kt;
@@ -102,11 +107,17 @@ namespace {
 
 // Workspace layout: push state (push_plan_bytes, the same for every tile
 // width, so its all-zero accumulator survives queries of any width) |
-// z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt] (floats)
-size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt) {
+// z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt] | (dense restarts)
+// c*q^T [n*kt] at the next 256-byte boundary (floats)
+size_t query_ws_floats_before_qt(const tpa_graph *g, const Schedule *s, int kt) {
     const size_t zf = (size_t)g->n * kt;
     const size_t pf = (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;
-    return push_plan_bytes(g->n, g->max_outdeg) + sizeof(float) * (2 * zf + pf) + 256;
+    return ((2 * zf + pf) + 63) & ~(size_t)63;
+}
+
+size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, bool dense) {
+    const size_t qf = dense ? (size_t)g->n * kt : 0;
+    return push_plan_bytes(g->n, g->max_outdeg) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) + 256;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -142,11 +153,11 @@ tpa_status check_query_args(tpa_graph *g, double c, int S, int T) {
 
 // Shared driver: `k` columns; restart from seeds [k] (plain) or
 // [nblocks][k] (packed), or from dense seed-major vectors q [k][n].
-size_t query_workspace_bytes(tpa_graph *g, int64_t k, hipStream_t st) {
+size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st) {
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
     if (get_schedule(g, choose_shape(g, kt), st, &s) != TPA_OK) return 0;
-    return query_ws_bytes(g, s, kt);
+    return query_ws_bytes(g, s, kt, dense);
 }
 
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
@@ -160,15 +171,16 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
     if (ws) {
-        if (ws_bytes < query_ws_bytes(g, s, kt)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
+        if (ws_bytes < query_ws_bytes(g, s, kt, q != nullptr)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
     } else {
-        TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt), st));
+        TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt, q != nullptr), st));
         ws = g->ws;
     }
     const PushPlan pp = push_plan_at(ws, g->n, g->max_outdeg, push_wmax(g));
     float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->max_outdeg));
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
+    float *qT = z0 + query_ws_floats_before_qt(g, s, kt);  // used by dense restarts only
     // a single seed whose step 2 is not the last: push steps 1 and 2 from
     // the seed's neighbourhood when it is small, pull otherwise (decided on
     // the device, so the launch sequence is fixed and capturable)
@@ -209,7 +221,12 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             TPA_TRY(launch_combine_only(p, st));
             continue;
         }
-        if (q) TPA_TRY(launch_dense_init(p, z0, nullptr, st));
+        p.qT = nullptr;
+        if (q) {
+            TPA_TRY(launch_dense_transpose(p, qT, st));
+            p.qT = qT;
+            TPA_TRY(launch_dense_init(p, z0, nullptr, st));
+        }
         for (int step = 1; step <= S - 1; ++step) {
             p.zin = (step & 1) ? z0 : z1;
             p.zout = (step & 1) ? z1 : z0;
@@ -357,7 +374,7 @@ extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, kt), nullptr, &s));
-    return ensure_ws(g, query_ws_bytes(g, s, kt), nullptr);
+    return ensure_ws(g, query_ws_bytes(g, s, kt, true), nullptr);  // room for dense restarts too
 }
 
 extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item) {

@@ -161,7 +161,7 @@ SchedShape choose_shape(const tpa_graph *g, int kt);
 // Query driver; ws == nullptr uses (and grows) the handle's workspace.
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
                      int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes);
-size_t query_workspace_bytes(tpa_graph *g, int64_t k, hipStream_t st);
+size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st);
 // Zero the push state at the front of a fresh query workspace.
 tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st);
 tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStream_t stream);

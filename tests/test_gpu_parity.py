@@ -324,6 +324,31 @@ def test_pushed_frontier_on_ragged_node_counts(tpa, torch, nn, scale, samples):
     assert np.all(l1_rows(pushed, expect) <= TOL)
 
 
+@pytest.mark.parametrize("kt", [1, 2, 16, 64])
+def test_dense_restarts_ragged_nodes_and_tiles(tpa, torch, kt):
+    """Dense restart vectors are transposed per tile into a node-major
+    block (64 nodes per transpose block) that every step's epilogue reads:
+    a node count that is not a multiple of 64 (1000) and a batch that
+    leaves a ragged last tile (k = 70) must match the oracle."""
+    og = oracle.Graph.rmat(10, 14000, 0xD15E, n_nodes=1000)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(10, 14000, 0xD15E, n_nodes=1000)
+    gg.preprocess(c, T)
+    rng = np.random.default_rng(77)
+    k = 70
+    Q = rng.random((k, og.n)) * (rng.random((k, og.n)) < 0.05)
+    Q[:, 0] += 1e-3
+    Q /= Q.sum(axis=1, keepdims=True)
+    gg.set_tuning(seed_tile=kt)
+    try:
+        R = gg.query_dense(torch.from_numpy(Q.astype(np.float32)), c, S, T).cpu().numpy()
+    finally:
+        gg.set_tuning(0, 0)
+    for j in (0, 1, kt - 1, kt, k - 1):
+        if j < k:
+            assert l1_rows(R[j], og.query_q(Q[j], c, S, T)) <= TOL, j
+
+
 @pytest.mark.parametrize("kt,Sq", [(64, 5), (64, 3), (1, 3)])
 def test_frontier_skip_is_bitwise_neutral(rmat13, torch, kt, Sq):
     """The pull after a pushed first step skips the rows the push left zero.
