@@ -239,7 +239,8 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * x(2) can be pushed over the out-edges of F = out(s) + {s} instead of
  * pulled over all m edges (the same sum; Section 2.3's CPI step).  The
  * choice is made on the device per query: push when the frontier's edge
- * count W = sum of outdeg over F is at most `max_edges`.  max_edges = -1
+ * count W = sum of outdeg over F is at most `max_edges` and F has at most
+ * 2048 nodes.  max_edges = -1
  * restores the default (m/8, at least 1024), 0 always pulls.  The pushed
  * sums are exact fixed-point additions of FP32 terms, so results are
  * reproducible but may differ from the pulled step in the last bits.
@@ -327,10 +328,10 @@ tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, int64_t n, d
  * (mode 0 = online family step, 1 = preprocessing stranger step, 2 =
  * plain step keeping its iterate, 3 = adjoint step; first = the gather-free
  * first step from one-hot seeds, or for mode 3 = with the edge gradient;
- * weighted = explicit edge weights); codes 120 and 121 are the gated pull
- * of a single seed's second family step (uniform, explicit weights), 124
- * its pushed form (push and convert launches together), and 127 the
- * long-row finish pass.  tpa_profile_read synchronises the
+ * weighted = explicit edge weights); codes 120 and 121 are the gated
+ * launch of a single seed's second family step, which converts the pushed
+ * sums or pulls (uniform, explicit weights), 124 the launch that pushes a
+ * single seed's first two steps, and 127 the long-row finish pass.  tpa_profile_read synchronises the
  * recorded events, adds their durations into per-code totals and returns
  * them (launches timed, milliseconds).  tpa_profile_reset clears the
  * totals.  Errors: INVALID_ARG (capacity outside 1..2^20, sample_period

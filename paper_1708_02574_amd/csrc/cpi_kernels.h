@@ -60,19 +60,14 @@ struct StepParams {
 };
 
 // Device state of the pushed first two family steps of a single seed
-// (kt == 1).  The frontier of step 2 is F = out(s) + {s} (s appended when
-// it has no self-loop); y1f holds y1 on F as gathered values, offs[f] the
-// exclusive prefix sum of outdeg over F, so the push touches W = offs[|F|]
-// edges of A~, and est[f] the first A~ edge of F's f-th node.  acc holds y2
-// in gathered form (scaled by 1/outdeg for uniform weights), indexed by
-// gather row, as fixed point (2^62 units); it is all zero between queries.
+// (kt == 1).  acc holds y2 in gathered form (scaled by 1/outdeg for uniform
+// weights), indexed by gather row, as fixed point (2^62 units); it is all
+// zero between queries.  ctrl = {W, |F|} and flag record the push decision
+// of the query's step 2 (the plan itself lives in each block's LDS).
 struct PushPlan {
     unsigned long long *acc = nullptr;  // [n] by gather row, zero between queries
     uint32_t *bits = nullptr;           // [ceil(n/32)]: rows of the pushed vector that may be non-zero
     int64_t nwords = 0;
-    int64_t *offs = nullptr;            // [max_outdeg + 2]
-    int64_t *est = nullptr;             // [max_outdeg + 1]
-    float *y1f = nullptr;               // [max_outdeg + 1]
     int64_t *ctrl = nullptr;            // {W, |F|}
     int32_t *flag = nullptr;            // 1: step 2 is pushed (the gated step converts acc)
     int64_t wmax = 0;                   // push only when W <= wmax
@@ -112,18 +107,14 @@ tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
 tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nblocks, uint32_t *bits,
                              int64_t nwords, hipStream_t st);
 
-// Single seed (kt == 1, unpacked): the first step kept compact on F (y1f)
-// with the plan of the second step (offs, est, W, |F|, flag = W <= wmax),
-// one wave.
-tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
-
-// Second family step of a single seed pushed over the out-edges of F when
-// the plan's flag is set: the terms of (1-c) A~^T y1, in gathered form,
-// accumulated in fixed point (order-independent, so bitwise reproducible)
-// into acc, which the plan seeded with the restart term c e_s.  With the
-// flag clear it writes y1 densely to p.zin instead, for the pulled second
-// step.
-tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
+// Single seed (kt == 1, unpacked): the first two family steps in one
+// launch.  x(1) is kept on F = out(s) + {s}; when F fits the plan (at most
+// 2048 nodes) and its out-edges number W <= wmax, step 2 is pushed over
+// them into acc (fixed point, order-independent, so bitwise reproducible,
+// with the restart term c e_s) and the flag is set; otherwise y1 is written
+// densely to p.zout (p holds the first step's parameters) for the pulled
+// step 2 and the flag is cleared.
+tpa_status launch_push_steps12(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
 
 // The second family step proper (p.zin = dense y1, p.zout = y2 as the next
 // gathered vector): with the flag set every row is converted from acc (and

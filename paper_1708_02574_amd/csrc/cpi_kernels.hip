@@ -880,96 +880,93 @@ __device__ __forceinline__ long long wave_scan_incl(long long x, int lane) {
     return x;
 }
 
-// The first family step of one seed (block 0, one wave), kept compact: F =
-// out(s) + {s} (s appended when it has no self-loop), y1f[f] = y1 of F's
-// f-th node as a gathered value, and the second step's plan: offs =
-// exclusive prefix sums of outdeg over F, est = the first A~ edge of each
-// node of F, ctrl = {W, |F|}, flag = (W <= wmax).  An invalid seed gives an
-// empty plan with the flag clear.
-__global__ __launch_bounds__(64) void push_first_plan_kernel(StepParams p, const int64_t *a_rowptr,
-                                                             const int32_t *a_col, const float *a_w, PushPlan pp) {
-    const int lane = threadIdx.x & 63;
+constexpr int kPlanMax = 2048;  // frontier nodes a block plans in LDS; larger frontiers pull step 2
+
+__device__ __forceinline__ unsigned long long to_fixed62(float x) { return __double2ull_rn((double)x * 0x1p62); }
+
+// The first two family steps of one seed (kt == 1, unpacked), in one launch.
+// Every block plans step 2 itself, in LDS: F = out(s) + {s} (s appended
+// when it has no self-loop), y1 on F as gathered values (x(1) lives on the
+// seed's out-edges), the first A~ edge of each node of F (est) and the
+// exclusive prefix sums of their out-degrees (offs), W = offs[|F|] edges
+// in all.  When |F| <= kPlanMax and W <= wmax, step 2 is pushed: thread t
+// takes edge slots t, t + T, ... (T threads), finds its node f by binary
+// search over offs, so its edge is est[f] + t - offs[f], and adds the
+// edge's term, in gathered form, to acc[zrow(v)] in 2^62 fixed point; no
+// atomic result is waited for.  Every term is in [0, 1] and they add up to
+// at most the mass of y2, below 1, so the sum cannot overflow.  Block 0
+// records the decision (flag, ctrl = {W, |F|}) and adds the restart term
+// c e_s.  Otherwise y1 is written densely to p.zout (the launch takes the
+// first step's parameters, so that is the vector the pulled step 2 reads;
+// zero for an invalid seed).
+__global__ __launch_bounds__(256) void push_steps12_kernel(StepParams p, const int64_t *a_rowptr,
+                                                           const int32_t *a_col, const float *a_w, PushPlan pp) {
+    __shared__ long long soffs[kPlanMax + 1];
+    __shared__ long long sest[kPlanMax];
+    __shared__ float sy[kPlanMax];
+    __shared__ long long swave[4];
+    __shared__ int sself;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t s = p.seeds[0];
-    if (s < 0 || (int64_t)s >= p.n) {
-        if (lane == 0) {
-            pp.ctrl[0] = 0;
-            pp.ctrl[1] = 0;
-            *pp.flag = 0;
-        }
-        return;
-    }
-    const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
+    const bool valid = s >= 0 && (int64_t)s < p.n;
+    const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
+    const int64_t d = e1 - e0;
+    const bool fits = valid && d < kPlanMax;  // |F| <= d + 1 <= kPlanMax
     const float cw = p.c * p.omc;
-    bool self = false;
     long long run = 0;
-    if (lane == 0) pp.offs[0] = 0;
-    for (int64_t base = e0; base < e1; base += 64) {
-        const int64_t e = base + lane;
-        const bool on = e < e1;
-        long long d = 0;
-        if (on) {
-            const int32_t v = a_col[e];
-            const float wt = a_w ? a_w[e] : p.inv[s];
-            const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
-            pp.y1f[e - e0] = a_w ? y : y * p.inv[v];
-            self |= (v == s);
-            const int64_t rb = a_rowptr[v];
-            d = a_rowptr[v + 1] - rb;
-            pp.est[e - e0] = rb;
+    int nf = 0;
+    if (fits) {
+        if (tid == 0) sself = 0;
+        __syncthreads();
+        for (int base = 0; base < (int)d; base += 256) {  // block-uniform trip count
+            const int f = base + tid;
+            long long deg = 0;
+            if (f < d) {
+                const int32_t v = a_col[e0 + f];
+                const float wt = a_w ? a_w[e0 + f] : p.inv[s];
+                const float y = fmaf(cw, wt, v == s ? p.c : 0.0f);
+                sy[f] = a_w ? y : y * p.inv[v];
+                if (v == s) sself = 1;
+                const int64_t rb = a_rowptr[v];
+                deg = a_rowptr[v + 1] - rb;
+                sest[f] = rb;
+            }
+            const long long incl = wave_scan_incl(deg, lane);
+            if (lane == 63) swave[wv] = incl;
+            __syncthreads();
+            long long before = run;
+            for (int w = 0; w < wv; ++w) before += swave[w];
+            if (f < d) soffs[f] = before + incl - deg;
+            run += swave[0] + swave[1] + swave[2] + swave[3];
+            __syncthreads();  // swave is rewritten next round
         }
-        const long long incl = wave_scan_incl(d, lane);
-        if (on) pp.offs[e - e0 + 1] = run + incl;
-        run += __shfl(incl, 63, 64);
-    }
-    int64_t nf = e1 - e0;
-    if (!__any(self)) {
-        const long long ds = a_rowptr[s + 1] - e0;
-        if (lane == 0) {
-            pp.y1f[nf] = a_w ? p.c : p.c * p.inv[s];
-            pp.offs[nf + 1] = run + ds;
-            pp.est[nf] = e0;
+        nf = (int)d;
+        if (!sself) {
+            if (tid == 0) {
+                sy[nf] = a_w ? p.c : p.c * p.inv[s];
+                sest[nf] = e0;
+                soffs[nf] = run;
+            }
+            run += d;
+            ++nf;
         }
-        run += ds;
-        ++nf;
+        if (tid == 0) soffs[nf] = run;
+        __syncthreads();
     }
-    if (lane == 0) {
-        pp.ctrl[0] = run;
+    const long long W = run;
+    const bool push = fits && W <= pp.wmax;
+    if (blockIdx.x == 0 && tid == 0) {
+        pp.ctrl[0] = W;
         pp.ctrl[1] = nf;
-        const bool push = run <= pp.wmax;
         *pp.flag = push ? 1 : 0;
-        // the restart term of y2 (acc is all zero between queries)
-        if (push) pp.acc[zrow(p, s)] = __double2ull_rn((double)(a_w ? p.c : p.c * p.inv[s]) * 0x1p62);
+        // the restart term of y2 (other blocks may already be adding to the row)
+        if (push) atomicAdd(&pp.acc[zrow(p, s)], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
     }
-}
-
-constexpr int kPushLdsOffs = 2048;  // frontier plan searched in LDS up to this size
-
-// Second family step pushed from F: thread t takes edge slots t, t + T, ...
-// (T threads), finds its frontier node f by binary search over offs, so its
-// edge is est[f] + t - offs[f], and adds the edge's term, already in
-// gathered form, to acc[zrow(v)] in 2^62 fixed point.  Every term is in
-// [0, 1] and the terms add up to at most the mass of y2, below 1, so the sum
-// cannot overflow.  No atomic result is waited for: the conversion that
-// follows finds the non-zero rows.
-__global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const int64_t *a_rowptr,
-                                                          const int32_t *a_col, const float *a_w, PushPlan pp) {
-    __shared__ long long soffs[kPushLdsOffs + 1];
-    __shared__ long long sest[kPushLdsOffs];
-    __shared__ float sy[kPushLdsOffs];
-    const int32_t flag = *pp.flag;
-    const int64_t W = pp.ctrl[0];
-    const int64_t nf = pp.ctrl[1];
-    if (!flag) {
+    if (!push) {
         // step 2 will be pulled: y1 densely, as the gathered vector that the
-        // step reads (p.zin of the step-2 launches).  Entry v is y1f at v's
-        // position in the seed's sorted out-neighbour list, the appended
-        // seed entry, or zero.
-        float *y1 = const_cast<float *>(p.zin);
-        const int32_t s = p.seeds[0];
-        const bool valid = s >= 0 && (int64_t)s < p.n;
-        const int64_t e0 = valid ? a_rowptr[s] : 0, e1 = valid ? a_rowptr[s + 1] : 0;
-        for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < p.n;
-             v += (int64_t)gridDim.x * blockDim.x) {
+        // step reads (the first step's output)
+        float *y1 = p.zout;
+        for (int64_t v = blockIdx.x * (int64_t)blockDim.x + tid; v < p.n; v += (int64_t)gridDim.x * blockDim.x) {
             float val = 0.0f;
             if (valid) {
                 int64_t lo = e0, hi = e1;  // first edge with a_col >= v
@@ -978,41 +975,32 @@ __global__ __launch_bounds__(256) void push_second_kernel(StepParams p, const in
                     if (a_col[mid] < v) lo = mid + 1;
                     else hi = mid;
                 }
-                if (lo < e1 && a_col[lo] == v) val = pp.y1f[lo - e0];
-                else if (v == (int64_t)s) val = pp.y1f[e1 - e0];
+                if (lo < e1 && a_col[lo] == v) {
+                    const float y = fmaf(cw, a_w ? a_w[lo] : p.inv[s], v == (int64_t)s ? p.c : 0.0f);
+                    val = a_w ? y : y * p.inv[v];
+                } else if (v == (int64_t)s) {
+                    val = a_w ? p.c : p.c * p.inv[s];
+                }
             }
             y1[zrow(p, v)] = val;
         }
         return;
     }
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
-    if (first >= W) return;
-    const bool in_lds = nf <= kPushLdsOffs;
-    if (in_lds) {
-        for (int64_t i = threadIdx.x; i <= nf; i += blockDim.x) soffs[i] = pp.offs[i];
-        for (int64_t i = threadIdx.x; i < nf; i += blockDim.x) {
-            sest[i] = pp.est[i];
-            sy[i] = pp.y1f[i];
-        }
-    }
-    __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = first + threadIdx.x; t < W; t += stride) {
-        int64_t lo = 0, hi = nf;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + tid; t < W; t += stride) {
+        int lo = 0, hi = nf;
         while (hi - lo > 1) {
-            const int64_t mid = (lo + hi) >> 1;
-            const long long om = in_lds ? soffs[mid] : pp.offs[mid];
-            if (om <= t) lo = mid;
+            const int mid = (lo + hi) >> 1;
+            if (soffs[mid] <= t) lo = mid;
             else hi = mid;
         }
-        const long long olo = in_lds ? soffs[lo] : pp.offs[lo];
-        const int64_t e = (in_lds ? sest[lo] : pp.est[lo]) + (t - olo);
-        const float zu = in_lds ? sy[lo] : pp.y1f[lo];
+        const int64_t e = sest[lo] + (t - soffs[lo]);
+        const float zu = sy[lo];
         const int32_t v = a_col[e];
         // (1-c) x1 term of row v, as its gathered value (times 1/outdeg(v)
         // for uniform weights)
         const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
-        atomicAdd(&pp.acc[zrow(p, v)], __double2ull_rn((double)term * 0x1p62));
+        atomicAdd(&pp.acc[zrow(p, v)], to_fixed62(term));
     }
 }
 
@@ -1159,44 +1147,32 @@ size_t bits_bytes(int64_t n) { return (((size_t)(n + 31) / 32) * 4 + 255) & ~(si
 }  // namespace
 
 size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
+    (void)max_outdeg;
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
-    const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
-    const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
-    return a + 2 * o + y + 256 + bits_bytes(n);
+    return a + 256 + bits_bytes(n);
 }
 
 PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
+    (void)max_outdeg;
     char *b = static_cast<char *>(base);
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
-    const size_t o = ((size_t)(max_outdeg + 2) * 8 + 255) & ~(size_t)255;
-    const size_t y = ((size_t)(max_outdeg + 2) * 4 + 255) & ~(size_t)255;
     PushPlan pp;
     pp.acc = reinterpret_cast<unsigned long long *>(b);
-    pp.offs = reinterpret_cast<int64_t *>(b + a);
-    pp.est = reinterpret_cast<int64_t *>(b + a + o);
-    pp.y1f = reinterpret_cast<float *>(b + a + 2 * o);
-    pp.ctrl = reinterpret_cast<int64_t *>(b + a + 2 * o + y);
-    pp.flag = reinterpret_cast<int32_t *>(b + a + 2 * o + y + 64);
-    pp.bits = reinterpret_cast<uint32_t *>(b + a + 2 * o + y + 256);
+    pp.ctrl = reinterpret_cast<int64_t *>(b + a);
+    pp.flag = reinterpret_cast<int32_t *>(b + a + 64);
+    pp.bits = reinterpret_cast<uint32_t *>(b + a + 256);
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
     return pp;
 }
 
-tpa_status launch_push_first_plan(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
-    if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
-    push_first_plan_kernel<<<1, 64, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, pp);
-    TPA_TRY_HIP(hipGetLastError());
-    return TPA_OK;
-}
-
-tpa_status launch_push_second(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
-    if (p.kt != 1 || p.node_block) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
+tpa_status launch_push_steps12(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
+    if (p.kt != 1 || p.node_block || !p.seeds) return fail(TPA_ERR_INVALID_ARG, "push plan needs a single unpacked seed");
     // grid-stride over the W edge slots: about 16 slots per thread up to the bound
     const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (pp.wmax + 16 * 256 - 1) / (16 * 256)), 4096);
     const int slot = profile_begin(124, st);
-    push_second_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr,
-                                                         pp);
+    push_steps12_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr,
+                                                          pp);
     profile_end(slot, st);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;

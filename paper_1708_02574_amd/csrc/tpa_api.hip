@@ -233,14 +233,13 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             p.last = step == S - 1;
             if (step == 1 && !q && !p.last) {
                 // one-hot restarts: x(1) lives on the seeds' out-edges; push it
-                if (push2) TPA_TRY(launch_push_first_plan(p, g, pp, st));
+                if (push2) TPA_TRY(launch_push_steps12(p, g, pp, st));  // steps 1 and 2
                 else TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, frontier ? pp.bits : nullptr,
                                                pp.nwords, st));
                 continue;
             }
             if (step == 2 && push2) {
-                tpa_status rc = launch_push_second(p, g, pp, st);
-                if (rc == TPA_OK) rc = launch_gated_step(*s, p, pp, st);
+                tpa_status rc = launch_gated_step(*s, p, pp, st);
                 if (rc != TPA_OK) {
                     // the conversion that clears acc may not have run: restore
                     // the all-zero push state before reporting the error

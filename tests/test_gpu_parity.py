@@ -297,6 +297,35 @@ def test_second_step_push_weighted(tpa, torch):
     assert np.abs(res[0] - res[1]).max() <= 1e-6
 
 
+def test_push_plan_size_limit(tpa, torch):
+    """Each block of the pushed first two steps plans the seed's frontier
+    F = out(s) + {s} in LDS, up to 2048 nodes.  Seeds with 2047 out-edges
+    (F fills the plan exactly), 2048 and 3000 (the plan does not fit: step 2
+    is pulled) and a few out-edges must all match the oracle, under a push
+    limit that admits every frontier."""
+    rng = np.random.default_rng(99)
+    n = 5000
+    src = [np.zeros(3000, np.int64), np.full(2047, 1), np.full(2048, 2)]
+    dst = [np.arange(1, 3001), np.arange(1001, 3048), np.arange(2000, 4048)]
+    rest = np.arange(3, n)
+    src.append(np.repeat(rest, 3))
+    dst.append(rng.integers(0, n, size=3 * rest.size))
+    src, dst = np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+    og = oracle.Graph(n, src, dst)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    gg.preprocess(c, T)
+    seeds = [0, 1, 2, 17, 4999]
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    gg.set_push_limit(og.m)
+    try:
+        R = run_single(gg, torch, sd, S, list(range(len(seeds)))).cpu().numpy()
+    finally:
+        gg.set_push_limit(-1)
+    expect = np.stack([og.query(s, c, S, T) for s in seeds])
+    assert np.all(l1_rows(R, expect) <= TOL), l1_rows(R, expect)
+
+
 @pytest.mark.parametrize("nn,scale,samples", [(3000, 12, 48000), (37, 6, 300), (64, 6, 500)])
 def test_pushed_frontier_on_ragged_node_counts(tpa, torch, nn, scale, samples):
     """The conversion after a pushed step 2 writes the frontier bitmap one
