@@ -116,8 +116,29 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
     g.backward(gv, C_RESTART, S_FAM, T_STR, seeds=seeds[:ka])
     b.record()
     torch.cuda.synchronize()
+    # a second run times every launch of the single-vector adjoint step with
+    # the edge gradient (the stranger chain's K steps) on its stream
+    tpa.profile_enable(True, 4096, 1)
+    tpa.profile_reset()
+    g.backward(gv, C_RESTART, S_FAM, T_STR, seeds=seeds[:ka])
+    torch.cuda.synchronize()
+    adj_launches, adj_kms = tpa.profile_read(tpa.profile_code(1, 3, True, False))
+    tpa.profile_enable(False)
     g.set_tuning(seed_tile=0)
     adj_ms = a.elapsed_time(b)
+    n, m = g.n, g.m
+    # algorithmic bytes of one step: A~'s row offsets and columns, the edge
+    # gradient read and written, lambda(i) gathered once, x(i-1), the loss
+    # weights, 1/outdeg and lambda(i-1) written
+    adj_bytes = 8 * (n + 1) + 4 * m + 8 * m + 4 * n * 5
+    adj_us = adj_kms * 1e3 / adj_launches if adj_launches else None
+    adj_roof = None
+    if adj_us:
+        achieved = adj_bytes / (adj_us * 1e-6) / 1e9
+        adj_roof = {"kernel": "adj_kernel_1<1/outdeg, edge gradient> (stranger-chain adjoint step)", "bound": "hbm",
+                    "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_launch": adj_bytes,
+                    "avg_launch_us": round(adj_us, 2), "launches_timed": adj_launches}
     s0 = int(seeds_h[0])
     exact_ms = _time_ms(torch, lambda: g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0))
     row = g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0)
@@ -129,7 +150,8 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
     dense_ms = _time_ms(torch, lambda: g.query_dense(qd, C_RESTART, S_FAM, T_STR, out=outd))
     return {"accuracy": acc,
             "adjoint": {"seeds": ka, "ms": round(adj_ms, 3),
-                        "note": "gradients w.r.t. edge logits and restart vectors (both CPI chains, 64-seed tile)"},
+                        "note": "gradients w.r.t. edge logits and restart vectors (both CPI chains, 64-seed tile)",
+                        "roofline": adj_roof},
             "ops_ms": {"exact_rwr_one_seed": round(exact_ms, 3), "topk_k100_one_row": round(topk_ms, 3),
                        "dense_restart_64": round(dense_ms, 3),
                        "note": "exact RWR = CPI from x(0) = c e_s until c(1-c)^i < 1e-9 (tpa_cpi, synchronous); "
