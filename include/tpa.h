@@ -299,6 +299,20 @@ tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t stream);
 tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, double c, int s_iter, int t_iter, double eps,
                    float *out, hipStream_t stream);
 
+/* tpa_cpi for k restarts at once, on seed tiles of the automatic width
+ * (the batched form of the same CPI steps): seeds int32[k] (device, q NULL)
+ * or dense restart vectors q float[k][n] (device, seed-major, seeds NULL).
+ * Row j of out float[k][n] is restart j's window sum over s_iter <= i <=
+ * t_iter, each restart with its own last iteration (min of t_iter and the
+ * first i with c (1-c)^i ||q_j||_1 < eps).  A seed outside [0, n) gives an
+ * all-NaN row and sets the sticky error of tpa_get_device_error.
+ * Synchronous (it allocates and frees its work tiles: five [n][kt] float
+ * tiles with dense q, four with seeds).  k = 0 does nothing.  Errors:
+ * INVALID_ARG (k < 0; for k > 0, not exactly one of seeds and q, or out
+ * NULL; the tpa_cpi parameter checks), OOM, HIP. */
+tpa_status tpa_cpi_batch(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k, double c, int s_iter,
+                         int t_iter, double eps, float *out, hipStream_t stream);
+
 /* The k largest entries of each row of vals (row-major [rows][n]), ordered
  * by value descending and, among equal values, index ascending; NaN ranks
  * below every number.  idx_out int32[rows][k], val_out float[rows][k].

@@ -64,6 +64,7 @@ _SIGS = {
     "tpa_get_push_limit": (_i, [_vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
     "tpa_cpi": (_i, [_vp, C.c_int32, _vp, _d, _i, _i, _d, _vp, _vp]),
+    "tpa_cpi_batch": (_i, [_vp, _vp, _vp, _i64, _d, _i, _i, _d, _vp, _vp]),
     "tpa_topk": (_i, [_vp, _i64, _i64, _i, _vp, _vp, _vp]),
     "tpa_row_l1": (_i, [_vp, _vp, _i64, _i64, _d, _vp, _vp]),
     "tpa_profile_enable": (_i, [_i, _i, _i]),
@@ -306,6 +307,29 @@ class Graph:
             out = torch.empty(self.n, dtype=torch.float32, device="cuda")
         _call("tpa_cpi", self._h, -1 if seed is None else int(seed), None if qd is None else _ptr(qd), c, s_iter,
               t_iter, eps, _ptr(out), _stream(stream))
+        return out
+
+    def cpi_batch(self, c: float, s_iter: int, t_iter: int = -1, eps: float = 1e-9, seeds=None, q=None, out=None,
+                  stream=None):
+        """Algorithm 1 for k restarts at once (seeds [k], or dense q [k, n]),
+        on seed tiles: row j is the sum of x(i) over s_iter <= i <= t_iter
+        for restart j, each with its own eps break.  Returns float32 [k, n]."""
+        torch = _torch()
+        if (seeds is None) == (q is None):
+            raise ValueError("pass exactly one of seeds and q")
+        sd = qd = None
+        if seeds is not None:
+            sd = seeds.to(device="cuda", dtype=torch.int32).contiguous().reshape(-1)
+            k = sd.numel()
+        else:
+            qd = q.to(device="cuda", dtype=torch.float32).contiguous()
+            if qd.dim() != 2 or qd.shape[1] != self.n:
+                raise ValueError("q must be [k, n]")
+            k = qd.shape[0]
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.float32, device="cuda")
+        _call("tpa_cpi_batch", self._h, None if sd is None else _ptr(sd), None if qd is None else _ptr(qd), k, c,
+              s_iter, t_iter, eps, _ptr(out), _stream(stream))
         return out
 
     def query_dense(self, q, c: float, S: int, T: int, out=None, stream=None):

@@ -17,8 +17,8 @@ and 2(1-c)^S for r_TPA (Theorem 2).  Recall@k is |top-k(r_TPA) and
 top-k(r_exact)| / k with ties broken by node id.
 
 Every vector and every L1 distance is computed by the library's kernels
-(tpa_cpi, tpa_query, tpa_row_l1, tpa_topk); only the set intersection of
-the two top-k lists is taken on the host.
+(tpa_cpi_batch, tpa_query, tpa_row_l1, tpa_topk); only the set
+intersection of the two top-k lists is taken on the host.
 """
 from __future__ import annotations
 
@@ -35,35 +35,35 @@ def error_bounds(c: float, S: int, T: int) -> dict:
 def error_report(g: Graph, seeds, c: float, S: int, T: int, eps: float = 1e-9, ks=(10, 100, 500)) -> list[dict]:
     """Per seed: L1 errors of r~_neighbor, r~_stranger and r_TPA against the
     exact parts, and recall of r_TPA's top-k for each k in ks.  The graph
-    must be preprocessed with (c, T)."""
+    must be preprocessed with (c, T).  The exact parts of all seeds are
+    computed together (tpa_cpi_batch); r_TPA by one single-seed query each."""
     import torch
 
+    seeds = [int(x) for x in seeds]
+    sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
     scale = ((1.0 - c) ** S - (1.0 - c) ** T) / (1.0 - (1.0 - c) ** S)
     stranger = g.stranger()
+    exact = g.cpi_batch(c, 0, -1, eps, seeds=sd)
+    st = g.cpi_batch(c, T, -1, eps, seeds=sd)
+    r = torch.stack([g.query(sd[i:i + 1], c, S, T)[0] for i in range(len(seeds))])
+    nb_err = [0.0] * len(seeds)  # S == T: the neighbor part is empty
+    if S < T:
+        fam = g.cpi_batch(c, 0, S - 1, eps, seeds=sd)
+        nb = g.cpi_batch(c, S, T - 1, eps, seeds=sd)
+        nb_err = row_l1(fam, nb, a=scale).cpu().tolist()
+    st_err = row_l1(stranger.expand(len(seeds), -1).contiguous(), st).cpu().tolist()
+    tpa_err = row_l1(r, exact).cpu().tolist()
+    tops = {}
+    for k in ks:
+        k = min(int(k), g.n)
+        ia, _ = topk(r, k)
+        ib, _ = topk(exact, k)
+        tops[k] = (ia.cpu().tolist(), ib.cpu().tolist())
     out = []
-    for s in [int(x) for x in seeds]:
-        exact = g.cpi(c, 0, -1, eps, seed=s)
-        st = g.cpi(c, T, -1, eps, seed=s)
-        r = g.query(torch.tensor([s], dtype=torch.int32, device="cuda"), c, S, T)[0]
-        nb_err = 0.0  # S == T: the neighbor part is empty
-        if S < T:
-            fam = g.cpi(c, 0, S - 1, eps, seed=s)
-            nb = g.cpi(c, S, T - 1, eps, seed=s)
-            nb_err = float(row_l1(fam, nb, a=scale)[0])
-        err = {
-            "neighbor": nb_err,
-            "stranger": float(row_l1(stranger, st)[0]),
-            "tpa": float(row_l1(r, exact)[0]),
-        }
-        rec = {}
-        for k in ks:
-            k = min(int(k), g.n)
-            ia, _ = topk(r, k)
-            ib, _ = topk(exact, k)
-            a = set(ia[0].cpu().tolist())
-            b = set(ib[0].cpu().tolist())
-            rec[k] = len(a & b) / k
-        out.append({"seed": s, "l1": err, "recall": rec})
+    for i, s in enumerate(seeds):
+        rec = {k: len(set(a[i]) & set(b[i])) / k for k, (a, b) in tops.items()}
+        out.append({"seed": s, "l1": {"neighbor": float(nb_err[i]), "stranger": float(st_err[i]),
+                                      "tpa": float(tpa_err[i])}, "recall": rec})
     return out
 
 
@@ -83,7 +83,7 @@ def st_sweep(g: Graph, seeds, c: float, pairs, eps: float = 1e-9, reps: int = 3)
 
     seeds = [int(x) for x in seeds]
     sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
-    exact = torch.stack([g.cpi(c, 0, -1, eps, seed=s) for s in seeds])
+    exact = g.cpi_batch(c, 0, -1, eps, seeds=sd)
     out = torch.empty_like(exact)
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     rows = []
@@ -94,8 +94,8 @@ def st_sweep(g: Graph, seeds, c: float, pairs, eps: float = 1e-9, reps: int = 3)
         b.record()
         torch.cuda.synchronize()
         pre_ms = a.elapsed_time(b)
-        stranger = g.stranger()
-        st_err = [float(row_l1(stranger, g.cpi(c, T, -1, eps, seed=s))[0]) for s in seeds]
+        stranger = g.stranger().expand(len(seeds), -1).contiguous()
+        st_err = row_l1(stranger, g.cpi_batch(c, T, -1, eps, seeds=sd)).cpu().tolist()
         for S in sorted({int(s) for s, t in pairs if int(t) == T}):
             best = float("inf")
             for _ in range(reps):
@@ -109,8 +109,8 @@ def st_sweep(g: Graph, seeds, c: float, pairs, eps: float = 1e-9, reps: int = 3)
             scale = ((1.0 - c) ** S - (1.0 - c) ** T) / (1.0 - (1.0 - c) ** S)
             nb_err = [0.0] * len(seeds)
             if S < T:
-                nb_err = [float(row_l1(g.cpi(c, 0, S - 1, eps, seed=s), g.cpi(c, S, T - 1, eps, seed=s),
-                                       a=scale)[0]) for s in seeds]
+                nb_err = row_l1(g.cpi_batch(c, 0, S - 1, eps, seeds=sd), g.cpi_batch(c, S, T - 1, eps, seeds=sd),
+                                a=scale).cpu().tolist()
             rows.append({"S": S, "T": T, "l1_mean": sum(err) / len(err), "l1_max": max(err),
                          "l1_neighbor": sum(nb_err) / len(nb_err), "l1_stranger": sum(st_err) / len(st_err),
                          "bound": 2 * (1.0 - c) ** S, "us_per_query": best * 1e3 / len(seeds),

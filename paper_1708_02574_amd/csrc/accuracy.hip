@@ -34,18 +34,20 @@ __global__ void cpi_init_kernel(int64_t n, float c, int32_t seed, const float *q
     }
 }
 
-// sum_v |q[v]| in FP64, one block, fixed order.
+// sum_v |q[v]| in FP64 for row blockIdx.x of q [rows][n], one block per
+// row, fixed order.
 __global__ void l1_norm_kernel(const float *q, int64_t n, double *out) {
     __shared__ double red[256];
+    const float *qr = q + (int64_t)blockIdx.x * n;
     double s = 0.0;
-    for (int64_t v = threadIdx.x; v < n; v += blockDim.x) s += fabs((double)q[v]);
+    for (int64_t v = threadIdx.x; v < n; v += blockDim.x) s += fabs((double)qr[v]);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = 128; off >= 1; off >>= 1) {
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = red[0];
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
 }
 
 // Per-row L1 distance in two fixed-order passes: block (row, b) of a
@@ -359,6 +361,126 @@ extern "C" tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, doubl
     }
     const hipError_t e = hipStreamSynchronize(st);
     dfree(tmp);
+    TPA_TRY(rc);
+    TPA_TRY_HIP(e);
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_cpi_batch(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k, double c,
+                                    int s_iter, int t_iter, double eps, float *out, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
+    if (!(c > 0.0 && c < 1.0)) return fail(TPA_ERR_INVALID_ARG, "c must lie in (0, 1)");
+    if (s_iter < 0 || t_iter < -1 || (t_iter >= 0 && t_iter < s_iter))
+        return fail(TPA_ERR_INVALID_ARG, "need 0 <= s_iter <= t_iter, or t_iter = -1");
+    if (!(eps >= 0.0) || (eps == 0.0 && t_iter < 0))
+        return fail(TPA_ERR_INVALID_ARG, "eps must be >= 0, and > 0 without a last iteration");
+    if (k == 0) return TPA_OK;
+    if ((seeds == nullptr) == (q == nullptr)) return fail(TPA_ERR_INVALID_ARG, "pass exactly one of seeds and q");
+    if (!out) return fail(TPA_ERR_INVALID_ARG, "out is NULL");
+    const int64_t n = g->n;
+    // per restart j: Algorithm 1's last iteration min(t_iter, first i with
+    // c (1-c)^i ||q_j||_1 < eps), as in tpa_cpi
+    std::vector<double> qn((size_t)k, 1.0);
+    if (q && eps > 0.0) {
+        double *d = nullptr;
+        TPA_TRY(dalloc(&d, (size_t)k, st));
+        hipError_t e = hipSuccess;
+        for (int64_t r0 = 0; r0 < k && e == hipSuccess; r0 += 65535) {
+            const int64_t rr = std::min<int64_t>(65535, k - r0);
+            l1_norm_kernel<<<(unsigned)rr, 256, 0, st>>>(q + r0 * n, n, d + r0);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(qn.data(), d, sizeof(double) * k, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        dfree(d);
+        TPA_TRY_HIP(e);
+    }
+    std::vector<int32_t> klast((size_t)k);
+    for (int64_t j = 0; j < k; ++j) {
+        int64_t K = t_iter >= 0 ? t_iter : INT64_MAX;
+        if (eps > 0.0) K = qn[j] > 0.0 ? std::min<int64_t>(K, stranger_last_iteration(c, eps / qn[j])) : 0;
+        klast[j] = (int32_t)std::min<int64_t>(K, INT32_MAX);
+    }
+    const int kt = choose_kt(g, k);
+    const Schedule *s = nullptr;
+    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
+    if (g->gather_layout) {
+        TPA_TRY(ensure_zlayout(g, st));
+        TPA_TRY(ensure_wz(g, st));
+    }
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    const size_t tile = (size_t)n * kt;
+    float *buf = nullptr;
+    const size_t nbuf = 4 * tile + (q ? tile : 0) + (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;
+    TPA_TRY(dalloc(&buf, nbuf, st));
+    int32_t *kd = nullptr;
+    if (dalloc(&kd, 64, st) != TPA_OK) {
+        dfree(buf);
+        return TPA_ERR_OUT_OF_MEMORY;
+    }
+    float *z0 = buf, *z1 = buf + tile, *acc = buf + 2 * tile, *comp = buf + 3 * tile;
+    float *qT = q ? buf + 4 * tile : nullptr;
+    float *part = buf + 4 * tile + (q ? tile : 0);
+    StepParams p;
+    p.rowptr = g->t.rowptr;
+    p.zperm = hub ? g->zperm : nullptr;
+    p.inv = g->inv_deg;
+    p.partials = part;
+    p.omc = (float)(1.0 - c);
+    p.c = (float)c;
+    p.kt = kt;
+    p.n = n;
+    p.tacc = acc;
+    p.tcomp = comp;
+    p.klast = kd;
+    p.s_iter = s_iter;
+    const int32_t *col_gather = hub ? g->t_colz : g->t.col;
+    const float *w_gather = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
+    tpa_status rc = TPA_OK;
+    int32_t kh[64];
+    for (int64_t base = 0; rc == TPA_OK && base < k; base += kt) {
+        const int ncols = (int)std::min<int64_t>(kt, k - base);
+        int64_t K = 0;
+        for (int j = 0; j < kt; ++j) {
+            kh[j] = j < ncols ? klast[base + j] : -1;
+            K = std::max<int64_t>(K, kh[j]);
+        }
+        if (hipMemcpyAsync(kd, kh, sizeof(int32_t) * kt, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {  // kh is reused by the next tile
+            rc = fail(TPA_ERR_HIP, "klast upload failed");
+            break;
+        }
+        p.seeds = seeds ? seeds + base : nullptr;
+        p.qdense = q ? q + base * n : nullptr;
+        p.ncols = ncols;
+        p.qT = nullptr;
+        // x(0) into the window sum when s_iter = 0; for dense restarts also
+        // the vector step 1 reads (one-hot first steps gather nothing)
+        if (q) {
+            rc = launch_dense_transpose(p, qT, st);
+            p.qT = qT;
+            if (rc == TPA_OK) rc = launch_dense_init(p, z0, s_iter == 0 ? acc : nullptr, st);
+        } else if (s_iter == 0) {
+            rc = launch_onehot_init(p, acc, st);
+        }
+        if (rc == TPA_OK && s_iter != 0) rc = launch_fill_zero(acc, (int64_t)tile, st);
+        if (rc == TPA_OK) rc = launch_fill_zero(comp, (int64_t)tile, st);
+        p.qT = nullptr;  // plain steps add no restart
+        for (int64_t i = 1; rc == TPA_OK && i <= K; ++i) {
+            p.zin = (i & 1) ? z0 : z1;
+            p.zout = (i & 1) ? z1 : z0;
+            p.iter = (int)i;
+            const bool first = i == 1 && !q;  // one-hot restarts: x(1) needs no gather
+            p.col = first ? g->t.col : col_gather;
+            p.w = first ? (g->weighted ? g->t.w : nullptr) : w_gather;
+            rc = launch_step(*s, kPlain, first, p, st);
+        }
+        if (rc == TPA_OK) rc = launch_tile_to_rows(acc, kt, ncols, n, p.seeds, out, base, g->dev_err, st);
+    }
+    const hipError_t e = hipStreamSynchronize(st);
+    dfree(buf);
+    dfree(kd);
     TPA_TRY(rc);
     TPA_TRY_HIP(e);
     return TPA_OK;

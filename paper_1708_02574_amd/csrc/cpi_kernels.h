@@ -47,6 +47,14 @@ struct StepParams {
     const float *qT = nullptr;         // the tile's c*q node-major [n][kt] (zero past ncols), when
                                        // qdense is set on a family query
     float *xs_out = nullptr;           // plain mode: iterate store [n][kt]
+    // plain mode, batched window sums: column j adds x(iter) into tacc
+    // (Kahan, compensation tcomp; both node-major [n][kt]) when
+    // s_iter <= iter <= klast[j]
+    float *tacc = nullptr;
+    float *tcomp = nullptr;
+    const int32_t *klast = nullptr;
+    int iter = 0;
+    int s_iter = 0;
     // stranger
     float *acc = nullptr;
     float *comp = nullptr;
@@ -97,6 +105,15 @@ tpa_status launch_dense_transpose(const StepParams &p, float *qT, hipStream_t st
 
 // x(0) = c*e_seed tile for seed lists (node-major), columns >= ncols zero.
 tpa_status launch_onehot_init(const StepParams &p, float *x0, hipStream_t st);
+
+// z[0..n) = 0 with a fill kernel (capturable, unlike a memset node).
+tpa_status launch_fill_zero(float *z, int64_t n, hipStream_t st);
+
+// out[(col0 + j) * n + v] = tile[v * kt + j] for j < ncols (seed-major rows
+// from a node-major tile).  With seeds, a column whose seed lies outside
+// [0, n) becomes NaN and raises the sticky error flag *err.
+tpa_status launch_tile_to_rows(const float *tile, int kt, int ncols, int64_t n, const int32_t *seeds, float *out,
+                               int64_t col0, int32_t *err, hipStream_t st);
 
 // First family step from seeds (any tile width) pushed over each seed's
 // out-edges of A~: zout = y1 scaled as the gathered vector (one wave per

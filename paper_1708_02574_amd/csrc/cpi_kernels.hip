@@ -149,6 +149,14 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
     } else if (MODE == kPlain) {
         const float x = p.omc * sum;
         if (p.xs_out) p.xs_out[v * p.kt + j] = x;
+        if (p.tacc && p.iter >= p.s_iter && p.iter <= p.klast[j]) {
+            // Kahan-compensated window sum of column j
+            const int64_t i = v * p.kt + j;
+            const float b = p.tacc[i], yk = x - p.tcomp[i];
+            const float t = b + yk;
+            p.tcomp[i] = (t - b) - yk;
+            p.tacc[i] = t;
+        }
         p.zout[(int64_t)q.zi * p.kt + j] = p.w ? x : x * q.a;
     } else {
         const float x = p.omc * sum;
@@ -1117,6 +1125,48 @@ tpa_status launch_dense_transpose(const StepParams &p, float *qT, hipStream_t st
     const int64_t blocks = (p.n + kTransNodes - 1) / kTransNodes;
     if (blocks > UINT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many nodes for one launch");
     if (blocks > 0) dense_transpose_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, qT);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+// One block per 64 nodes: read the tile block (coalesced), write each
+// column's run of 64 entries (coalesced).
+__global__ __launch_bounds__(256) void tile_to_rows_kernel(const float *tile, int kt, int ncols, int64_t n,
+                                                           const int32_t *seeds, float *out, int64_t col0,
+                                                           int32_t *err) {
+    __shared__ float blk[64][64 + 1];
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int64_t nv = min((int64_t)64, n - v0);
+    for (int i = threadIdx.x; i < nv * kt; i += blockDim.x) {
+        const int vl = i / kt, j = i - vl * kt;
+        blk[j][vl] = tile[(v0 + vl) * kt + j];
+    }
+    __syncthreads();
+    const int t = threadIdx.x & 63, r = threadIdx.x >> 6;
+    for (int j = r; j < ncols; j += 4) {
+        bool ok = true;
+        if (seeds) {
+            const int32_t sd = seeds[j];
+            ok = sd >= 0 && (int64_t)sd < n;
+        }
+        if (t < nv) out[(col0 + j) * n + v0 + t] = ok ? blk[j][t] : qnan();
+        if (!ok && t == 0 && blockIdx.x == 0) *err = 1;
+    }
+}
+
+tpa_status launch_tile_to_rows(const float *tile, int kt, int ncols, int64_t n, const int32_t *seeds, float *out,
+                               int64_t col0, int32_t *err, hipStream_t st) {
+    if (kt < 1 || kt > 64 || ncols < 0 || ncols > kt) return fail(TPA_ERR_INVALID_ARG, "bad tile shape");
+    const int64_t blocks = (n + 63) / 64;
+    if (blocks > UINT32_MAX) return fail(TPA_ERR_INDEX_OVERFLOW, "too many nodes for one launch");
+    if (blocks > 0 && ncols > 0)
+        tile_to_rows_kernel<<<(unsigned)blocks, 256, 0, st>>>(tile, kt, ncols, n, seeds, out, col0, err);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_fill_zero(float *z, int64_t n, hipStream_t st) {
+    if (n > 0) fill_zero_kernel<<<grid_1d(n), 256, 0, st>>>(z, n);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

@@ -112,6 +112,70 @@ def test_cpi_argument_errors(rmat13, tpa, torch):
         gg.cpi(c, 0, -1, EPS)
 
 
+@pytest.mark.parametrize("k", [1, 5, 70])
+def test_cpi_batch_seeds_vs_oracle(rmat13, torch, k):
+    """Batched CPI windows (seed tiles of 1, 8 and 64 with a ragged last
+    tile) against the oracle's CPI of each seed."""
+    og, gg = rmat13
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, k, 67)
+    sd = torch.from_numpy(seeds).cuda()
+    rows = sorted({0, k // 2, k - 1})
+    for si, tj in WINDOWS:
+        R = gg.cpi_batch(c, si, tj, EPS, seeds=sd).cpu().numpy()
+        for j in rows:
+            q = np.zeros(og.n)
+            q[seeds[j]] = 1.0
+            expect, _ = og.cpi(q, c, EPS, si, tj)
+            assert l1(R[j], expect) <= TOL, (k, j, si, tj)
+
+
+def test_cpi_batch_dense_per_row_break(tpa, torch):
+    """Dense restarts with different norms stop at their own last
+    iteration (Lemma 2's c (1-c)^i ||q||_1 < eps per row), on node and hub
+    layouts, matching the single-restart tpa_cpi and the oracle."""
+    og = oracle.Graph.rmat(10, 12000, 71)
+    gg = tpa.Graph.rmat(10, 12000, 71)
+    rng = np.random.default_rng(72)
+    q = rng.random((4, og.n))
+    q /= q.sum(axis=1, keepdims=True)
+    q[1] *= 0.5
+    q[2] *= 3.0
+    q[3] = 0.0
+    q[3, 5] = 1e-3
+    for layout in (True, False):
+        gg.set_gather_layout(layout)
+        for si, tj in ((0, -1), (2, 9), (10, -1)):
+            R = gg.cpi_batch(c, si, tj, EPS, q=torch.from_numpy(q.astype(np.float32))).cpu().numpy()
+            for j in range(4):
+                expect, _ = og.cpi(q[j], c, EPS, si, tj)
+                assert l1(R[j], expect) <= TOL * max(1.0, q[j].sum()), (layout, j, si, tj)
+                single = gg.cpi(c, si, tj, EPS, q=torch.from_numpy(q[j].astype(np.float32))).cpu().numpy()
+                assert l1(R[j], single) <= 1e-6 * max(1.0, q[j].sum()), (layout, j, si, tj)
+    gg.set_gather_layout(True)
+
+
+def test_cpi_batch_bad_seed_and_arguments(rmat13, tpa, torch):
+    og, gg = rmat13
+    gg.device_error()  # nothing pending
+    seeds = torch.tensor([3, og.n, 7], dtype=torch.int32).cuda()
+    R = gg.cpi_batch(c, 0, -1, EPS, seeds=seeds).cpu().numpy()
+    assert np.isnan(R[1]).all() and np.isfinite(R[0]).all() and np.isfinite(R[2]).all()
+    with pytest.raises(tpa.TPAError):
+        gg.device_error()
+    gg.device_error()  # cleared
+    q = np.zeros(og.n)
+    q[7] = 1.0
+    assert l1(R[2], og.cpi(q, c, EPS, 0, -1)[0]) <= TOL
+    empty = gg.cpi_batch(c, 0, -1, EPS, seeds=torch.zeros(0, dtype=torch.int32).cuda())
+    assert tuple(empty.shape) == (0, og.n)
+    with pytest.raises(tpa.TPAError):
+        gg.cpi_batch(c, 3, 2, EPS, seeds=seeds[:1])
+    with pytest.raises(tpa.TPAError):
+        gg.cpi_batch(c, 0, -1, 0.0, seeds=seeds[:1])
+    with pytest.raises(ValueError):
+        gg.cpi_batch(c, 0, -1, EPS)
+
+
 @pytest.mark.parametrize("rows,n,k", [(1, 1, 1), (3, 9, 4), (5, 300, 7), (2, 300, 300), (4, 5000, 64),
                                       (2, 70000, 1024), (3, 1024, 1024), (1, 100000, 1),
                                       (2, 49252, 1024), (1, 300000, 1024), (2, 300000, 10)])
@@ -180,6 +244,7 @@ def test_error_report_vs_oracle(rmat13, tpa, torch):
     og, gg = rmat13
     seeds = ti.draw_seeds(og.export()["padded"] == 0, 5, 65)
     rep = accuracy.error_report(gg, seeds, c, S, T, EPS, ks=(10, 100))
+    exact_all = gg.cpi_batch(c, 0, -1, EPS, seeds=torch.from_numpy(seeds).cuda()).cpu().numpy()
     bounds = accuracy.error_bounds(c, S, T)
     assert abs(bounds["tpa"] - 2 * (1 - c) ** S) < 1e-15
     scale = oracle.neighbor_scale(c, S, T)
@@ -198,7 +263,7 @@ def test_error_report_vs_oracle(rmat13, tpa, torch):
         for k, rec in row["recall"].items():
             assert 0.0 <= rec <= 1.0
         r = gg.query(torch.tensor([int(s)], dtype=torch.int32).cuda(), c, S, T)[0].cpu().numpy()
-        ex = gg.cpi(c, 0, -1, EPS, seed=int(s)).cpu().numpy()
+        ex = exact_all[list(seeds).index(s)]
         for k in (10, 100):
             a = set(oracle.topk(r, k)[0][0].tolist())
             b = set(oracle.topk(ex, k)[0][0].tolist())
