@@ -141,6 +141,7 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
                     "avg_launch_us": round(adj_us, 2), "launches_timed": adj_launches}
     s0 = int(seeds_h[0])
     exact_ms = _time_ms(torch, lambda: g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0))
+    exact64_ms = _time_ms(torch, lambda: g.cpi_batch(C_RESTART, 0, -1, 1e-9, seeds=seeds[:64]), reps=2)
     row = g.cpi(C_RESTART, 0, -1, 1e-9, seed=s0)
     topk_ms = _time_ms(torch, lambda: tpa.topk(row, 100))
     qd = torch.from_numpy(np.random.default_rng(8).random((64, g.n)).astype(np.float32)).cuda()
@@ -152,9 +153,11 @@ def extras(tpa, g, seeds, seeds_h, torch, np) -> dict:
             "adjoint": {"seeds": ka, "ms": round(adj_ms, 3),
                         "note": "gradients w.r.t. edge logits and restart vectors (both CPI chains, 64-seed tile)",
                         "roofline": adj_roof},
-            "ops_ms": {"exact_rwr_one_seed": round(exact_ms, 3), "topk_k100_one_row": round(topk_ms, 3),
+            "ops_ms": {"exact_rwr_one_seed": round(exact_ms, 3), "exact_rwr_64_seeds": round(exact64_ms, 3),
+                       "topk_k100_one_row": round(topk_ms, 3),
                        "dense_restart_64": round(dense_ms, 3),
-                       "note": "exact RWR = CPI from x(0) = c e_s until c(1-c)^i < 1e-9 (tpa_cpi, synchronous); "
+                       "note": "exact RWR = CPI from x(0) = c e_s until c(1-c)^i < 1e-9 (tpa_cpi, synchronous; "
+                               "64 seeds at once: tpa_cpi_batch, one seed tile of 64); "
                                "top-k of one n-entry row (tpa_topk); TPA for 64 dense restart vectors "
                                "(tpa_query_dense, automatic seed tile: 64)"}}
 
