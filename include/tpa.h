@@ -252,6 +252,15 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
 
+/* Keep the stranger chain's iterates (Algorithm 2's x'(0) .. x'(K-1), node
+ * order, K x n floats) on the handle at the next tpa_preprocess, so that
+ * tpa_backward with checkpoint_every = 0 reads them instead of recomputing
+ * the chain (the same values).  They are taken only when they fit in a
+ * quarter of the free device memory at preprocessing; tpa_graph_set_logits
+ * drops them until the next tpa_preprocess.  keep = 0 (the default) frees
+ * them (after a device synchronisation).  Errors: INVALID_ARG (NULL). */
+tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
+
 /* Memory order of the vectors a CPI step gathers (internal work buffers).
  * hub_first = 1 (default): node v's
  * entries sit at the rank of v by descending out-degree (ties by id), so

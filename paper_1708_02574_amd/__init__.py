@@ -59,6 +59,7 @@ _SIGS = {
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
     "tpa_set_push_limit": (_i, [_vp, _i64]),
+    "tpa_set_keep_iterates": (_i, [_vp, _i]),
     "tpa_set_gather_layout": (_i, [_vp, _i]),
     "tpa_get_gather_layout": (_i, [_vp, _vp]),
     "tpa_get_push_limit": (_i, [_vp, _vp]),
@@ -436,6 +437,11 @@ class Graph:
         _call("tpa_get_tuning", self._h, C.byref(a), C.byref(b))
         return a.value, b.value
 
+    def set_keep_iterates(self, keep: bool = True):
+        """Keep the stranger chain's iterates at the next preprocess, for the
+        adjoint (tpa_set_keep_iterates)."""
+        _call("tpa_set_keep_iterates", self._h, int(bool(keep)))
+
     def device_error(self, stream=None):
         """Raise TPAError if a query since the last check saw a bad seed."""
         _call("tpa_get_device_error", self._h, _stream(stream))
@@ -507,6 +513,10 @@ def _autograd_function():
         @staticmethod
         def forward(ctx, theta, Q, graph, c, S, T, checkpoint_every=0):
             graph.set_logits(theta.detach())
+            # the backward then reads the stranger chain's iterates instead of
+            # recomputing them
+            if ctx.needs_input_grad[0] and checkpoint_every == 0:
+                graph.set_keep_iterates(True)
             graph.preprocess(c, T)
             R = graph.query_dense(Q.detach(), c, S, T)
             ctx.graph, ctx.args = graph, (c, S, T, checkpoint_every)

@@ -541,7 +541,40 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
 
-    if (grad_logits) {
+    if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
+        TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
+        // ---- stranger chain from the iterates kept by tpa_preprocess ----
+        float *gs, *lam0, *lam1, *part_a;
+        TPA_TRY(sc.get(&gs, n, st));
+        TPA_TRY(sc.get(&lam0, n, st));
+        TPA_TRY(sc.get(&lam1, n, st));
+        TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
+        gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
+        AdjParams ap;
+        ap.rowptr = g->a.rowptr;
+        ap.col = g->a.col;
+        ap.w = g->weighted ? g->a.w : nullptr;
+        ap.inv = g->inv_deg;
+        ap.longs = sa1->longs;
+        ap.G = grad_logits;
+        ap.gvec = gs;
+        ap.omc = omc;
+        ap.kt = 1;
+        ap.ncols = 1;
+        ap.n = n;
+        ap.partials = part_a;
+        ap.beta = (K >= T) ? 1.0f : 0.0f;
+        lam_init_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(ap, lam0);
+        float *lc = lam0, *ln = lam1;
+        for (int64_t i = K; i >= 1; --i) {
+            ap.xprev = g->xiter + (size_t)(i - 1) * n;
+            ap.lam_in = lc;
+            ap.lam_out = ln;
+            ap.beta = (i - 1 >= T) ? 1.0f : 0.0f;
+            TPA_TRY(adj_step(*sa1, ap, st));
+            std::swap(lc, ln);
+        }
+    } else if (grad_logits) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
         // ---- stranger chain, checkpointed ----
         int64_t C = checkpoint_every;

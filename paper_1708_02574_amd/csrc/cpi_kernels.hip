@@ -161,6 +161,7 @@ __device__ __forceinline__ void epi_store(const StepParams &p, int64_t v, int j,
     } else {
         const float x = p.omc * sum;
         p.zout[q.zi] = p.w ? x : x * q.a;
+        if (p.xs_out) p.xs_out[v] = x;
         if (p.accumulate) {
             // Kahan-compensated r~_stranger += x
             const float yk = x - q.c;

@@ -657,7 +657,10 @@ void graph_release(tpa_graph *g) {
     g->t_colz = nullptr;
     g->t_locz = nullptr;
     g->t_wz = nullptr;
-    dfree(g->str); dfree(g->ws); dfree(g->dev_err);
+    dfree(g->str); dfree(g->ws); dfree(g->dev_err); dfree(g->xiter);
+    g->xiter = nullptr;
+    g->xiter_K = 0;
+    g->xiter_cap = 0;
     for (auto &kv : g->sched_t) kv.second.release();
     for (auto &kv : g->sched_a) kv.second.release();
     g->sched_t.clear();
@@ -888,6 +891,7 @@ extern "C" tpa_status tpa_graph_padded(tpa_graph_t g, uint8_t *mask, hipStream_t
 extern "C" tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hipStream_t st) {
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     g->preprocessed = false;
+    g->xiter_K = 0;
     if (!theta) {
         dfree(g->a.w); dfree(g->t.w);
         g->a.w = g->t.w = nullptr;

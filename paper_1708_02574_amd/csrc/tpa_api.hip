@@ -298,6 +298,22 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     const int64_t K = stranger_last_iteration(c, eps);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
+    // iterates kept for the adjoint: K x n floats, when they fit in a quarter
+    // of the free device memory
+    g->xiter_K = 0;
+    if (g->keep_iterates) {
+        const size_t need = (size_t)K * (size_t)g->n;
+        size_t free_b = 0, total_b = 0;
+        if (!g->xiter || g->xiter_cap < need) {
+            dfree(g->xiter);
+            g->xiter = nullptr;
+            g->xiter_cap = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && need * sizeof(float) <= free_b / 4 &&
+                dalloc(&g->xiter, need, st) == TPA_OK)
+                g->xiter_cap = need;
+        }
+    }
+    float *xit = (g->keep_iterates && g->xiter) ? g->xiter : nullptr;
     if (g->gather_layout) {
         TPA_TRY(ensure_zlayout(g, st));
         TPA_TRY(ensure_wz(g, st));
@@ -308,7 +324,9 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     const size_t n = (size_t)g->n;
     TPA_TRY(dalloc(&tmp, 3 * n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));
     float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
-    tpa_status rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, hub ? g->zperm : nullptr, st);
+    tpa_status rc = TPA_OK;
+    if (xit) rc = launch_stranger_init(g, (float)c, 1, z0, xit, comp, hub ? g->zperm : nullptr, st);  // x'(0)
+    if (rc == TPA_OK) rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, hub ? g->zperm : nullptr, st);
     StepParams p;
     p.rowptr = g->t.rowptr;
     p.col = hub ? g->t_colz : g->t.col;
@@ -326,6 +344,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
         p.zin = (i & 1) ? z0 : z1;
         p.zout = (i & 1) ? z1 : z0;
         p.accumulate = i >= T;
+        p.xs_out = (xit && i < K) ? xit + (size_t)i * n : nullptr;
         rc = launch_step(*s, kStranger, false, p, st);
     }
     hipError_t e = hipStreamSynchronize(st);
@@ -336,6 +355,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     g->T = T;
     g->eps = eps;
     g->K = K;
+    g->xiter_K = xit ? K : 0;
     g->preprocessed = true;
     return TPA_OK;
 }
@@ -410,6 +430,19 @@ extern "C" tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first) {
 extern "C" tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first) {
     if (!g || !hub_first) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
     *hub_first = g->gather_layout;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    g->keep_iterates = keep != 0;
+    if (!keep) {
+        (void)hipDeviceSynchronize();  // no kernel may still read them
+        dfree(g->xiter);
+        g->xiter = nullptr;
+        g->xiter_K = 0;
+        g->xiter_cap = 0;
+    }
     return TPA_OK;
 }
 

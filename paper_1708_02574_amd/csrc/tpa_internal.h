@@ -133,6 +133,12 @@ struct tpa_graph {
 
     // preprocessing state
     bool preprocessed = false;
+    // stranger-chain iterates x'(0..K-1), node order, [K][n], kept by
+    // tpa_preprocess when keep_iterates is on (for tpa_backward)
+    bool keep_iterates = false;
+    float *xiter = nullptr;
+    int64_t xiter_K = 0;  // iterates held (0: none)
+    size_t xiter_cap = 0;  // floats allocated at xiter
     double c = 0.0, eps = 0.0;
     int T = 0;
     int64_t K = 0;

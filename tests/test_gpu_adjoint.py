@@ -204,3 +204,40 @@ def test_autograd_function(g10, tpa, torch):
     og.preprocess(c, T, EPS)
     expect = np.stack([og.query_q(q, c, S, T) for q in Qn])
     assert np.all(l1_rows(R.detach().cpu().numpy(), expect) <= TOL)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_backward_with_kept_iterates_is_bitwise_equal(g10, tpa, torch, weighted):
+    """With tpa_set_keep_iterates the adjoint reads the stranger chain's
+    iterates kept by preprocessing instead of recomputing them: the same
+    values, so the gradients are bit for bit those of the recomputing path
+    (automatic and checkpointed), and set_logits drops the kept iterates."""
+    og, gg = g10
+    theta = ti.draw_logits(og.m, 91) if weighted else None
+    gg.set_logits(torch.from_numpy(theta).cuda() if weighted else None)
+    seeds = torch.from_numpy(ti.draw_seeds(og.export()["padded"] == 0, 6, 92)).cuda()
+    W = torch.from_numpy(ti.draw_loss_weights((6, og.n), 93)).cuda()
+    try:
+        gg.set_keep_iterates(False)
+        gg.preprocess(c, T)
+        ref = gg.backward(W, c, S, T, seeds=seeds)
+        ref_ck = gg.backward(W, c, S, T, seeds=seeds, checkpoint_every=11)
+        gg.set_keep_iterates(True)
+        gg.preprocess(c, T)
+        kept = gg.backward(W, c, S, T, seeds=seeds)
+        for a, b in zip(kept, ref):
+            assert torch.equal(a, b)
+        for a, b in zip(ref_ck, ref):
+            assert torch.equal(a, b)
+        # new weights: the iterates are dropped until the next preprocessing
+        gg.set_logits(torch.from_numpy(ti.draw_logits(og.m, 94)).cuda())
+        gg.preprocess(c, T)
+        again = gg.backward(W, c, S, T, seeds=seeds)
+        gg.set_keep_iterates(False)
+        gg.preprocess(c, T)
+        fresh = gg.backward(W, c, S, T, seeds=seeds)
+        for a, b in zip(again, fresh):
+            assert torch.equal(a, b)
+    finally:
+        gg.set_keep_iterates(False)
+        gg.set_logits(None)
