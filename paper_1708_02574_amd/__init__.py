@@ -507,7 +507,9 @@ def _autograd_function():
         theta: per-edge logits [m] in A~ order (row-softmax weights), Q: dense
         restart vectors [k, n].  The forward sets the graph's weights from
         theta and re-runs preprocessing (the stranger part depends on the
-        weights); the backward differentiates both CPI chains on the device.
+        weights), keeping the stranger chain's iterates when theta needs a
+        gradient and checkpoint_every is 0 (tpa_set_keep_iterates); the
+        backward differentiates both CPI chains on the device.
         """
 
         @staticmethod
