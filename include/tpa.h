@@ -184,7 +184,12 @@ tpa_status tpa_query_dense(tpa_graph_t g, const float *q, int64_t k, double c, i
  *               derivative at theta = 0;
  *   grad_q      float[k][n]: dL/dq_j = c * lambda_j(0).
  * Requires tpa_preprocess with the same (c, T) (K comes from its eps).
- * Allocates scratch and synchronises `stream` before returning.
+ * Its work buffers stay on the handle for the next call (up to 8 GiB in
+ * all; buffers beyond that are allocated and freed per call), so repeated
+ * calls of one shape allocate nothing; they are freed with the graph.
+ * Synchronises `stream` before returning; calls on one handle must not
+ * overlap.  With tpa_set_keep_iterates on and checkpoint_every = 0 the
+ * stranger chain is read from the iterates kept by tpa_preprocess.
  * Errors: INVALID_ARG, NOT_PREPROCESSED, PARAM_MISMATCH, OOM, HIP. */
 tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const float *q, int64_t k, int packed,
                         double c, int S, int T, const float *grad_out, float *grad_logits,

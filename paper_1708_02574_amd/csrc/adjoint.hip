@@ -496,15 +496,48 @@ tpa_status adj_step(const Schedule &s, const AdjParams &p, hipStream_t st) {
 }
 
 // Scoped device buffers freed on every exit path.
+// Work buffers of one tpa_backward call.  The call's i-th buffer reuses
+// slot i of the handle's cache when it is large enough, and otherwise
+// replaces it, while the cache stays within kAdjCacheBytes; beyond that a
+// buffer is allocated for this call only.  Repeated calls of one shape
+// (a training loop) then allocate nothing.  Calls on one handle must not
+// overlap.
+constexpr size_t kAdjCacheBytes = (size_t)8 << 30;
+
 struct Scratch {
-    std::vector<void *> bufs;
+    tpa_graph *g;
+    size_t next = 0;
+    std::vector<void *> own;  // this call's uncached buffers
+    explicit Scratch(tpa_graph *graph) : g(graph) {}
     ~Scratch() {
-        for (void *b : bufs) dfree(b);
+        for (void *b : own) dfree(b);
     }
     template <class T>
     tpa_status get(T **p, size_t count, hipStream_t st) {
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        auto &cache = g->adj_cache;
+        const size_t slot = next++;
+        if (slot < cache.size() && cache[slot].second >= bytes) {
+            *p = static_cast<T *>(cache[slot].first);
+            return TPA_OK;
+        }
+        size_t held = 0;
+        for (size_t i = 0; i < cache.size(); ++i)
+            if (i != slot) held += cache[i].second;
+        if (held + bytes <= kAdjCacheBytes) {
+            if (slot < cache.size()) {
+                dfree(cache[slot].first);
+                cache[slot] = {nullptr, 0};
+            }
+            void *b = nullptr;
+            TPA_TRY(dmalloc(&b, bytes, st));
+            if (slot < cache.size()) cache[slot] = {b, bytes};
+            else cache.push_back({b, bytes});  // slot == cache.size(): slots fill in order
+            *p = static_cast<T *>(b);
+            return TPA_OK;
+        }
         TPA_TRY(dalloc(p, std::max<size_t>(count, 1), st));
-        bufs.push_back(*p);
+        own.push_back(*p);
         return TPA_OK;
     }
 };
@@ -533,7 +566,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     const float omc = (float)(1.0 - c);
     const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     const float alpha = (float)((1.0 - pT) / (1.0 - pS));
-    Scratch sc;
+    Scratch sc(g);
 
     const Schedule *sf1 = nullptr, *sa1 = nullptr;
     SchedShape adj_shape = choose_shape(g, 1);

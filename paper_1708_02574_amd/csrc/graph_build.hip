@@ -658,6 +658,8 @@ void graph_release(tpa_graph *g) {
     g->t_locz = nullptr;
     g->t_wz = nullptr;
     dfree(g->str); dfree(g->ws); dfree(g->dev_err); dfree(g->xiter);
+    for (auto &b : g->adj_cache) dfree(b.first);
+    g->adj_cache.clear();
     g->xiter = nullptr;
     g->xiter_K = 0;
     g->xiter_cap = 0;

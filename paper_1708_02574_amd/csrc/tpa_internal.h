@@ -139,6 +139,9 @@ struct tpa_graph {
     float *xiter = nullptr;
     int64_t xiter_K = 0;  // iterates held (0: none)
     size_t xiter_cap = 0;  // floats allocated at xiter
+    // tpa_backward's work buffers, kept for the next call (slot i = the
+    // call's i-th buffer; at most kAdjCacheBytes in all)
+    std::vector<std::pair<void *, size_t>> adj_cache;
     double c = 0.0, eps = 0.0;
     int T = 0;
     int64_t K = 0;
