@@ -495,7 +495,6 @@ tpa_status adj_step(const Schedule &s, const AdjParams &p, hipStream_t st) {
     return TPA_OK;
 }
 
-// Scoped device buffers freed on every exit path.
 // Work buffers of one tpa_backward call.  The call's i-th buffer reuses
 // slot i of the handle's cache when it is large enough, and otherwise
 // replaces it, while the cache stays within kAdjCacheBytes; beyond that a
