@@ -229,6 +229,13 @@ tpa_status tpa_autotune(tpa_graph_t g, const int32_t *seeds, int64_t k, double c
  * so that later queries allocate nothing (e.g. under stream capture). */
 tpa_status tpa_reserve(tpa_graph_t g, int64_t k);
 
+/* Bytes of device workspace a query of k columns (seeds, per_block slots or
+ * dense restart vectors) needs under the current tuning: the size that
+ * tpa_reserve(g, k) holds on the handle and that a captured query allocates
+ * for itself.  It may build the work schedule (synchronously).  Errors:
+ * INVALID_ARG (NULL, k < 0), HIP. */
+tpa_status tpa_query_workspace_size(tpa_graph_t g, int64_t k, size_t *bytes);
+
 /* Query tuning: seed-tile width kt (seeds per SpMM pass: 1, 2, 4, 8, 16,
  * 32 or 64; 0 = automatic: the next power of two up to 16 for k <= 32
  * columns, 64 above) and the edge budget of a wave work item that

@@ -56,6 +56,7 @@ _SIGS = {
     "tpa_query_graph_destroy": (_i, [_vp]),
     "tpa_autotune": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp, _vp, _vp, _vp]),
     "tpa_reserve": (_i, [_vp, _i64]),
+    "tpa_query_workspace_size": (_i, [_vp, _i64, _vp]),
     "tpa_set_tuning": (_i, [_vp, _i, _i]),
     "tpa_get_tuning": (_i, [_vp, _vp, _vp]),
     "tpa_set_push_limit": (_i, [_vp, _i64]),
@@ -406,6 +407,12 @@ class Graph:
 
     def reserve(self, k: int):
         _call("tpa_reserve", self._h, k)
+
+    def workspace_size(self, k: int) -> int:
+        """Bytes of query workspace for k columns (tpa_query_workspace_size)."""
+        b = C.c_size_t(0)
+        _call("tpa_query_workspace_size", self._h, k, C.byref(b))
+        return int(b.value)
 
     def set_tuning(self, seed_tile: int = 0, edges_per_item: int = 0):
         _call("tpa_set_tuning", self._h, seed_tile, edges_per_item)

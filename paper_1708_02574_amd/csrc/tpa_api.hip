@@ -388,6 +388,13 @@ extern "C" tpa_status tpa_query_packed(tpa_graph_t g, const int32_t *seeds, int 
     return run_query(g, seeds, nullptr, per_block, true, c, S, T, out, st, nullptr, 0);
 }
 
+extern "C" tpa_status tpa_query_workspace_size(tpa_graph_t g, int64_t k, size_t *bytes) {
+    if (!g || !bytes || k < 0) return fail(TPA_ERR_INVALID_ARG, "bad argument");
+    *bytes = query_workspace_bytes(g, k, true, nullptr);
+    if (*bytes == 0) return fail(TPA_ERR_HIP, "could not build the work schedule");
+    return TPA_OK;
+}
+
 extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     if (!g || k < 0) return fail(TPA_ERR_INVALID_ARG, "bad argument");
     const int kt = choose_kt(g, k);

@@ -57,6 +57,9 @@ def test_header_status_codes_match_binding():
     lambda L: L.tpa_graph_padded(None, None, None),
     lambda L: L.tpa_graph_set_logits(None, None, None),
     lambda L: L.tpa_reserve(None, 1),
+    lambda L: L.tpa_query_workspace_size(None, 1, None),
+    lambda L: L.tpa_set_keep_iterates(None, 1),
+    lambda L: L.tpa_cpi_batch(None, None, None, 1, 0.15, 0, -1, 1e-9, None, None),
     lambda L: L.tpa_get_device_error(None, None),
     lambda L: L.tpa_graph_pack(None, 0, None, None),
     lambda L: L.tpa_query_dense(None, None, 1, 0.15, 5, 10, None, None),

@@ -101,3 +101,16 @@ def test_autotune_choice_passes_parity(rmat13, torch):
     gg.set_tuning(0, 0)
     for i in (0, 57, 199):
         assert l1_rows(R[i], og.query(int(seeds[i]), c, S, T)) <= TOL
+
+
+def test_workspace_size_and_reserve(rmat13, torch):
+    """tpa_query_workspace_size reports the bytes tpa_reserve holds; it grows
+    with the batch (seed tiles of 1, 8 and 64) and covers dense restarts."""
+    og, gg = rmat13
+    gg.set_tuning(0, 0)  # automatic tiles (an earlier test may have autotuned the handle)
+    sizes = [gg.workspace_size(k) for k in (1, 8, 100)]
+    assert 0 < sizes[0] < sizes[1] < sizes[2]
+    gg.reserve(100)
+    seeds = torch.from_numpy(ti.draw_seeds(og.export()["padded"] == 0, 100, 5)).cuda()
+    R = gg.query(seeds, c, S, T)
+    assert bool(torch.isfinite(R).all())
