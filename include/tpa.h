@@ -100,6 +100,14 @@ tpa_status tpa_graph_destroy(tpa_graph_t g);
 /* Sizes (host outputs; any may be NULL). nblocks is 1 unless packed. */
 tpa_status tpa_graph_info(tpa_graph_t g, int64_t *n, int64_t *m, int64_t *nblocks);
 
+/* Device memory the handle holds, in bytes (host output): both CSR
+ * orientations and per-node arrays, the gather layout's arrays, the work
+ * schedules, the query workspace, kept iterates and tpa_backward's cached
+ * buffers (the requested sizes, before allocator rounding).  Query graphs
+ * (tpa_query_graph_create) hold their own workspace and are not counted.
+ * Errors: INVALID_ARG (NULL). */
+tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes);
+
 /* Host copy of the block offsets (nblocks + 1 entries). */
 tpa_status tpa_graph_blocks(tpa_graph_t g, int64_t *offsets_host);
 
@@ -274,7 +282,7 @@ tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
 tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
 
 /* Memory order of the vectors a CPI step gathers (internal work buffers).
- * hub_first = 1 (default): node v's
+ * hub_first = 1: node v's
  * entries sit at the rank of v by descending out-degree (ties by id), so
  * the most gathered entries, those of high out-degree sources, share cache
  * lines, and each row of A~^T is summed in ascending rank, so the lanes
@@ -286,7 +294,19 @@ tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
  * here when the graph is already preprocessed.  hub_first = 0 keeps node
  * order, A~^T's own edge order and no extra memory.  The two orders give
  * the same sums up to FP32 rounding (each row is added in a different
- * order).  Synchronous when it builds.  Errors: INVALID_ARG, OOM, HIP. */
+ * order).  hub_first = 2 (the default) is order 1 plus, for the
+ * single-vector step (one seed, preprocessing, tpa_cpi, the adjoint's
+ * forward chain), one more int32[m] copy of the column ids in which the
+ * edges of each work item that sums several short rows (at most 512 edges)
+ * are sorted by rank across the rows, so each 64-edge load reads fewer
+ * cache lines; every entry carries its position in the item, where its
+ * product is added, so the sums are bitwise those of order 1.  The copy
+ * is built with the work schedule (by tpa_preprocess, the first
+ * single-seed query or tpa_reserve; not during stream capture, where the
+ * kernels read the order-1 ids instead) when the graph has fewer than
+ * 2^23 nodes and the copy takes at most a quarter of the free device
+ * memory.  Synchronous when it builds.  Errors: INVALID_ARG (layout not
+ * 0, 1 or 2), OOM, HIP. */
 tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first);
 tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
 tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);

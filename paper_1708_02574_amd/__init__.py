@@ -41,6 +41,7 @@ _SIGS = {
     "tpa_graph_destroy": (_i, [_vp]),
     "tpa_graph_info": (_i, [_vp, _vp, _vp, _vp]),
     "tpa_graph_blocks": (_i, [_vp, _vp]),
+    "tpa_graph_device_bytes": (_i, [_vp, _vp]),
     "tpa_graph_export": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "tpa_graph_padded": (_i, [_vp, _vp, _vp]),
     "tpa_graph_set_logits": (_i, [_vp, _vp, _vp]),
@@ -423,16 +424,25 @@ class Graph:
         0: always pull)."""
         _call("tpa_set_push_limit", self._h, max_edges)
 
-    def set_gather_layout(self, hub_first: bool = True):
+    def set_gather_layout(self, layout=2):
         """Order of the gathered work vectors and of each row's edge sum:
-        hub-first (default) or node order; results agree up to FP32
-        rounding."""
-        _call("tpa_set_gather_layout", self._h, int(bool(hub_first)))
+        2 (default, also for True) hub-first with the single-vector step's
+        group items in rank order (bitwise the sums of 1), 1 hub-first,
+        0 (also for False) node order; 0 and 1 agree up to FP32 rounding."""
+        if isinstance(layout, bool):
+            layout = 2 if layout else 0
+        _call("tpa_set_gather_layout", self._h, int(layout))
 
-    def get_gather_layout(self) -> bool:
+    def device_bytes(self) -> int:
+        """Device memory the handle holds (tpa_graph_device_bytes)."""
+        v = C.c_size_t()
+        _call("tpa_graph_device_bytes", self._h, C.byref(v))
+        return v.value
+
+    def get_gather_layout(self) -> int:
         v = C.c_int()
         _call("tpa_get_gather_layout", self._h, C.byref(v))
-        return bool(v.value)
+        return v.value
 
     def get_push_limit(self) -> int:
         v = C.c_int64()

@@ -332,6 +332,7 @@ extern "C" tpa_status tpa_cpi(tpa_graph_t g, int32_t seed, const float *q, doubl
         TPA_TRY(ensure_wz(g, st));
     }
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    if (hub) TPA_TRY(ensure_group_order(g, s, st));
     float *tmp = nullptr;
     TPA_TRY(dalloc(&tmp, 3 * (size_t)n + (size_t)std::max<int64_t>(s->n_chunk_items, 1), st));
     float *z0 = tmp, *z1 = tmp + n, *comp = tmp + 2 * n, *part = tmp + 3 * n;
@@ -410,6 +411,7 @@ extern "C" tpa_status tpa_cpi_batch(tpa_graph_t g, const int32_t *seeds, const f
         TPA_TRY(ensure_wz(g, st));
     }
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, st));
     const size_t tile = (size_t)n * kt;
     float *buf = nullptr;
     const size_t nbuf = 4 * tile + (q ? tile : 0) + (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;

@@ -572,6 +572,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     adj_shape.eb = 0;  // the adjoint kernels take wave, group and chunk items
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
+    if (hub) TPA_TRY(ensure_group_order(g, sf1, st));
 
     if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));

@@ -27,6 +27,8 @@ struct StepParams {
     float *zout = nullptr;             // next gathered vector [n][kt]
     const int32_t *zperm = nullptr;    // row of node v in zin/zout (null: v); col is
                                        // then given in those rows, except on first steps
+    int col_slots = 0;                 // kt == 1: col is a schedule's colg (group items in
+                                       // gather order with LDS slots); set by the launchers
     float *partials = nullptr;         // [chunk items][kt] chunk sums of long rows
     float omc = 0.f;                   // 1 - c
     float c = 0.f;

@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kWaves = 4;          // waves (items) per block
 constexpr int kThreads = 64 * kWaves;
-constexpr int kGroupMax = 512;     // max edges of a group item (LDS floats per wave)
+constexpr int kGroupMax = kGroupEdges;  // max edges of a group item (LDS floats per wave)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -255,15 +255,27 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         constexpr int NS = kGroupMax / 64;
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
-        // all index loads, the epilogue operands, then all gathers, then LDS
-        int32_t u[NS];
+        // all index loads, the epilogue operands, then all gathers, then LDS.
+        // In gather order (col_slots) entry e holds the row to gather and,
+        // above it, the edge's position in the item, where its product goes:
+        // the LDS slice is then in row order as before, so are the sums.
+        const bool slots = p.col_slots != 0;
+        uint32_t raw[NS];  // kNoEdge past the item's end
+        constexpr uint32_t kNoEdge = ~0u;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int e = s * 64 + lane;
-            u[s] = e < nnz ? col[e] : -1;
+            raw[s] = e < nnz ? (uint32_t)col[e] : kNoEdge;
         }
         EpiPre q;
         if (lane < nrows) q = epi_load<MODE>(p, it.row0 + lane);
+        int32_t u[NS];
+        int pos[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            u[s] = raw[s] == kNoEdge ? -1 : (int32_t)(slots ? raw[s] & kGroupRowMask : raw[s]);
+            pos[s] = slots ? (int)(raw[s] >> kGroupSlotShift) : s * 64 + lane;
+        }
         if (!FIRST && frontier_on(p)) {
 #pragma unroll
             for (int s = 0; s < NS; ++s)
@@ -272,11 +284,11 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         float v[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            v[s] = u[s] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + s * 64 + lane, u[s], 0) : 0.0f;
+            v[s] = u[s] >= 0 ? edge_value<FIRST, WEIGHTED, 1>(p, it.e0 + pos[s], u[s], 0) : 0.0f;
         wave_sync();  // the previous item's LDS reads are done
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            if (s * 64 < nnz) my[s * 64 + lane] = v[s];
+            if (raw[s] != kNoEdge) my[pos[s]] = v[s];
         const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
         wave_sync();
         // rows of <= 32 edges: lane r adds row r's slice; longer rows: the
@@ -1073,7 +1085,24 @@ void launch_w(const Schedule &s, const StepParams &p, hipStream_t st) {
 
 }  // namespace
 
-tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams &p, hipStream_t st) {
+namespace {
+
+// The single-vector kernels read a schedule's group-ordered column ids in
+// place of the hub-first ones they were built from.
+StepParams with_group_order(const Schedule &s, const StepParams &p) {
+    StepParams q = p;
+    q.col_slots = 0;
+    if (q.kt == 1 && s.colg && q.col == s.colg_src) {
+        q.col = s.colg;
+        q.col_slots = 1;
+    }
+    return q;
+}
+
+}  // namespace
+
+tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams &p0, hipStream_t st) {
+    const StepParams p = with_group_order(s, p0);
     if (p.kt != 1 && p.kt != 2 && p.kt != 4 && p.kt != 8 && p.kt != 16 && p.kt != 32 && p.kt != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
@@ -1232,7 +1261,8 @@ tpa_status launch_push_steps12(const StepParams &p, const tpa_graph *g, const Pu
     return TPA_OK;
 }
 
-tpa_status launch_gated_step(const Schedule &s, const StepParams &p, const PushPlan &pp, hipStream_t st) {
+tpa_status launch_gated_step(const Schedule &s, const StepParams &p0, const PushPlan &pp, hipStream_t st) {
+    const StepParams p = with_group_order(s, p0);
     if (p.kt != 1 || p.node_block || !p.seeds || p.last)
         return fail(TPA_ERR_INVALID_ARG, "a gated step is a single-seed non-last family step");
     if (s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");

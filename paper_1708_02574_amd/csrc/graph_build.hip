@@ -451,6 +451,41 @@ __global__ void low32_kernel(const uint64_t *keys, int64_t m, int32_t *out) {
         out[e] = (int32_t)(uint32_t)keys[e];
 }
 
+// One block per group item (grid-stride over the items): the item's edges
+// sorted by gather row, ties by position, with a bitonic sort of kGroupEdges
+// (row, position) keys in LDS, padded with all-ones keys; each entry then
+// holds its row and, above it, its position in the item.
+__global__ __launch_bounds__(256) void group_order_kernel(const Item *items, int64_t n_items, const int32_t *colz,
+                                                          int32_t *colg) {
+    __shared__ uint64_t key[kGroupEdges];
+    for (int64_t b = blockIdx.x; b < n_items; b += gridDim.x) {
+        const Item it = items[b];
+        if (item_kind(it.meta) != kItemGroup) continue;  // block-uniform
+        const int nnz = (int)item_nnz(it.meta);
+        for (int k = threadIdx.x; k < kGroupEdges; k += 256)
+            key[k] = k < nnz ? ((uint64_t)(uint32_t)colz[it.e0 + k] << 32) | (uint32_t)k : ~0ull;
+        __syncthreads();
+        for (int size = 2; size <= kGroupEdges; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < kGroupEdges / 2; t += 256) {
+                    const int i = 2 * t - (t & (stride - 1)), j = i + stride;
+                    const uint64_t x = key[i], y = key[j];
+                    if ((x > y) == ((i & size) == 0)) {
+                        key[i] = y;
+                        key[j] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = threadIdx.x; k < nnz; k += 256) {
+            const uint64_t x = key[k];
+            colg[it.e0 + k] = (int32_t)((uint32_t)(x >> 32) | ((uint32_t)x << kGroupSlotShift));
+        }
+        __syncthreads();  // the keys are read before the next item overwrites them
+    }
+}
+
 }  // namespace
 
 // Rank of every node by descending out-degree (a stable radix sort keeps
@@ -551,12 +586,50 @@ tpa_status ensure_wz(tpa_graph *g, hipStream_t st) {
     return TPA_OK;
 }
 
+tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) {
+    Schedule *s = const_cast<Schedule *>(cs);  // an entry of g's schedule cache
+    if (g->gather_layout != 2 || !g->t_colz || s->colg || s->n_items == 0) return TPA_OK;
+    if (g->n >= kGroupSlotMaxN || s->ew > kGroupEdges) return TPA_OK;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return TPA_OK;
+    // an optional copy: built only when it takes at most a quarter of the free memory
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || (size_t)g->m * sizeof(int32_t) > free_b / 4) return TPA_OK;
+    int32_t *colg = nullptr;
+    TPA_TRY(dalloc(&colg, g->m, st));
+    hipError_t e = hipMemcpyAsync(colg, g->t_colz, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        const unsigned grid = (unsigned)std::min<int64_t>(s->n_items, int64_t(1) << 20);
+        group_order_kernel<<<grid, 256, 0, st>>>(s->items, s->n_items, g->t_colz, colg);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        dfree(colg);
+        return fail(TPA_ERR_HIP, std::string("group order: ") + hipGetErrorString(e));
+    }
+    s->colg = colg;
+    s->colg_src = g->t_colz;
+    return TPA_OK;
+}
+
+void drop_group_order(tpa_graph *g) {
+    for (auto &kv : g->sched_t) {
+        dfree(kv.second.colg);
+        kv.second.colg = nullptr;
+        kv.second.colg_src = nullptr;
+    }
+}
+
 // ------------------------------------------------------------------ schedule
 void Schedule::release() {
     dfree(items);
     dfree(longs);
+    dfree(colg);
     items = nullptr;
     longs = nullptr;
+    colg = nullptr;
+    colg_src = nullptr;
 }
 
 // Rows of A~^T are cut into wave items, heaviest first so they start early:
@@ -857,6 +930,44 @@ extern "C" tpa_status tpa_graph_info(tpa_graph_t g, int64_t *n, int64_t *m, int6
     if (n) *n = g->n;
     if (m) *m = g->m;
     if (nblocks) *nblocks = g->nblocks;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
+    if (!g || !bytes) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    const size_t n = (size_t)g->n, m = (size_t)g->m;
+    size_t b = 0;
+    auto add = [&b](const void *p, size_t sz) {
+        if (p) b += sz;
+    };
+    for (const Csr *c : {&g->a, &g->t}) {
+        add(c->rowptr, sizeof(int64_t) * (n + 1));
+        add(c->col, sizeof(int32_t) * m);
+        add(c->w, sizeof(float) * m);
+    }
+    add(g->t2a, sizeof(int64_t) * m);
+    add(g->inv_deg, sizeof(float) * n);
+    add(g->padded, n);
+    add(g->node_block, sizeof(int32_t) * n);
+    add(g->restart_pr, sizeof(float) * n);
+    add(g->zperm, sizeof(int32_t) * n);
+    add(g->t_colz, sizeof(int32_t) * m);
+    add(g->t_locz, sizeof(int32_t) * m);
+    add(g->t_wz, sizeof(float) * m);
+    add(g->str, sizeof(float) * n);
+    add(g->dev_err, sizeof(int32_t));
+    add(g->ws, g->ws_bytes);
+    add(g->xiter, sizeof(float) * g->xiter_cap);
+    for (const auto &c : g->adj_cache) add(c.first, c.second);
+    for (const auto *cache : {&g->sched_t, &g->sched_a}) {
+        for (const auto &kv : *cache) {
+            const Schedule &s = kv.second;
+            add(s.items, sizeof(Item) * (size_t)s.n_items);
+            add(s.longs, sizeof(LongRow) * (size_t)s.n_long);
+            add(s.colg, sizeof(int32_t) * m);
+        }
+    }
+    *bytes = b;
     return TPA_OK;
 }
 

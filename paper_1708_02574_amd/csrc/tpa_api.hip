@@ -197,6 +197,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     // gathered vectors in hub-first rows (first steps read node ids: t.col
     // and t.w in A~^T's own order)
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, st));  // a no-op under capture
     p.zperm = hub ? g->zperm : nullptr;
     const int32_t *col_gather = hub ? g->t_colz : g->t.col;
     const float *w_gather = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
@@ -319,6 +320,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
         TPA_TRY(ensure_wz(g, st));
     }
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    if (hub) TPA_TRY(ensure_group_order(g, s, st));
     if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
     float *tmp = nullptr;
     const size_t n = (size_t)g->n;
@@ -400,6 +402,8 @@ extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, kt), nullptr, &s));
+    const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
+    if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, nullptr));  // not buildable under capture
     return ensure_ws(g, query_ws_bytes(g, s, kt, true), nullptr);  // room for dense restarts too
 }
 
@@ -424,13 +428,17 @@ extern "C" tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_p
 
 extern "C" tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first) {
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
-    if (hub_first != 0 && hub_first != 1) return fail(TPA_ERR_INVALID_ARG, "hub_first must be 0 or 1");
+    if (hub_first < 0 || hub_first > 2) return fail(TPA_ERR_INVALID_ARG, "layout must be 0, 1 or 2");
+    if (hub_first < 2) drop_group_order(g);
+    g->gather_layout = hub_first;
     if (hub_first && g->preprocessed) {
         TPA_TRY(ensure_zlayout(g, nullptr));
         TPA_TRY(ensure_wz(g, nullptr));
+        const Schedule *s = nullptr;
+        TPA_TRY(get_schedule(g, choose_shape(g, 1), nullptr, &s));
+        TPA_TRY(ensure_group_order(g, s, nullptr));
         TPA_TRY_HIP(hipStreamSynchronize(nullptr));
     }
-    g->gather_layout = hub_first;
     return TPA_OK;
 }
 

@@ -68,6 +68,18 @@ struct LongRow {
     int32_t row, nchunks, first_item, pad;
 };
 
+// Group items in gather order: the single-vector step keeps a group item's
+// products in a kGroupEdges-float LDS slice.  In a schedule's colg copy of
+// the hub-first column ids, each group item's edges are re-sorted by gather
+// row (ties by position) and each entry carries, above its kGroupSlotShift
+// row bits, its position in the item: the LDS slot its product goes to, so
+// the rows are still summed in the same order.  Graphs of at least
+// kGroupSlotMaxN nodes do not fit and keep the row order.
+constexpr int kGroupEdges = 512;
+constexpr int kGroupSlotShift = 23;
+constexpr int64_t kGroupSlotMaxN = int64_t(1) << kGroupSlotShift;
+constexpr uint32_t kGroupRowMask = (1u << kGroupSlotShift) - 1u;
+
 // Shape of a schedule: group items hold <= ew edges; rows of ew+1..el edges
 // are one wave item each; rows of el+1..eb edges are block items; longer
 // rows are cut into chunks of `chunk` edges.
@@ -92,6 +104,10 @@ struct Schedule {
     int64_t n_chunk_items = 0;
     LongRow *longs = nullptr;    // device
     int64_t n_long = 0;
+    // device, m: colg_src (the graph's t_colz) with group items in gather
+    // order (see kGroupEdges), built by ensure_group_order; null when absent
+    int32_t *colg = nullptr;
+    const int32_t *colg_src = nullptr;
     void release();
 };
 
@@ -126,7 +142,8 @@ struct tpa_graph {
     int32_t *t_locz = nullptr;              // m
     float *t_wz = nullptr;                  // m, weighted graphs
     bool t_wz_valid = false;
-    int gather_layout = 1;                  // 1 = hub-first order, 0 = node order
+    int gather_layout = 2;                  // 2 = hub-first order, group items in gather
+                                            // order; 1 = hub-first order; 0 = node order
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
     bool weighted = false;                  // weights from logits (a.w, t.w set)
@@ -180,6 +197,13 @@ tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, cons
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
 // Build zperm, t_colz and t_locz (synchronises `stream`); no-op when present.
 tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
+// Give a single-vector schedule its group-ordered column ids (colg) when
+// the graph's layout asks for them and they fit; a no-op otherwise, also
+// under stream capture (the step kernels then read t_colz, with the same
+// sums).  Synchronous when it builds.
+tpa_status ensure_group_order(tpa_graph *g, const Schedule *s, hipStream_t stream);
+// Drop every schedule's colg (after the layout leaves group order).
+void drop_group_order(tpa_graph *g);
 // Build t_wz from the current weights when the graph is weighted.
 tpa_status ensure_wz(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);

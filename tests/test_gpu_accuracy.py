@@ -51,10 +51,10 @@ def l1(a, b):
 WINDOWS = [(0, -1), (0, S - 1), (S, T - 1), (T, -1), (0, 0), (3, 3), (7, 200)]
 
 
-@pytest.mark.parametrize("layout", [1, 0])
+@pytest.mark.parametrize("layout", [2, 1, 0])
 def test_cpi_windows_seed(rmat13, torch, layout):
     og, gg = rmat13
-    gg.set_gather_layout(bool(layout))
+    gg.set_gather_layout(layout)
     try:
         for s in ti.draw_seeds(og.export()["padded"] == 0, 4, 61):
             q = np.zeros(og.n)
@@ -142,7 +142,7 @@ def test_cpi_batch_dense_per_row_break(tpa, torch):
     q[2] *= 3.0
     q[3] = 0.0
     q[3, 5] = 1e-3
-    for layout in (True, False):
+    for layout in (2, 1, 0):
         gg.set_gather_layout(layout)
         for si, tj in ((0, -1), (2, 9), (10, -1)):
             R = gg.cpi_batch(c, si, tj, EPS, q=torch.from_numpy(q.astype(np.float32))).cpu().numpy()

@@ -430,7 +430,7 @@ def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
     try:
         for hub in (True, False):
             gg.set_gather_layout(hub)
-            assert gg.get_gather_layout() == hub
+            assert gg.get_gather_layout() == (2 if hub else 0)
             gg.preprocess(c, T)
             out = [gg.stranger()]
             for kt in (1, 4, 64):
@@ -450,6 +450,56 @@ def test_gather_layout_node_and_hub_order(tpa, torch, weighted):
         assert np.all(l1_rows(a.cpu().numpy(), e) <= TOL), i
         assert np.all(l1_rows(b.cpu().numpy(), e) <= TOL), i
         assert float((a - b).abs().max()) <= 1e-6, i
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_group_order_is_bitwise_row_order(tpa, torch, weighted):
+    """Layout 2 re-sorts each group item's edges by rank across its rows and
+    sends each product to its row-order LDS slot: the stranger vector,
+    single-seed queries (pushed, pulled, S = 2), exact CPI (seed and dense)
+    and both gradients are bit for bit those of layout 1, with 1/outdeg and
+    with logit weights (read through the slot).  The group-ordered ids are
+    one more int32 per edge, held only under layout 2."""
+    og = oracle.Graph.rmat(15, 300000, 41)
+    gg = tpa.Graph.rmat(15, 300000, 41)
+    if weighted:
+        theta = ti.draw_logits(gg.m, 42)
+        og.set_logits(theta.astype(np.float64))
+        gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    sd = ti.draw_seeds(og.export()["padded"] == 0, 6, 43)
+    seeds = torch.from_numpy(sd).cuda()
+    q = np.random.default_rng(44).random(gg.n)
+    q /= q.sum()
+    qt = torch.from_numpy(q.astype(np.float32)).cuda()
+    W = torch.from_numpy(ti.draw_loss_weights((1, gg.n), 45)).cuda()
+    res, mem = [], []
+    try:
+        for layout in (1, 2):
+            gg.set_gather_layout(layout)
+            gg.preprocess(c, T)
+            out = [gg.stranger()]
+            for j in range(len(sd)):
+                out.append(gg.query(seeds[j:j + 1], c, S, T))
+            gg.set_push_limit(0)
+            out.append(gg.query(seeds[:1], c, S, T))
+            gg.set_push_limit(-1)
+            out.append(gg.query(seeds[1:2], c, 2, T))
+            out.append(gg.cpi(c, 0, -1, EPS, seed=int(sd[2])))
+            out.append(gg.cpi(c, 3, 9, EPS, q=qt))
+            out.extend(gg.backward(W, c, S, T, seeds=seeds[3:4]))
+            res.append(out)
+            mem.append(gg.device_bytes())
+    finally:
+        gg.set_gather_layout(2)
+        gg.set_logits(None)
+    assert res[1][-2] is not None
+    for i, (a, b) in enumerate(zip(res[0], res[1])):
+        assert (a is None) == (b is None), i
+        assert a is None or torch.equal(a, b), i
+    for sv, r in zip(sd, res[1][1:7]):
+        assert np.all(l1_rows(r.cpu().numpy(), og.query(int(sv), c, S, T)[None]) <= TOL)
+    assert mem[1] - mem[0] == 4 * gg.m
 
 
 # ---------------------------------------------------------------- packed
