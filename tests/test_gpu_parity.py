@@ -502,6 +502,39 @@ def test_group_order_is_bitwise_row_order(tpa, torch, weighted):
     assert mem[1] - mem[0] == 4 * gg.m
 
 
+@pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23])
+def test_group_order_node_id_limit(tpa, torch, n):
+    """The group-ordered ids keep 23 bits of gather row: a graph of 2^23 - 1
+    nodes gets them (its highest rank, n - 1, still fits), one of 2^23 nodes
+    keeps layout 1's ids; either way queries and the stranger vector are
+    bitwise those of layout 1 and each query's mass is 1.  The edges join a
+    dense core of 2048 nodes to the top node ids, so that gather rows near
+    n - 1 appear in group items."""
+    rng = np.random.default_rng(47)
+    core = rng.integers(0, 2048, size=(2, 40000))
+    top = n - 1 - rng.integers(0, 2048, size=20000)
+    low = rng.integers(0, 2048, size=20000)
+    src = np.concatenate([core[0], top, low]).astype(np.int32)
+    dst = np.concatenate([core[1], low, top]).astype(np.int32)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    seeds = torch.tensor([3, 100, n - 1, n - 7], dtype=torch.int32).cuda()
+    res, mem = [], []
+    try:
+        for layout in (1, 2):
+            gg.set_gather_layout(layout)
+            gg.preprocess(c, T)
+            out = [gg.stranger()] + [gg.query(seeds[j:j + 1], c, S, T) for j in range(4)]
+            res.append(out)
+            mem.append(gg.device_bytes())
+    finally:
+        gg.set_gather_layout(2)
+    for i, (a, b) in enumerate(zip(res[0], res[1])):
+        assert torch.equal(a, b), i
+    for r in res[1][1:]:
+        assert abs(float(r.double().sum()) - 1.0) < 1e-4
+    assert mem[1] - mem[0] == (4 * gg.m if n < (1 << 23) else 0)
+
+
 # ---------------------------------------------------------------- packed
 def test_packed_blocks_equal_separate_graphs(tpa, torch):
     params = [(9, 4000, 1, 400), (10, 9000, 2, 0), (8, 1500, 3, 200)]
