@@ -588,7 +588,11 @@ tpa_status ensure_wz(tpa_graph *g, hipStream_t st) {
 
 tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) {
     Schedule *s = const_cast<Schedule *>(cs);  // an entry of g's schedule cache
-    if (g->gather_layout != 2 || !g->t_colz || s->colg || s->n_items == 0) return TPA_OK;
+    if (g->gather_layout != 2 || !g->t_colz || s->n_items == 0) return TPA_OK;
+    if (s->colg) {  // built before, set aside by a layout change: t_colz has not changed
+        s->colg_src = g->t_colz;
+        return TPA_OK;
+    }
     if (g->n >= kGroupSlotMaxN || s->ew > kGroupEdges) return TPA_OK;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return TPA_OK;
@@ -614,11 +618,8 @@ tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) 
 }
 
 void drop_group_order(tpa_graph *g) {
-    for (auto &kv : g->sched_t) {
-        dfree(kv.second.colg);
-        kv.second.colg = nullptr;
-        kv.second.colg_src = nullptr;
-    }
+    // the copies stay allocated (query graphs captured before may read them)
+    for (auto &kv : g->sched_t) kv.second.colg_src = nullptr;
 }
 
 // ------------------------------------------------------------------ schedule

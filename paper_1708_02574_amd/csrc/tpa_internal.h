@@ -105,7 +105,8 @@ struct Schedule {
     LongRow *longs = nullptr;    // device
     int64_t n_long = 0;
     // device, m: colg_src (the graph's t_colz) with group items in gather
-    // order (see kGroupEdges), built by ensure_group_order; null when absent
+    // order (see kGroupEdges), built by ensure_group_order; null when absent.
+    // The step launchers use colg only while colg_src is set (layout 2).
     int32_t *colg = nullptr;
     const int32_t *colg_src = nullptr;
     void release();
@@ -202,7 +203,8 @@ tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
 // under stream capture (the step kernels then read t_colz, with the same
 // sums).  Synchronous when it builds.
 tpa_status ensure_group_order(tpa_graph *g, const Schedule *s, hipStream_t stream);
-// Drop every schedule's colg (after the layout leaves group order).
+// Stop using every schedule's colg (after the layout leaves group order);
+// the arrays stay allocated until the handle is destroyed.
 void drop_group_order(tpa_graph *g);
 // Build t_wz from the current weights when the graph is weighted.
 tpa_status ensure_wz(tpa_graph *g, hipStream_t stream);

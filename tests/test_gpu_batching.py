@@ -114,3 +114,35 @@ def test_workspace_size_and_reserve(rmat13, torch):
     seeds = torch.from_numpy(ti.draw_seeds(og.export()["padded"] == 0, 100, 5)).cuda()
     R = gg.query(seeds, c, S, T)
     assert bool(torch.isfinite(R).all())
+
+
+def test_query_graph_keeps_group_order_copy(rmat13, torch):
+    """A single-seed query graph captured under layout 2 reads the
+    group-ordered column ids.  Switching to layout 1 afterwards keeps them
+    allocated, so the replays still give the same bits, and switching back
+    reuses the same copy (the handle's device bytes do not change)."""
+    og, gg = rmat13
+    seeds = torch.from_numpy(ti.draw_seeds(og.export()["padded"] == 0, 1, 48)).cuda()
+    gg.set_gather_layout(2)
+    ref = gg.query(seeds, c, S, T)
+    held = gg.device_bytes()
+    out = torch.empty_like(ref)
+    qg = gg.capture_query(c, S, T, out, seeds=seeds)
+    try:
+        gg.set_gather_layout(1)
+        assert gg.device_bytes() == held
+        for _ in range(3):
+            out.fill_(-1.0)
+            qg.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref)
+            assert torch.equal(gg.query(seeds, c, S, T), ref)
+        gg.set_gather_layout(2)
+        assert gg.device_bytes() == held
+        qg.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert torch.equal(gg.query(seeds, c, S, T), ref)
+    finally:
+        qg.close()
+        gg.set_gather_layout(2)
