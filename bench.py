@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seeds", type=int, default=N_SEEDS)
-    ap.add_argument("--cpu-queries", type=int, default=5)
+    ap.add_argument("--cpu-queries", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the untimed accuracy report and adjoint timing")
