@@ -305,7 +305,9 @@ tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
  * single-seed query or tpa_reserve; not during stream capture, where the
  * kernels read the order-1 ids instead) when the graph has fewer than
  * 2^23 nodes and the copy takes at most a quarter of the free device
- * memory.  Leaving layout 2 stops its use but keeps the copy (query
+ * memory.  tpa_backward's single-vector adjoint step gets one more such
+ * copy of A~'s destination ids (sorted by node id within its items, the
+ * gradients again bitwise those of order 1), built at its first call.  Leaving layout 2 stops its use but keeps the copy (query
  * graphs captured before may read it) until tpa_graph_destroy; coming
  * back uses it again.  Synchronous when it builds.  Errors: INVALID_ARG
  * (layout not 0, 1 or 2), OOM, HIP. */

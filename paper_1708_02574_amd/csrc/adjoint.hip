@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kGroupMax = 512;
+constexpr int kGroupMax = kGroupEdges;  // max edges of a group item (LDS floats per wave)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -58,6 +58,8 @@ struct AdjParams {
     int64_t n = 0;
     float *partials = nullptr;         // chunk partials [chunk items][kt]
     const float *gT = nullptr;         // kt == 64: grad_out tile node-major [n][64]
+    int col_slots = 0;                 // kt == 1: col is the schedule's colg (group items in
+                                       // gather order, each entry with its LDS slot); set by adj_step
 };
 
 __device__ __forceinline__ float g_of(const AdjParams &p, int64_t u, int j) {
@@ -77,6 +79,9 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
                                                          AdjParams p) {
     __shared__ float lds_v[kWaves][kGroupMax];
     __shared__ float lds_x[kWaves][kGroupMax];
+    // lambda(i)[v] by edge position, for the edge gradient of weighted
+    // graphs in gather order (lds_v then holds w * lambda)
+    __shared__ float lds_l[WEIGHTED && WITHG ? kWaves : 1][WEIGHTED && WITHG ? kGroupMax : 1];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
     if (wid >= n_items) return;
@@ -88,12 +93,20 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         constexpr int NS = kGroupMax / 64;
         const int nrows = (int)item_nrows(it.meta);
         const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        // In gather order (col_slots) entry e holds the destination to gather
+        // and, above it, the edge's position in the item: lambda goes to LDS
+        // at that position, so the row sums and the edge gradient (which read
+        // LDS by position) are those of the row order, bit for bit.
+        const bool slots = p.col_slots != 0;
         int32_t v[NS];
-        float gold[NS];  // G of the item's edges, read together with the column ids
+        int pos[NS];
+        float gold[NS];  // G of the item's edges (by position), read together with the column ids
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int e = s * 64 + lane;
-            v[s] = e < nnz ? col[e] : -1;
+            const uint32_t raw = e < nnz ? (uint32_t)col[e] : ~0u;
+            v[s] = e < nnz ? (int32_t)(slots ? raw & kGroupRowMask : raw) : -1;
+            pos[s] = slots ? (int)(raw >> kGroupSlotShift) : e;
             gold[s] = (WITHG && e < nnz) ? p.G[it.e0 + e] : 0.0f;
         }
         const float xr = (WITHG && lane < nrows) ? p.omc * p.xprev[it.row0 + lane] : 0.0f;
@@ -121,12 +134,32 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
             }
             wave_sync();
         }
+        if (!slots) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int e = s * 64 + lane;
-            if (s * 64 < nnz) {
-                if (WITHG && e < nnz) p.G[it.e0 + e] = gold[s] + mx[e] * l[s];
-                my[e] = (WEIGHTED && e < nnz) ? p.w[it.e0 + e] * l[s] : l[s];
+            for (int s = 0; s < NS; ++s) {
+                const int e = s * 64 + lane;
+                if (s * 64 < nnz) {
+                    if (WITHG && e < nnz) p.G[it.e0 + e] = gold[s] + mx[e] * l[s];
+                    my[e] = (WEIGHTED && e < nnz) ? p.w[it.e0 + e] * l[s] : l[s];
+                }
+            }
+        } else {
+            float *ml = lds_l[WEIGHTED && WITHG ? wv : 0];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (v[s] >= 0) {
+                    my[pos[s]] = WEIGHTED ? p.w[it.e0 + pos[s]] * l[s] : l[s];
+                    if (WEIGHTED && WITHG) ml[pos[s]] = l[s];
+                }
+            }
+            wave_sync();
+            if (WITHG) {
+                const float *lp = WEIGHTED ? ml : my;  // lambda(i)[v] by edge position
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const int e = s * 64 + lane;
+                    if (e < nnz) p.G[it.e0 + e] = gold[s] + mx[e] * lp[e];
+                }
             }
         }
         wave_sync();
@@ -479,7 +512,15 @@ void launch_adj_kt(const Schedule &s, const AdjParams &p, hipStream_t st) {
 #undef TPA_ADJ_CASE
 }
 
-tpa_status adj_step(const Schedule &s, const AdjParams &p, hipStream_t st) {
+tpa_status adj_step(const Schedule &s, const AdjParams &p0, hipStream_t st) {
+    // the single-vector step reads the schedule's group-ordered ids in place
+    // of A~'s own when it has them
+    AdjParams p = p0;
+    p.col_slots = 0;
+    if (p.kt == 1 && s.colg && p.col == s.colg_src) {
+        p.col = s.colg;
+        p.col_slots = 1;
+    }
     if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
         return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
     if (s.n_items > 0) {
@@ -573,6 +614,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
     if (hub) TPA_TRY(ensure_group_order(g, sf1, st));
+    TPA_TRY(ensure_group_order(g, sa1, st, true));
 
     if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));

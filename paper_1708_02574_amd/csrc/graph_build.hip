@@ -586,11 +586,13 @@ tpa_status ensure_wz(tpa_graph *g, hipStream_t st) {
     return TPA_OK;
 }
 
-tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) {
+tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st, bool over_a) {
     Schedule *s = const_cast<Schedule *>(cs);  // an entry of g's schedule cache
-    if (g->gather_layout != 2 || !g->t_colz || s->n_items == 0) return TPA_OK;
-    if (s->colg) {  // built before, set aside by a layout change: t_colz has not changed
-        s->colg_src = g->t_colz;
+    // forward: hub-first ids of A~^T (gather rows); adjoint: A~'s destination ids
+    const int32_t *src = over_a ? g->a.col : g->t_colz;
+    if (g->gather_layout != 2 || !src || s->n_items == 0) return TPA_OK;
+    if (s->colg) {  // built before, set aside by a layout change: src has not changed
+        s->colg_src = src;
         return TPA_OK;
     }
     if (g->n >= kGroupSlotMaxN || s->ew > kGroupEdges) return TPA_OK;
@@ -601,10 +603,10 @@ tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) 
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || (size_t)g->m * sizeof(int32_t) > free_b / 4) return TPA_OK;
     int32_t *colg = nullptr;
     if (dalloc(&colg, g->m, st) != TPA_OK) return TPA_OK;  // optional: the kernels read t_colz instead
-    hipError_t e = hipMemcpyAsync(colg, g->t_colz, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, st);
+    hipError_t e = hipMemcpyAsync(colg, src, sizeof(int32_t) * g->m, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) {
         const unsigned grid = (unsigned)std::min<int64_t>(s->n_items, int64_t(1) << 20);
-        group_order_kernel<<<grid, 256, 0, st>>>(s->items, s->n_items, g->t_colz, colg);
+        group_order_kernel<<<grid, 256, 0, st>>>(s->items, s->n_items, src, colg);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -613,13 +615,14 @@ tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st) 
         return fail(TPA_ERR_HIP, std::string("group order: ") + hipGetErrorString(e));
     }
     s->colg = colg;
-    s->colg_src = g->t_colz;
+    s->colg_src = src;
     return TPA_OK;
 }
 
 void drop_group_order(tpa_graph *g) {
     // the copies stay allocated (query graphs captured before may read them)
     for (auto &kv : g->sched_t) kv.second.colg_src = nullptr;
+    for (auto &kv : g->sched_a) kv.second.colg_src = nullptr;
 }
 
 // ------------------------------------------------------------------ schedule

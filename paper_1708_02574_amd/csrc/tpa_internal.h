@@ -104,8 +104,9 @@ struct Schedule {
     int64_t n_chunk_items = 0;
     LongRow *longs = nullptr;    // device
     int64_t n_long = 0;
-    // device, m: colg_src (the graph's t_colz) with group items in gather
-    // order (see kGroupEdges), built by ensure_group_order; null when absent.
+    // device, m: colg_src (the graph's t_colz, or a.col for a schedule over
+    // A~) with group items in gather order (see kGroupEdges), built by
+    // ensure_group_order; null when absent.
     // The step launchers use colg only while colg_src is set (layout 2).
     int32_t *colg = nullptr;
     const int32_t *colg_src = nullptr;
@@ -200,9 +201,11 @@ tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
 tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
 // Give a single-vector schedule its group-ordered column ids (colg) when
 // the graph's layout asks for them and they fit; a no-op otherwise, also
-// under stream capture (the step kernels then read t_colz, with the same
-// sums).  Synchronous when it builds.
-tpa_status ensure_group_order(tpa_graph *g, const Schedule *s, hipStream_t stream);
+// under stream capture (the step kernels then read the row-ordered ids,
+// with the same sums).  over_a: a schedule over the rows of A~ (the
+// adjoint), whose ids are A~'s destinations; else over A~^T, from t_colz.
+// Synchronous when it builds.
+tpa_status ensure_group_order(tpa_graph *g, const Schedule *s, hipStream_t stream, bool over_a = false);
 // Stop using every schedule's colg (after the layout leaves group order);
 // the arrays stay allocated until the handle is destroyed.
 void drop_group_order(tpa_graph *g);

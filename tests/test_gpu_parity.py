@@ -459,7 +459,9 @@ def test_group_order_is_bitwise_row_order(tpa, torch, weighted):
     single-seed queries (pushed, pulled, S = 2), exact CPI (seed and dense)
     and both gradients are bit for bit those of layout 1, with 1/outdeg and
     with logit weights (read through the slot).  The group-ordered ids are
-    one more int32 per edge, held only under layout 2."""
+    one more int32 per edge for each of the two single-vector schedules
+    (the forward's over A~^T and the adjoint's over A~), held only under
+    layout 2."""
     og = oracle.Graph.rmat(15, 300000, 41)
     gg = tpa.Graph.rmat(15, 300000, 41)
     if weighted:
@@ -499,7 +501,7 @@ def test_group_order_is_bitwise_row_order(tpa, torch, weighted):
         assert a is None or torch.equal(a, b), i
     for sv, r in zip(sd, res[1][1:7]):
         assert np.all(l1_rows(r.cpu().numpy(), og.query(int(sv), c, S, T)[None]) <= TOL)
-    assert mem[1] - mem[0] == 4 * gg.m
+    assert mem[1] - mem[0] == 8 * gg.m
 
 
 @pytest.mark.parametrize("n", [(1 << 23) - 1, 1 << 23])
