@@ -108,6 +108,14 @@ tpa_status tpa_graph_info(tpa_graph_t g, int64_t *n, int64_t *m, int64_t *nblock
  * Errors: INVALID_ARG (NULL). */
 tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes);
 
+/* A counter (host output) that changes whenever the graph's weights or its
+ * preprocessed state change: each tpa_graph_set_logits and each
+ * tpa_preprocess call moves it on.  A caller that keeps results derived
+ * from one state (for example a forward pass awaiting its derivative)
+ * compares it to tell whether the handle still holds that state.
+ * Errors: INVALID_ARG (NULL). */
+tpa_status tpa_graph_version(tpa_graph_t g, uint64_t *version);
+
 /* Host copy of the block offsets (nblocks + 1 entries). */
 tpa_status tpa_graph_blocks(tpa_graph_t g, int64_t *offsets_host);
 
@@ -139,6 +147,13 @@ tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hipStream_t s
  * eps <= 0), OOM, HIP. */
 tpa_status tpa_preprocess(tpa_graph_t g, double c, int T, hipStream_t stream);
 tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double eps, hipStream_t stream);
+
+/* The neighbor scale of Section 3.2 (host output): r~_neighbor = scale *
+ * r_family with scale = ((1-c)^S - (1-c)^T) / (1 - (1-c)^S), the ratio of
+ * the norms Lemma 2 gives; tpa_query's combine multiplies the family part
+ * by 1 + scale.  Errors: INVALID_ARG (NULL, c outside (0,1), S < 1,
+ * T < S). */
+tpa_status tpa_neighbor_scale(double c, int S, int T, double *scale);
 
 /* Copy r~_stranger (float[n]) out.  Errors: NOT_PREPROCESSED. */
 tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t stream);

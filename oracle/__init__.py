@@ -6,7 +6,7 @@ with it.
 
 Everything here is a thin ctypes wrapper around tpa_oracle.c (plain,
 single-threaded C in double precision).  What each function follows and
-what pins it (tests/test_oracle_*.py):
+what pins it (tests/test_oracle.py):
 
 * ``rmat``            R-MAT sampling with a SplitMix64 counter hash (input
                       generator, not paper arithmetic).  Pinned by quadrant

@@ -41,6 +41,8 @@ _SIGS = {
     "tpa_graph_destroy": (_i, [_vp]),
     "tpa_graph_info": (_i, [_vp, _vp, _vp, _vp]),
     "tpa_graph_blocks": (_i, [_vp, _vp]),
+    "tpa_graph_version": (_i, [_vp, _vp]),
+    "tpa_neighbor_scale": (_i, [_d, _i, _i, _vp]),
     "tpa_graph_device_bytes": (_i, [_vp, _vp]),
     "tpa_graph_export": (_i, [_vp, _i, _vp, _vp, _vp, _vp]),
     "tpa_graph_padded": (_i, [_vp, _vp, _vp]),
@@ -145,6 +147,13 @@ def _ptr(t):
     return _vp(t.data_ptr())
 
 
+def neighbor_scale(c: float, S: int, T: int) -> float:
+    """The closed-form neighbor scale of Section 3.2 (tpa_neighbor_scale)."""
+    v = C.c_double()
+    _call("tpa_neighbor_scale", c, S, T, C.byref(v))
+    return v.value
+
+
 def profile_code(kt: int, mode: int, first: bool, weighted: bool) -> int:
     """Variant code of a CPI step kernel for tpa_profile_read."""
     return 16 * (int(kt).bit_length() - 1) + 4 * mode + 2 * int(first) + int(weighted)
@@ -230,6 +239,12 @@ class Graph:
         out = np.empty(self.nblocks + 1, np.int64)
         _call("tpa_graph_blocks", self._h, out.ctypes.data_as(_vp))
         return out
+
+    def version(self) -> int:
+        """Counter of the weights / preprocessed state (tpa_graph_version)."""
+        v = C.c_uint64()
+        _call("tpa_graph_version", self._h, C.byref(v))
+        return v.value
 
     def export(self, transpose: bool = False, col: bool = True, weights: bool = True, stream=None):
         """(row_ptr, col, w) of A~ (or A~^T); col / w are None when not asked for."""
@@ -515,6 +530,16 @@ class QueryGraph:
             pass
 
 
+def _set_state(graph, theta, c, T, keep_iterates):
+    """Weights from theta, then preprocessing (the stranger part depends
+    on the weights), keeping the stranger chain's iterates for the adjoint
+    when asked."""
+    graph.set_logits(theta.detach())
+    if keep_iterates:
+        graph.set_keep_iterates(True)
+    graph.preprocess(c, T)
+
+
 def _autograd_function():
     import torch
 
@@ -531,23 +556,27 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, theta, Q, graph, c, S, T, checkpoint_every=0):
-            graph.set_logits(theta.detach())
-            # the backward then reads the stranger chain's iterates instead of
-            # recomputing them
-            if ctx.needs_input_grad[0] and checkpoint_every == 0:
-                graph.set_keep_iterates(True)
-            graph.preprocess(c, T)
+            keep = ctx.needs_input_grad[0] and checkpoint_every == 0
+            _set_state(graph, theta, c, T, keep)
             R = graph.query_dense(Q.detach(), c, S, T)
-            ctx.graph, ctx.args = graph, (c, S, T, checkpoint_every)
-            ctx.save_for_backward(Q)
+            ctx.graph, ctx.args = graph, (c, S, T, checkpoint_every, keep)
+            # the handle's state this output was computed from
+            ctx.version = graph.version()
+            ctx.save_for_backward(theta, Q)
             return R
 
         @staticmethod
         def backward(ctx, gR):
-            (Q,) = ctx.saved_tensors
-            c, S, T, ck = ctx.args
-            dth, dq = ctx.graph.backward(gR, c, S, T, q=Q, want_logits=ctx.needs_input_grad[0],
-                                         want_q=ctx.needs_input_grad[1], checkpoint_every=ck)
+            theta, Q = ctx.saved_tensors
+            c, S, T, ck, keep = ctx.args
+            g = ctx.graph
+            if g.version() != ctx.version:
+                # the graph was given other logits (or preprocessed again)
+                # since this forward: restore the forward's weights and
+                # stranger part, so the derivative is that of this output
+                _set_state(g, theta, c, T, keep)
+            dth, dq = g.backward(gR, c, S, T, q=Q, want_logits=ctx.needs_input_grad[0],
+                                 want_q=ctx.needs_input_grad[1], checkpoint_every=ck)
             return dth, dq, None, None, None, None, None
 
     return TPAFunction

@@ -22,7 +22,7 @@ intersection of the two top-k lists is taken on the host.
 """
 from __future__ import annotations
 
-from . import Graph, row_l1, topk
+from . import Graph, neighbor_scale, row_l1, topk
 
 
 def error_bounds(c: float, S: int, T: int) -> dict:
@@ -41,7 +41,7 @@ def error_report(g: Graph, seeds, c: float, S: int, T: int, eps: float = 1e-9, k
 
     seeds = [int(x) for x in seeds]
     sd = torch.tensor(seeds, dtype=torch.int32, device="cuda")
-    scale = ((1.0 - c) ** S - (1.0 - c) ** T) / (1.0 - (1.0 - c) ** S)
+    scale = neighbor_scale(c, S, T)
     stranger = g.stranger()
     exact = g.cpi_batch(c, 0, -1, eps, seeds=sd)
     st = g.cpi_batch(c, T, -1, eps, seeds=sd)
@@ -106,7 +106,7 @@ def st_sweep(g: Graph, seeds, c: float, pairs, eps: float = 1e-9, reps: int = 3)
                 torch.cuda.synchronize()
                 best = min(best, a.elapsed_time(b))
             err = row_l1(out, exact).cpu().tolist()
-            scale = ((1.0 - c) ** S - (1.0 - c) ** T) / (1.0 - (1.0 - c) ** S)
+            scale = neighbor_scale(c, S, T)
             nb_err = [0.0] * len(seeds)
             if S < T:
                 nb_err = row_l1(g.cpi_batch(c, 0, S - 1, eps, seeds=sd), g.cpi_batch(c, S, T - 1, eps, seeds=sd),

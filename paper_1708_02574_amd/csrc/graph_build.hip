@@ -975,6 +975,12 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     return TPA_OK;
 }
 
+extern "C" tpa_status tpa_graph_version(tpa_graph_t g, uint64_t *version) {
+    if (!g || !version) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    *version = g->version;
+    return TPA_OK;
+}
+
 extern "C" tpa_status tpa_graph_blocks(tpa_graph_t g, int64_t *offsets) {
     if (!g || !offsets) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
     std::copy(g->block_off.begin(), g->block_off.end(), offsets);
@@ -1009,6 +1015,7 @@ extern "C" tpa_status tpa_graph_set_logits(tpa_graph_t g, const float *theta, hi
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     g->preprocessed = false;
     g->xiter_K = 0;
+    ++g->version;
     if (!theta) {
         dfree(g->a.w); dfree(g->t.w);
         g->a.w = g->t.w = nullptr;

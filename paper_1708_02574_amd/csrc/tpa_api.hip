@@ -49,6 +49,15 @@ constexpr int kDefaultEW64 = 512;  // group edge budget, seed tiles
 
 }  // namespace
 
+// 1 + the neighbor scale of Section 3.2: r_family + r~_neighbor =
+// alpha r_family with alpha = (1 - (1-c)^T) / (1 - (1-c)^S), from the norms
+// of Lemma 2 (||r_family||_1 = 1 - (1-c)^S, ||r_neighbor||_1 = (1-c)^S -
+// (1-c)^T).
+double family_alpha(double c, int S, int T) {
+    const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
+    return (1.0 - pT) / (1.0 - pS);
+}
+
 // First i >= 1 with c (1-c)^i < eps: Algorithm 1's L1 break, with the
 // per-block norm ||x'(i)||_1 = c (1-c)^i of Lemma 2.
 int64_t stranger_last_iteration(double c, double eps) {
@@ -188,7 +197,6 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     // pulls after a push skip the rows it left zero (seed tiles of 1 and 64)
     const bool frontier = pp.wmax > 0 && (kt == 1 || kt == 64);
 
-    const double pS = std::pow(1.0 - c, (double)S), pT = std::pow(1.0 - c, (double)T);
     StepParams p;
     p.rowptr = g->t.rowptr;
     p.inv = g->inv_deg;
@@ -208,7 +216,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     p.kt = kt;
     p.node_block = packed ? g->node_block : nullptr;
     p.seed_stride = packed ? (int)k : 0;
-    p.alpha = (float)((1.0 - pT) / (1.0 - pS));  // 1 + neighbor scale
+    p.alpha = (float)family_alpha(c, S, T);  // 1 + neighbor scale
     p.str = g->str;
     p.out = out;
     p.n = g->n;
@@ -296,6 +304,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     if (T < 0) return fail(TPA_ERR_INVALID_ARG, "T must be >= 0");
     if (!(eps > 0.0)) return fail(TPA_ERR_INVALID_ARG, "eps must be > 0");
     g->preprocessed = false;
+    ++g->version;
     const int64_t K = stranger_last_iteration(c, eps);
     const Schedule *s = nullptr;
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &s));
@@ -364,6 +373,15 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
 
 extern "C" tpa_status tpa_preprocess(tpa_graph_t g, double c, int T, hipStream_t st) {
     return tpa_preprocess_ex(g, c, T, 1e-9, st);
+}
+
+extern "C" tpa_status tpa_neighbor_scale(double c, int S, int T, double *scale) {
+    if (!scale) return fail(TPA_ERR_INVALID_ARG, "scale is NULL");
+    if (!(c > 0.0 && c < 1.0)) return fail(TPA_ERR_INVALID_ARG, "c must lie in (0, 1)");
+    if (S < 1) return fail(TPA_ERR_INVALID_ARG, "S must be >= 1");
+    if (T < S) return fail(TPA_ERR_INVALID_ARG, "T must be >= S");
+    *scale = family_alpha(c, S, T) - 1.0;
+    return TPA_OK;
 }
 
 extern "C" tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t st) {

@@ -152,6 +152,9 @@ struct tpa_graph {
 
     // preprocessing state
     bool preprocessed = false;
+    // changes whenever the weights or the preprocessed state change
+    // (tpa_graph_set_logits, tpa_preprocess)
+    uint64_t version = 1;
     // stranger-chain iterates x'(0..K-1), node order, [K][n], kept by
     // tpa_preprocess when keep_iterates is on (for tpa_backward)
     bool keep_iterates = false;
@@ -184,6 +187,7 @@ struct tpa_graph {
 namespace tpa {
 
 int64_t stranger_last_iteration(double c, double eps);
+double family_alpha(double c, int S, int T);
 int choose_kt(const tpa_graph *g, int64_t k);
 SchedShape choose_shape(const tpa_graph *g, int kt);
 // Query driver; ws == nullptr uses (and grows) the handle's workspace.

@@ -206,6 +206,41 @@ def test_autograd_function(g10, tpa, torch):
     assert np.all(l1_rows(R.detach().cpu().numpy(), expect) <= TOL)
 
 
+def test_autograd_two_applies_on_one_graph(g10, tpa, torch):
+    """Two forward passes on one graph with different logits before either
+    backward: each output's gradients are those of its own logits (the
+    backward restores the weights and stranger part its forward used when
+    the graph has changed since), checked against the oracle."""
+    og, gg = g10
+    rng = np.random.default_rng(16)
+    Qn = rng.random((2, og.n))
+    Qn /= Qn.sum(axis=1, keepdims=True)
+    thetas = [torch.from_numpy(ti.draw_logits(og.m, 17 + i)).cuda().requires_grad_(True) for i in range(2)]
+    Qs = [torch.from_numpy(Qn.astype(np.float32)).cuda().requires_grad_(True) for _ in range(2)]
+    Ws = [torch.from_numpy(ti.draw_loss_weights((2, og.n), 19 + i)).cuda() for i in range(2)]
+    try:
+        Rs = [tpa.TPAFunction.apply(thetas[i], Qs[i], gg, c, S, T) for i in range(2)]
+        v_after_second = gg.version()
+        # the first output's backward runs while the graph holds the second theta
+        (Rs[0] * Ws[0]).sum().backward()
+        assert gg.version() != v_after_second
+        (Rs[1] * Ws[1]).sum().backward()
+        for i in range(2):
+            th = thetas[i].detach().cpu().numpy().astype(np.float64)
+            og.set_logits(th)
+            _, K = og.tpa_forward(Qn, c, S, T, EPS)
+            odth, _, odq = og.backward(Qn, Ws[i].cpu().numpy().astype(np.float64), c, S, T, K)
+            assert nl1(thetas[i].grad.cpu().numpy(), odth) <= TOL, i
+            assert nl1(Qs[i].grad.cpu().numpy(), odq) <= TOL, i
+            og.preprocess(c, T, EPS)
+            expect = np.stack([og.query_q(q, c, S, T) for q in Qn])
+            assert np.all(l1_rows(Rs[i].detach().cpu().numpy(), expect) <= TOL), i
+    finally:
+        gg.set_keep_iterates(False)
+        gg.set_logits(None)
+        og.set_logits(None)
+
+
 @pytest.mark.parametrize("weighted", [False, True])
 def test_backward_with_kept_iterates_is_bitwise_equal(g10, tpa, torch, weighted):
     """With tpa_set_keep_iterates the adjoint reads the stranger chain's

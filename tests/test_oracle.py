@@ -307,6 +307,42 @@ def test_error_bounds_against_exact_cpi():
         assert np.abs(exact - g.query(seed, c, S, T)).sum() <= 2 * (1 - c) ** S
 
 
+# ---------------------------------------------------------------- logit weights
+def test_softmax_weights_query_and_cpi_match_dense():
+    """Row-softmax weights from per-edge logits (the weighted A~ of the
+    adjoint's forward pass): the oracle's weights equal the dense softmax
+    written out from the edge list, its weighted TPA equals dense brute force
+    (family by matrix powers, stranger as dense PageRank minus its first T
+    terms), and weighted CPI to eps solves the RWR system (Theorem 1)."""
+    n, s, d = small_rmat(8, 1500, 606)
+    g = oracle.Graph(n, s, d)
+    ex = g.export()
+    rows = np.repeat(np.arange(n), np.diff(ex["a_rowptr"]))
+    theta = 0.5 * np.random.default_rng(607).standard_normal(g.m)
+    theta_mat = np.zeros((n, n))
+    theta_mat[rows, ex["a_col"]] = theta
+    At = dense_At_from_edges(n, s, d, theta_of=theta_mat)
+    g.set_logits(theta)
+    w = g.export()["a_w"]
+    # weights: A~_uv = exp(theta_uv) / sum_w exp(theta_uw), read off the dense matrix
+    assert np.abs(w - At.T[rows, ex["a_col"]]).max() < 1e-15
+    assert np.abs(w - 1.0 / np.diff(ex["a_rowptr"])[rows]).max() > 1e-3  # not the uniform weights
+    st = g.preprocess(c, T, EPS)
+    b = np.full(n, 1.0 / n)
+    p = np.linalg.solve(np.eye(n) - (1 - c) * At, c * b)
+    assert np.abs(st - (p - dense_cpi_window(At, b, 0, T - 1))).sum() <= (1 - c) ** (g.K + 1) + 1e-12
+    alpha = (1 - (1 - c) ** T) / (1 - (1 - c) ** S)
+    st_dense = dense_cpi_window(At, b, T, g.K)
+    for seed in (0, 7, 100, 255):
+        expect = alpha * dense_cpi_window(At, e(n, seed), 0, S - 1) + st_dense
+        assert np.abs(g.query(seed, c, S, T) - expect).sum() < 1e-13
+        r, _ = g.cpi(e(n, seed), c, 1e-15, 0, -1)
+        r_solve = np.linalg.solve(np.eye(n) - (1 - c) * At, c * e(n, seed))
+        assert np.abs(r - r_solve).sum() < 1e-12
+    g.set_logits(None)
+    assert np.array_equal(g.export()["a_w"], ex["a_w"])
+
+
 # ---------------------------------------------------------------- adjoint
 def test_adjoint_matches_central_differences():
     """Oracle gradient of L = sum_j <w_j, r_TPA(q_j)> w.r.t. edge logits and
@@ -376,3 +412,36 @@ def test_topk_defining_properties():
             for v in np.unique(ks):
                 pos = sel[ks == v]
                 assert np.all(np.diff(pos) > 0)
+
+
+# ---------------------------------------------------------------- structured closed form
+def test_structured_closed_form_helper_matches_oracle():
+    """The O(n) closed-form helper that checks the GPU path on a graph with
+    more than 2^31 edges (tests/closed_form.py: complete digraph block,
+    two-successor circulant, isolated nodes), pinned on a small instance of
+    the same structure against the oracle: CSR offsets, stranger, TPA for
+    seeds in each part and a dense restart, restart and logit gradients."""
+    from closed_form import Structured
+    cf = Structured(nc=12, L=9, D=3)
+    src, dst = cf.edge_list(order_seed=5)
+    g = oracle.Graph(cf.n, src.astype(np.int32), dst.astype(np.int32))
+    assert (g.n, g.m) == (cf.n, cf.m)
+    ex = g.export()
+    assert np.array_equal(ex["a_rowptr"], cf.a_rowptr())
+    rows = np.repeat(np.arange(cf.n), np.diff(ex["a_rowptr"]))
+    sel = rows < cf.i0
+    assert np.array_equal(cf.edge_index(rows[sel], ex["a_col"][sel]), np.flatnonzero(sel))
+    st = g.preprocess(c, T, EPS)
+    assert np.abs(st - cf.stranger(c, T, g.K)).sum() < 1e-15
+    rng = np.random.default_rng(6)
+    qd = rng.random(cf.n)
+    qd /= qd.sum()
+    Q = np.stack([e(cf.n, 3), e(cf.n, cf.c0 + 7), e(cf.n, cf.i0 + 1), qd])
+    for q in Q:
+        assert np.abs(g.query_q(q, c, S, T) - cf.tpa(q, c, S, T, g.K)).sum() < 1e-14
+    W = rng.standard_normal((4, cf.n))
+    dth, _, dq = g.backward(Q, W, c, S, T, g.K)
+    dQ, dtheta = cf.backward(Q, W, c, S, T, g.K)
+    assert np.abs(dq - dQ).max() < 1e-13 * np.abs(dQ).max()
+    assert np.abs(dth[sel] - dtheta(rows[sel], ex["a_col"][sel])).max() < 1e-12 * np.abs(dth).max()
+    assert np.all(dth[~sel] == 0.0)
