@@ -174,6 +174,25 @@ tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t stream);
 tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
                      float *out, hipStream_t stream);
 
+/* tpa_query for callers that cannot allocate device memory (code under HIP
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results as tpa_query (bitwise), but the workspace is
+ * a fixed device array inside the library, 64 MiB per device, held from the
+ * first call on a device until the process ends, and no call here allocates
+ * or frees device memory.  The work schedule of the seed tile tpa_query
+ * would use must exist already: tpa_preprocess builds the single-seed one;
+ * for k > 1 call tpa_reserve(g, k) (or one tpa_query of k seeds) first.
+ * The workspace a query needs is tpa_query_workspace_size's figure without
+ * the dense-restart tile: about 16 bytes per node for one seed and 8*kt
+ * more per node for a seed tile of kt columns.  Every call on one device
+ * shares the array (the state the previous call left is cleared where it
+ * must start at zero), so calls that overlap on one device, from any
+ * stream, thread or graph, race and must be serialised by the caller.
+ * Errors: as tpa_query, and INVALID_ARG when the schedule is missing or the
+ * workspace would exceed the 64 MiB (the message gives the size needed). */
+tpa_status tpa_query_noalloc(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
+                             float *out, hipStream_t stream);
+
 /* Online phase on a block-diagonal graph with `per_block` seed slots per
  * block: seeds[b*per_block + j] is a node of block b; out[j*n + v] is the
  * r_TPA of block(v)'s j-th seed at node v (float[per_block][n]).  One

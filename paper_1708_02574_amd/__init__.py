@@ -51,6 +51,7 @@ _SIGS = {
     "tpa_preprocess_ex": (_i, [_vp, _d, _i, _d, _vp]),
     "tpa_stranger": (_i, [_vp, _vp, _vp]),
     "tpa_query": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
+    "tpa_query_noalloc": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_query_packed": (_i, [_vp, _vp, _i, _d, _i, _i, _vp, _vp]),
     "tpa_query_dense": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_backward": (_i, [_vp, _vp, _vp, _i64, _i, _d, _i, _i, _vp, _vp, _vp, _i, _vp]),
@@ -294,6 +295,18 @@ class Graph:
         elif out.shape != (k, self.n) or out.dtype != torch.float32 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float32 [k, n] device tensor")
         _call("tpa_query", self._h, _ptr(sd), k, c, S, T, _ptr(out), _stream(stream))
+        return out
+
+    def query_noalloc(self, seeds, c: float, S: int, T: int, out, stream=None):
+        """tpa_query_noalloc: r_TPA for each seed into out [k, n] with the
+        library's fixed workspace (no device allocation in the call)."""
+        torch = _torch()
+        if seeds.dtype != torch.int32 or not seeds.is_cuda or not seeds.is_contiguous():
+            raise ValueError("seeds must be a contiguous int32 device tensor")
+        k = seeds.numel()
+        if out.shape != (k, self.n) or out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 [k, n] device tensor")
+        _call("tpa_query_noalloc", self._h, _ptr(seeds), k, c, S, T, _ptr(out), _stream(stream))
         return out
 
     def query_packed(self, seeds, c: float, S: int, T: int, out=None, stream=None):

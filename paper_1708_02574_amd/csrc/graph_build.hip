@@ -643,6 +643,12 @@ void Schedule::release() {
 //   * runs of rows with <= EW edges: greedy groups of at most 63 rows and
 //     EW edges (rows of <= DS = 32 edges are summed one lane per row, longer
 //     ones by the whole wave).
+const Schedule *find_schedule(const tpa_graph *g, SchedShape shape, bool over_a) {
+    const auto &cache = over_a ? g->sched_a : g->sched_t;
+    auto it = cache.find(shape);
+    return it == cache.end() ? nullptr : &it->second;
+}
+
 tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t st, const Schedule **out, bool over_a) {
     auto &cache = over_a ? g->sched_a : g->sched_t;
     const int64_t *rowptr_dev = over_a ? g->a.rowptr : g->t.rowptr;

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cpi_kernels.h"
@@ -170,15 +171,23 @@ size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st
 }
 
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes) {
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc) {
     TPA_TRY(check_query_args(g, c, S, T));
     if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
     if (k == 0) return TPA_OK;
     if ((!seeds && !q) || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/q/out is NULL");
     if (packed && !g->node_block) return fail(TPA_ERR_INVALID_ARG, "graph is not packed");
+    if (no_alloc && !ws) return fail(TPA_ERR_INVALID_ARG, "a query without allocation needs a workspace");
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
-    TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
+    if (no_alloc) {
+        s = find_schedule(g, choose_shape(g, kt));
+        if (!s)
+            return fail(TPA_ERR_INVALID_ARG, "no work schedule for this seed tile yet (building one allocates): "
+                                             "call tpa_reserve(g, k) or run one tpa_query of k seeds first");
+    } else {
+        TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
+    }
     if (ws) {
         if (ws_bytes < query_ws_bytes(g, s, kt, q != nullptr)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
     } else {
@@ -205,7 +214,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     // gathered vectors in hub-first rows (first steps read node ids: t.col
     // and t.w in A~^T's own order)
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
-    if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, st));  // a no-op under capture
+    if (hub && kt == 1 && !no_alloc) TPA_TRY(ensure_group_order(g, s, st));  // a no-op under capture
     p.zperm = hub ? g->zperm : nullptr;
     const int32_t *col_gather = hub ? g->t_colz : g->t.col;
     const float *w_gather = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
@@ -253,8 +262,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                     // the conversion that clears acc may not have run: restore
                     // the all-zero push state before reporting the error
                     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-                    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
-                        (void)clear_push_state(g, ws, st);
+                    if (!no_alloc && hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+                        (void)clear_push_state(g, ws, st);  // (the no-allocation path clears it per call)
                     return rc;
                 }
                 continue;
@@ -503,4 +512,68 @@ extern "C" tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t st) {
         return fail(TPA_ERR_INVALID_ARG, "a query saw a seed outside [0, n) or outside its block");
     }
     return TPA_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation query
+// For callers that cannot allocate device memory (code under stream capture,
+// serving loops, harnesses that forbid hipMalloc): the query workspace is a
+// file-scope device array of kScratchBytes, one copy per device, held until
+// the process ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name is a
+// host-side stand-in there).  Every call on a device shares that device's
+// array and finds the previous call's contents, so the part that must start
+// at zero (the push accumulator) is cleared by a fill kernel on every call;
+// calls that overlap on one device race.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of the current device's scratch array, looked up once per
+// device with that device current.
+tpa_status scratch_address(void **out) {
+    int dev = 0;
+    TPA_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(TPA_ERR_INVALID_ARG, "device ordinal out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TPA_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TPA_OK;
+}
+
+}  // namespace
+
+extern "C" tpa_status tpa_query_noalloc(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, int S, int T,
+                                        float *out, hipStream_t st) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
+    if (k == 0) return TPA_OK;
+    TPA_TRY(check_query_args(g, c, S, T));
+    if (!seeds || !out) return fail(TPA_ERR_INVALID_ARG, "seeds/out is NULL");
+    const int kt = choose_kt(g, k);
+    const Schedule *s = find_schedule(g, choose_shape(g, kt));
+    if (!s)
+        return fail(TPA_ERR_INVALID_ARG, "no work schedule for this seed tile yet (building one allocates): "
+                                         "call tpa_reserve(g, k) or run one tpa_query of k seeds first");
+    const size_t need = query_ws_bytes(g, s, kt, false);
+    if (need > kScratchBytes)
+        return fail(TPA_ERR_INVALID_ARG, "the query needs " + std::to_string(need) +
+                                             " bytes of workspace; tpa_query_noalloc holds at most " +
+                                             std::to_string(kScratchBytes));
+    void *ws = nullptr;
+    TPA_TRY(scratch_address(&ws));
+    // the push accumulator must be all zero when a query starts
+    TPA_TRY(launch_fill_zero(static_cast<float *>(ws), (int64_t)(push_plan_bytes(g->n, g->max_outdeg) / 4), st));
+    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st, static_cast<float *>(ws), kScratchBytes, true);
 }

@@ -191,8 +191,10 @@ double family_alpha(double c, int S, int T);
 int choose_kt(const tpa_graph *g, int64_t k);
 SchedShape choose_shape(const tpa_graph *g, int kt);
 // Query driver; ws == nullptr uses (and grows) the handle's workspace.
+// no_alloc: allocate nothing (the work schedule must exist already and the
+// group-ordered ids are used only if built; ws must be given).
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes);
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc = false);
 size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st);
 // Zero the push state at the front of a fresh query workspace.
 tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st);
@@ -200,6 +202,8 @@ tpa_status build_from_keys(tpa_graph *g, uint64_t *keys, int64_t nkeys, hipStrea
 // Work schedule over the rows of A~^T (over_a = false) or of A~ (true).
 tpa_status get_schedule(tpa_graph *g, SchedShape shape, hipStream_t stream, const Schedule **out,
                         bool over_a = false);
+// The cached schedule of that shape, or null (never builds one).
+const Schedule *find_schedule(const tpa_graph *g, SchedShape shape, bool over_a = false);
 tpa_status ensure_t2a(tpa_graph *g, hipStream_t stream);
 // Build zperm, t_colz and t_locz (synchronises `stream`); no-op when present.
 tpa_status ensure_zlayout(tpa_graph *g, hipStream_t stream);
