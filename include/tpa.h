@@ -155,6 +155,12 @@ tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double eps, hipStre
  * T < S). */
 tpa_status tpa_neighbor_scale(double c, int S, int T, double *scale);
 
+/* Parameters of the last tpa_preprocess (host outputs, any may be NULL):
+ * c, T, eps and K, the last iteration of the stranger chain (the first i
+ * with c (1-c)^i < eps).  Errors: INVALID_ARG (NULL graph),
+ * NOT_PREPROCESSED. */
+tpa_status tpa_preprocess_info(tpa_graph_t g, double *c, int *T, double *eps, int64_t *K);
+
 /* Copy r~_stranger (float[n]) out.  Errors: NOT_PREPROCESSED. */
 tpa_status tpa_stranger(tpa_graph_t g, float *out, hipStream_t stream);
 

@@ -50,6 +50,7 @@ _SIGS = {
     "tpa_preprocess": (_i, [_vp, _d, _i, _vp]),
     "tpa_preprocess_ex": (_i, [_vp, _d, _i, _d, _vp]),
     "tpa_stranger": (_i, [_vp, _vp, _vp]),
+    "tpa_preprocess_info": (_i, [_vp, _vp, _vp, _vp, _vp]),
     "tpa_query": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_query_noalloc": (_i, [_vp, _vp, _i64, _d, _i, _i, _vp, _vp]),
     "tpa_query_packed": (_i, [_vp, _vp, _i, _d, _i, _i, _vp, _vp]),
@@ -278,6 +279,13 @@ class Graph:
             _call("tpa_preprocess", self._h, c, T, _stream(stream))
         else:
             _call("tpa_preprocess_ex", self._h, c, T, eps, _stream(stream))
+
+    def preprocess_info(self) -> dict:
+        """c, T, eps and K (the stranger chain's last iteration) of the last
+        preprocessing (tpa_preprocess_info)."""
+        cc, tt, ee, kk = C.c_double(), C.c_int(), C.c_double(), C.c_int64()
+        _call("tpa_preprocess_info", self._h, C.byref(cc), C.byref(tt), C.byref(ee), C.byref(kk))
+        return {"c": cc.value, "T": tt.value, "eps": ee.value, "K": kk.value}
 
     def stranger(self, stream=None):
         torch = _torch()

@@ -384,6 +384,16 @@ extern "C" tpa_status tpa_preprocess(tpa_graph_t g, double c, int T, hipStream_t
     return tpa_preprocess_ex(g, c, T, 1e-9, st);
 }
 
+extern "C" tpa_status tpa_preprocess_info(tpa_graph_t g, double *c, int *T, double *eps, int64_t *K) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (!g->preprocessed) return fail(TPA_ERR_NOT_PREPROCESSED, "tpa_preprocess has not run on this graph");
+    if (c) *c = g->c;
+    if (T) *T = g->T;
+    if (eps) *eps = g->eps;
+    if (K) *K = g->K;
+    return TPA_OK;
+}
+
 extern "C" tpa_status tpa_neighbor_scale(double c, int S, int T, double *scale) {
     if (!scale) return fail(TPA_ERR_INVALID_ARG, "scale is NULL");
     if (!(c > 0.0 && c < 1.0)) return fail(TPA_ERR_INVALID_ARG, "c must lie in (0, 1)");
