@@ -71,15 +71,19 @@ def test_rmat20_bench_configuration(tpa, torch):
 
 
 def test_rmat22_batched_sampled(tpa, torch):
-    """2^22 nodes, 2^26 samples, 1024 seeds in one batched call (kt=64)."""
+    """2^22 nodes, 2^26 samples, 1024 seeds in one batched call: eager with
+    tiles of 64 and 512-edge groups, then in the configuration bench.py
+    times -- the autotuner's choice, replayed from a captured HIP graph
+    (twice) -- with sampled seeds of both against the oracle."""
     scale, samples, gseed = ti.GRAPHS["rmat22"]
     print("rmat22: GPU build + preprocess + 1024-seed query", flush=True)
     gg = tpa.Graph.rmat(scale, samples, gseed)
     gg.preprocess(c, T)
     eligible = (gg.padded() == 0).cpu().numpy()
     seeds = ti.draw_seeds(eligible, 1024, 2)
+    sd = torch.from_numpy(seeds).cuda()
     gg.set_tuning(seed_tile=64)
-    R = gg.query(torch.from_numpy(seeds).cuda(), c, S, T)
+    R = gg.query(sd, c, S, T)
     gg.set_tuning(seed_tile=0)
     mass = R.sum(dim=1, dtype=torch.float64).cpu().numpy()
     assert np.all(np.abs(mass - MASS) < 1e-5)
@@ -87,14 +91,34 @@ def test_rmat22_batched_sampled(tpa, torch):
     sample = [0, 517, 1023]
     Rs = R[sample].cpu().numpy()
     st = gg.stranger().cpu().numpy()
-    del R
-    print("rmat22: oracle build + preprocess", flush=True)
+    print("rmat22: autotune + captured query", flush=True)
+    tile, ew, _ = gg.autotune(sd, c, S, T, scratch_out=R)
+    gg.reserve(1024)
+    out = torch.full_like(R, float("nan"))
+    qg = gg.capture_query(c, S, T, out, seeds=sd)
+    qg.launch()
+    torch.cuda.synchronize()
+    first = out.clone()
+    qg.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(first, out)
+    eager = gg.query(sd, c, S, T)
+    assert torch.equal(eager, out)  # the replay equals the eager query of the same tuning
+    mass = out.sum(dim=1, dtype=torch.float64).cpu().numpy()
+    assert np.all(np.abs(mass - MASS) < 1e-5)
+    Rc = out[sample].cpu().numpy()
+    qg.close()
+    gg.set_tuning(0, 0)
+    del R, out, first, eager
+    print(f"rmat22: oracle build + preprocess (autotuned tile {tile}, {ew}-edge groups)", flush=True)
     og = oracle.Graph.rmat(scale, samples, gseed)
     assert og.m == gg.m
     og.preprocess(c, T, EPS)
     assert l1_rows(st, og.str) <= TOL
     for r, i in enumerate(sample):
-        assert l1_rows(Rs[r], og.query(int(seeds[i]), c, S, T)) <= TOL
+        expect = og.query(int(seeds[i]), c, S, T)
+        assert l1_rows(Rs[r], expect) <= TOL
+        assert l1_rows(Rc[r], expect) <= TOL
 
 
 def nl1(a, b):

@@ -509,9 +509,9 @@ def test_group_order_node_id_limit(tpa, torch, n):
     """The group-ordered ids keep 23 bits of gather row: a graph of 2^23 - 1
     nodes gets them (its highest rank, n - 1, still fits), one of 2^23 nodes
     keeps layout 1's ids; either way queries and the stranger vector are
-    bitwise those of layout 1 and each query's mass is 1.  The edges join a
-    dense core of 2048 nodes to the top node ids, so that gather rows near
-    n - 1 appear in group items."""
+    bitwise those of layout 1, each query's mass is 1, and both are within
+    L1 <= 1e-5 of the oracle.  The edges join a dense core of 2048 nodes to
+    the top node ids, so that gather rows near n - 1 appear in group items."""
     rng = np.random.default_rng(47)
     core = rng.integers(0, 2048, size=(2, 40000))
     top = n - 1 - rng.integers(0, 2048, size=20000)
@@ -535,6 +535,14 @@ def test_group_order_node_id_limit(tpa, torch, n):
     for r in res[1][1:]:
         assert abs(float(r.double().sum()) - 1.0) < 1e-4
     assert mem[1] - mem[0] == (4 * gg.m if n < (1 << 23) else 0)
+    # and against the oracle
+    og = oracle.Graph(n, src, dst)
+    assert og.m == gg.m
+    og.preprocess(c, T, EPS)
+    assert np.abs(res[1][0].cpu().numpy().astype(np.float64) - og.str).sum() <= 1e-5
+    for j, s in enumerate(seeds.cpu().tolist()):
+        got = res[1][1 + j][0].cpu().numpy().astype(np.float64)
+        assert np.abs(got - og.query(int(s), c, S, T)).sum() <= 1e-5, s
 
 
 # ---------------------------------------------------------------- packed
