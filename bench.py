@@ -281,7 +281,8 @@ def headline(tpa, torch, np, ti, args) -> dict:
                              bytes_stranger(n, m, K, T_STR), *prof[cs],
                              traffic_from_profile("step_kernel_1_stranger_rmat27_traffic")),
         "roofline_batched": roofline(f"step_kernel_kt<16, family> ({k}-seed tile CPI step)",
-                                     bytes_sweep(n, m, 16), *prof[cf16]),
+                                     bytes_sweep(n, m, 16), *prof[cf16],
+                                     traffic_from_profile("step_kernel_16_family_rmat27_traffic")),
         "roofline_plain": roofline("step_kernel_1<family> (single-seed CPI step)", bytes_sweep(n, m, 1),
                                    *prof[cf1]),
         "checks": checks,
@@ -378,7 +379,8 @@ def rmat20(tpa, torch, np, ti, args, oracle_out) -> dict:
            "roofline_batched": roofline("step_kernel_64<family> (64-seed tile CPI step)", bytes_sweep(n, m, 64),
                                         *prof[cf64], traffic_from_profile("step_kernel_64_family_rmat20_traffic")),
            "roofline_preprocess": roofline("step_kernel_1<stranger> (preprocessing CPI step)",
-                                           bytes_stranger(n, m, K, T_STR), *prof[cs]),
+                                           bytes_stranger(n, m, K, T_STR), *prof[cs],
+                                           traffic_from_profile("step_kernel_1_stranger_rmat20_traffic")),
            "checks": checks}
     if not args.no_extras:
         rec.update(rmat20_extras(tpa, g, seeds, seeds_h, torch, np, K))
