@@ -190,7 +190,10 @@ tpa_status tpa_query(tpa_graph_t g, const int32_t *seeds, int64_t k, double c, i
  * for k > 1 call tpa_reserve(g, k) (or one tpa_query of k seeds) first.
  * The workspace a query needs is tpa_query_workspace_size's figure without
  * the dense-restart tile: about 16 bytes per node for one seed and 8*kt
- * more per node for a seed tile of kt columns.  Every call on one device
+ * more per node for a seed tile of kt columns, and for a tile whose second
+ * step may be pushed (tpa_set_tile_push_limit) its push buffer: 8*kt bytes
+ * per node, about 400 KB of plan and m/8 bytes of pieces, cleared per
+ * call.  Every call on one device
  * shares the array (the state the previous call left is cleared where it
  * must start at zero), so calls that overlap on one device, from any
  * stream, thread or graph, race and must be serialised by the caller.
@@ -311,6 +314,26 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * skip off.
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
+
+/* Direction of the second family step of a seed tile (2..64 one-hot
+ * columns, unpacked graph, S >= 4), the tile form of the single seed's
+ * pushed step (Section 2.3's CPI step, over the columns' frontiers).
+ * Column j's x(1) lives on F_j = out(s_j) + {s_j}; the device plans the
+ * tile (one entry per node of every F_j) and pushes step 2 over their
+ * out-edges when the plan has at most 16384 entries and the tile's
+ * frontier edge count W = sum over j of sum over F_j of outdeg is at most
+ * `max_edges`; it pulls otherwise.  The pushed step also replaces the
+ * pushed first step (y1 is folded into the plan).  max_edges = -1 restores
+ * the default (m/4, at least 2048), 0 always pulls.  The pushed sums are
+ * exact fixed-point additions of FP32 terms (reproducible, and within FP32
+ * rounding of the pulled step).  The push needs a buffer of 8 bytes per
+ * node and column (allocated on the handle at the first such query, or by
+ * tpa_reserve; not under stream capture; none above 32 GiB or a quarter of
+ * the free device memory, when tiles pull).  Captured query graphs hold
+ * their own buffer; tpa_query_noalloc takes it from its fixed array.
+ * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
+tpa_status tpa_set_tile_push_limit(tpa_graph_t g, int64_t max_edges);
+tpa_status tpa_get_tile_push_limit(tpa_graph_t g, int64_t *max_edges);
 
 /* Keep the stranger chain's iterates (Algorithm 2's x'(0) .. x'(K-1), node
  * order, K x n floats) on the handle at the next tpa_preprocess, so that

@@ -69,6 +69,8 @@ _SIGS = {
     "tpa_set_gather_layout": (_i, [_vp, _i]),
     "tpa_get_gather_layout": (_i, [_vp, _vp]),
     "tpa_get_push_limit": (_i, [_vp, _vp]),
+    "tpa_set_tile_push_limit": (_i, [_vp, _i64]),
+    "tpa_get_tile_push_limit": (_i, [_vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
     "tpa_cpi": (_i, [_vp, C.c_int32, _vp, _d, _i, _i, _d, _vp, _vp]),
     "tpa_cpi_batch": (_i, [_vp, _vp, _vp, _i64, _d, _i, _i, _d, _vp, _vp]),
@@ -483,6 +485,17 @@ class Graph:
     def get_push_limit(self) -> int:
         v = C.c_int64()
         _call("tpa_get_push_limit", self._h, C.byref(v))
+        return v.value
+
+    def set_tile_push_limit(self, max_edges: int = -1):
+        """Seed tiles (2..64 seeds) push their second family step when the
+        tile's frontier edges, summed over its columns, number at most
+        max_edges (-1: default m/4, 0: always pull)."""
+        _call("tpa_set_tile_push_limit", self._h, max_edges)
+
+    def get_tile_push_limit(self) -> int:
+        v = C.c_int64()
+        _call("tpa_get_tile_push_limit", self._h, C.byref(v))
         return v.value
 
     def get_tuning(self):

@@ -60,7 +60,12 @@ struct AdjParams {
     const float *gT = nullptr;         // kt == 64: grad_out tile node-major [n][64]
     int col_slots = 0;                 // kt == 1: col is the schedule's colg (group items in
                                        // gather order, each entry with its LDS slot); set by adj_step
+    const int32_t *lrow = nullptr;     // row of node v in lambda (rank by in-degree; null: v);
+                                       // col then holds rows of lambda
 };
+
+// Row of node u in the lambda vectors.
+__device__ __forceinline__ int64_t lam_row(const AdjParams &p, int64_t u) { return p.lrow ? p.lrow[u] : u; }
 
 __device__ __forceinline__ float g_of(const AdjParams &p, int64_t u, int j) {
     if (p.kt == 1) return p.gvec[u];
@@ -70,7 +75,7 @@ __device__ __forceinline__ float g_of(const AdjParams &p, int64_t u, int j) {
 // lambda(i-1)[u][j] = beta g + (1-c) * (explicit weights ? sum : sum / outdeg(u))
 __device__ __forceinline__ void adj_epilogue(const AdjParams &p, int64_t u, int j, float sum) {
     const float s = p.w ? sum : sum * p.inv[u];
-    p.lam_out[u * p.kt + j] = fmaf(p.beta, g_of(p, u, j), p.omc * s);
+    p.lam_out[lam_row(p, u) * p.kt + j] = fmaf(p.beta, g_of(p, u, j), p.omc * s);
 }
 
 // ------------------------------------------------------------ kt == 1
@@ -113,6 +118,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         // epilogue operands of row (row0 + lane), loaded ahead
         const float gu = lane < nrows ? p.gvec[it.row0 + lane] : 0.0f;
         const float iu = (!WEIGHTED && lane < nrows) ? p.inv[it.row0 + lane] : 0.0f;
+        const int32_t lr = lane < nrows ? (int32_t)lam_row(p, it.row0 + lane) : 0;
         float l[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) l[s] = v[s] >= 0 ? p.lam_in[v[s]] : 0.0f;
@@ -166,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         if (lane < nrows && len <= 32) {
             float acc = 0.0f;
             for (int k = rel; k < rel_next; ++k) acc += my[k];
-            p.lam_out[it.row0 + lane] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? acc : acc * iu));
+            p.lam_out[lr] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? acc : acc * iu));
         }
         uint64_t big = __ballot(lane < nrows && len > 32);
         while (big) {
@@ -179,7 +185,8 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
             for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
             const float gr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gu), r));
             const float ir = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(iu), r));
-            if (lane == 0) p.lam_out[it.row0 + r] = fmaf(p.beta, gr, p.omc * (WEIGHTED ? t : t * ir));
+            const int32_t lrr = __builtin_amdgcn_readlane(lr, r);
+            if (lane == 0) p.lam_out[lrr] = fmaf(p.beta, gr, p.omc * (WEIGHTED ? t : t * ir));
         }
         return;
     }
@@ -216,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
     for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
     if (lane == 0) {
         if (whole)
-            p.lam_out[row] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? s : s * iu));
+            p.lam_out[lam_row(p, row)] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? s : s * iu));
         else
             p.partials[wid] = s;
     }
@@ -301,6 +308,7 @@ __device__ __forceinline__ void adj_item_64(const AdjParams &p, const Item it, i
     const int64_t row0 = chunk ? (int64_t)p.longs[it.row0].row : (int64_t)it.row0;
     const int rel = group ? (lane <= nrows ? (int)(p.rowptr[row0 + lane] - it.e0) : nnz) : (lane == 0 ? 0 : nnz);
     const float inv_l = (!WEIGHTED && lane < nrows) ? p.inv[row0 + lane] : 0.0f;
+    const int32_t lr_l = (!chunk && lane < nrows) ? (int32_t)lam_row(p, row0 + lane) : 0;
     int r = 0;
     int rend = __builtin_amdgcn_readlane(rel, 1);
     float xr = WITHG ? p.omc * p.xprev[row0 * 64 + lane] : 0.0f;
@@ -316,7 +324,7 @@ __device__ __forceinline__ void adj_item_64(const AdjParams &p, const Item it, i
             p.partials[wid * 64 + lane] = acc;
         } else {
             const float sc = WEIGHTED ? acc : acc * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inv_l), r));
-            p.lam_out[(row0 + r) * 64 + lane] = fmaf(p.beta, gc, p.omc * sc);
+            p.lam_out[(int64_t)__builtin_amdgcn_readlane(lr_l, r) * 64 + lane] = fmaf(p.beta, gc, p.omc * sc);
         }
         acc = 0.0f;
         ++r;
@@ -418,7 +426,7 @@ __global__ void lam_init_kernel(AdjParams p, float *lam) {
     const int kt = p.kt;
     if (kt == 1) {
         for (int i = threadIdx.x; i < 64; i += blockDim.x)
-            if (v0 + i < p.n) lam[v0 + i] = p.beta * p.gvec[v0 + i];
+            if (v0 + i < p.n) lam[lam_row(p, v0 + i)] = p.beta * p.gvec[v0 + i];
         return;
     }
     for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
@@ -430,7 +438,7 @@ __global__ void lam_init_kernel(AdjParams p, float *lam) {
     for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
         const int vv = i / kt, j = i % kt;
         if (v0 + vv < p.n) {
-            lam[(v0 + vv) * kt + j] = p.beta * tile[vv][j];
+            lam[lam_row(p, v0 + vv) * kt + j] = p.beta * tile[vv][j];
             if (gT) gT[(v0 + vv) * kt + j] = tile[vv][j];
         }
     }
@@ -438,12 +446,13 @@ __global__ void lam_init_kernel(AdjParams p, float *lam) {
 
 // grad_q[col0 + j][v] = c * lambda(0)[v][j], transposed through LDS (one
 // block per 64 nodes).
-__global__ void gradq_kernel(const float *lam, int64_t n, int kt, int ncols, float c, int64_t col0, float *gq) {
+__global__ void gradq_kernel(const float *lam, const int32_t *lrow, int64_t n, int kt, int ncols, float c,
+                             int64_t col0, float *gq) {
     __shared__ float tile[64][65];
     const int64_t v0 = (int64_t)blockIdx.x * 64;
     for (int i = threadIdx.x; i < 64 * kt; i += blockDim.x) {
         const int vv = i / kt, j = i % kt;
-        tile[vv][j] = v0 + vv < n ? lam[(v0 + vv) * kt + j] : 0.0f;
+        tile[vv][j] = v0 + vv < n ? lam[(lrow ? (int64_t)lrow[v0 + vv] : v0 + vv) * kt + j] : 0.0f;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 64 * ncols; i += blockDim.x) {
@@ -614,6 +623,13 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
     if (hub) TPA_TRY(ensure_group_order(g, sf1, st));
+    // layout 2 on large graphs: lambda in rank order by in-degree (built
+    // before the adjoint's group-ordered ids, which are taken from a_colr then)
+    const bool lam_rank = g->gather_layout == 2 && g->n >= kLamRankMinN;
+    if (lam_rank) TPA_TRY(ensure_lam_layout(g, st));
+    const bool lam_hub = lam_rank && g->a_colr;
+    const int32_t *a_col = lam_hub ? g->a_colr : g->a.col;
+    const int32_t *lrow = lam_hub ? g->lrank : nullptr;
     TPA_TRY(ensure_group_order(g, sa1, st, true));
 
     if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
@@ -627,7 +643,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         AdjParams ap;
         ap.rowptr = g->a.rowptr;
-        ap.col = g->a.col;
+        ap.col = a_col;
+        ap.lrow = lrow;
         ap.w = g->weighted ? g->a.w : nullptr;
         ap.inv = g->inv_deg;
         ap.longs = sa1->longs;
@@ -700,7 +717,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         // backward over segments
         AdjParams ap;
         ap.rowptr = g->a.rowptr;
-        ap.col = g->a.col;
+        ap.col = a_col;
+        ap.lrow = lrow;
         ap.w = g->weighted ? g->a.w : nullptr;
         ap.inv = g->inv_deg;
         ap.longs = sa1->longs;
@@ -771,7 +789,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     fp.seed_stride = packed ? (int)k : 0;
     AdjParams ap;
     ap.rowptr = g->a.rowptr;
-    ap.col = g->a.col;
+    ap.col = a_col;
+    ap.lrow = lrow;
     ap.w = g->weighted ? g->a.w : nullptr;
     ap.inv = g->inv_deg;
     ap.longs = sak->longs;
@@ -818,7 +837,8 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             TPA_TRY(adj_step(*sak, ap, st));
             std::swap(lc, ln);
         }
-        if (grad_q) gradq_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(lc, n, kt, ncols, (float)c, base, grad_q);
+        if (grad_q)
+            gradq_kernel<<<(unsigned)((n + 63) / 64), 256, 0, st>>>(lc, lrow, n, kt, ncols, (float)c, base, grad_q);
     }
     if (grad_logits) {
         const unsigned sgrid = (unsigned)std::min<int64_t>((n * 64 + 255) / 256, 1 << 20);

@@ -67,6 +67,9 @@ struct StepParams {
     // bits_on is null or *bits_on != 0
     const uint32_t *bits = nullptr;
     const int32_t *bits_on = nullptr;
+    // set: the launch does nothing when *skip_on != 0 (the pulled step 2 and
+    // the pushed step 1 of a seed tile whose step 2 the device pushed)
+    const int32_t *skip_on = nullptr;
 };
 
 // Device state of the pushed first two family steps of a single seed
@@ -86,6 +89,52 @@ struct PushPlan {
 // Bytes of the push state (kept at the front of the query workspace).
 size_t push_plan_bytes(int64_t n, int64_t max_outdeg);
 PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax);
+
+// Device state of the pushed first two family steps of a seed tile (kt >= 2,
+// one-hot seeds, unpacked graph).  Column j's x(1) lives on F_j = out(s_j)
+// + {s_j}; one block plans the push on the device: an entry per node of
+// every F_j (its y1 in gathered form, its A~ edges) and the entries' edges
+// cut into pieces of kTilePiece.  When the plan fits (at most kTilePlanMax
+// entries, at most qmax pieces) and the tile's frontier edges W = sum over
+// j of sum over F_j of outdeg number at most wmax, the flag is set and the
+// pieces are pushed into acc.  acc holds y2 in gathered form, by gather row,
+// [n][kt] in 2^62 fixed point, all zero between queries; bits receives the
+// rows the push reached.
+constexpr int kTilePlanMax = 16384;
+constexpr int kTilePiece = 256;
+struct TilePush {
+    unsigned long long *acc = nullptr;  // [n][kt] by gather row
+    uint32_t *bits = nullptr;           // [ceil(n/32)]
+    int64_t nwords = 0;
+    int64_t *ent_e0 = nullptr;          // [kTilePlanMax] first A~ edge of the entry's node
+    int64_t *ent_e1 = nullptr;          // end of its edges
+    float *ent_y = nullptr;             // its y1 value, gathered form
+    int32_t *ent_col = nullptr;         // its column j
+    int64_t *pieces = nullptr;          // [qmax] entry << 32 | offset of the piece's first edge
+    int64_t *ctrl = nullptr;            // {W, pieces pushed (0 when pulled), entries}
+    int32_t *flag = nullptr;            // 1: step 2 of the tile is pushed
+    int64_t qmax = 0;
+    int64_t wmax = 0;
+};
+
+// Bytes of the tile push state for kt columns, and its layout from base
+// (256-byte aligned).
+size_t tile_push_bytes(int64_t n, int64_t m, int kt);
+TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax);
+
+// Steps 1 and 2 of a seed tile, pushed when the device's plan allows:
+// clears bits, plans (flag, ctrl, the restart terms c e_s of y2 in acc) and
+// pushes the plan's pieces (nothing when the flag is clear).  The caller
+// launches the pushed first step (launch_push_first) between the plan and
+// the push with p.skip_on = tp.flag, so it runs only when step 2 is pulled.
+tpa_status launch_tile_plan(const StepParams &p, const tpa_graph *g, const TilePush &tp, hipStream_t st);
+tpa_status launch_tile_push(const StepParams &p, const tpa_graph *g, const TilePush &tp, hipStream_t st);
+
+// Step 2 of a pushed tile: p.zout = y2 as the next gathered vector, every
+// row written (the rows the push reached from acc, which is cleared, the
+// others zero).  Nothing when the flag is clear; the pulled step 2 is then
+// launched with p.skip_on = tp.flag.
+tpa_status launch_tile_convert(const StepParams &p, const TilePush &tp, hipStream_t st);
 
 tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams &p, hipStream_t st);
 

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void finish_kernel(const LongRow *__restr
                                                           StepParams p) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_long) return;
+    if (wid >= n_long || (p.skip_on && *p.skip_on)) return;
     finish_row<MODE>(p, longs[wid], lane);
 }
 
@@ -648,7 +648,7 @@ __global__ __launch_bounds__(kThreads, 7) void step_kernel_64(const Item *__rest
     __shared__ float stage[kWaves][kStageRows * kStageStride];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
-    if (wid >= n_items) return;
+    if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
     item_64<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane, stage[wv]);
 }
 
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restric
                                                            StepParams p) {
     const int lane = threadIdx.x & 63;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (wid >= n_items) return;
+    if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
     item_kt<KT, MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane);
 }
 
@@ -854,6 +854,7 @@ __device__ __forceinline__ void claim_row(const StepParams &p, uint32_t *bits, i
 // zout is ever read (the pull after it skips them).  One wave per slot.
 __global__ void push_first_rows_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, int64_t nslots,
                                        uint32_t *bits) {
+    if (p.skip_on && *p.skip_on) return;
     const int lane = threadIdx.x & 63;
     const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (w >= nslots) return;
@@ -871,6 +872,7 @@ __global__ void push_first_rows_kernel(StepParams p, const int64_t *a_rowptr, co
 // with the frontier skip, the rows written here were zeroed).
 __global__ void push_first_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col, const float *a_w,
                                   int64_t nslots) {
+    if (p.skip_on && *p.skip_on) return;
     const int lane = threadIdx.x & 63;
     const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     if (w >= nslots) return;
@@ -1026,6 +1028,183 @@ __global__ __launch_bounds__(256) void push_steps12_kernel(StepParams p, const i
         const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
         atomicAdd(&pp.acc[zrow(p, v)], to_fixed62(term));
     }
+}
+
+// ------------------------------------------------------------ pushed tiles
+// Plan of a seed tile's pushed second step (one block of 1024 threads).
+// Column j holds d_j + 1 entries when its seed row has no self-loop (the
+// out-neighbours in edge order, then the seed itself), d_j otherwise; an
+// invalid seed or a column past ncols holds none.  Entry i gets its node's
+// y1 in gathered form, as the first step's push writes it, and its A~
+// edges; its edges are cut into pieces of kTilePiece, whose indices come
+// from a block scan.  Block-uniform loops throughout (the scans need every
+// wave at each barrier).
+__global__ __launch_bounds__(1024) void tile_plan_kernel(StepParams p, const int64_t *a_rowptr, const int32_t *a_col,
+                                                         const float *a_w, TilePush tp) {
+    __shared__ long long cstart[65];  // first entry of column j
+    __shared__ long long swq[16], sww[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (wv == 0) {
+        long long cnt = 0;
+        if (lane < p.ncols) {
+            const int32_t s = p.seeds[lane];
+            if (s >= 0 && (int64_t)s < p.n) {
+                const int64_t e0 = a_rowptr[s], e1 = a_rowptr[s + 1];
+                int64_t lo = e0, hi = e1;  // first edge with a_col >= s (rows are sorted)
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a_col[mid] < s) lo = mid + 1;
+                    else hi = mid;
+                }
+                cnt = (e1 - e0) + ((lo < e1 && a_col[lo] == s) ? 0 : 1);
+            }
+        }
+        const long long incl = wave_scan_incl(cnt, lane);
+        cstart[lane + 1] = incl;
+        if (lane == 0) cstart[0] = 0;
+    }
+    __syncthreads();
+    const long long P = cstart[64];
+    const float cw = p.c * p.omc;
+    long long runq = 0, runw = 0;
+    const bool fits = P > 0 && P <= kTilePlanMax;
+    if (fits) {
+        for (long long base = 0; base < P; base += 1024) {  // block-uniform trip count
+            const long long i = base + tid;
+            long long deg = 0, npc = 0;
+            if (i < P) {
+                int lo = 0, hi = 64;  // column: the last j with cstart[j] <= i
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (cstart[mid] <= i) lo = mid;
+                    else hi = mid;
+                }
+                const int j = lo;
+                const int32_t s = p.seeds[j];
+                const int64_t e0 = a_rowptr[s], d = a_rowptr[s + 1] - e0;
+                const long long l = i - cstart[j];
+                int32_t f = s;
+                float y = p.c;
+                if (l < d) {
+                    f = a_col[e0 + l];
+                    y = fmaf(cw, a_w ? a_w[e0 + l] : p.inv[s], f == s ? p.c : 0.0f);
+                }
+                const int64_t f0 = a_rowptr[f], f1 = a_rowptr[f + 1];
+                tp.ent_e0[i] = f0;
+                tp.ent_e1[i] = f1;
+                tp.ent_y[i] = a_w ? y : y * p.inv[f];
+                tp.ent_col[i] = j;
+                deg = f1 - f0;
+                npc = (deg + kTilePiece - 1) / kTilePiece;
+            }
+            const long long iq = wave_scan_incl(npc, lane);
+            const long long iw = wave_scan_incl(deg, lane);
+            if (lane == 63) {
+                swq[wv] = iq;
+                sww[wv] = iw;
+            }
+            __syncthreads();
+            long long q0 = runq + iq - npc;
+            for (int w = 0; w < wv; ++w) q0 += swq[w];
+            for (long long k = 0; k < npc; ++k)
+                if (q0 + k < tp.qmax) tp.pieces[q0 + k] = (long long)(i << 32) | (k * kTilePiece);
+            for (int w = 0; w < 16; ++w) {
+                runq += swq[w];
+                runw += sww[w];
+            }
+            __syncthreads();  // swq, sww are rewritten next round
+        }
+    }
+    const bool push = fits && runw <= tp.wmax && runq <= tp.qmax;
+    if (tid == 0) {
+        tp.ctrl[0] = runw;
+        tp.ctrl[1] = push ? runq : 0;
+        tp.ctrl[2] = P;
+        *tp.flag = push ? 1 : 0;
+    }
+    // the restart terms c e_s of y2, and their rows (the push adds to them
+    // in a later launch)
+    if (push && tid < p.ncols) {
+        const int32_t s = p.seeds[tid];
+        if (s >= 0 && (int64_t)s < p.n) {
+            const int64_t zr = zrow(p, s);
+            atomicAdd(&tp.acc[zr * p.kt + tid], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
+            atomicOr(&tp.bits[zr >> 5], 1u << (zr & 31));
+        }
+    }
+}
+
+// The pushed second step of a seed tile: waves stride over the plan's
+// pieces; lanes take a piece's edges in order and add each edge's term of
+// column j to acc in 2^62 fixed point (no atomic result awaited), marking
+// its row in bits.  Every term lies in [0, 1] and column j's terms add up to
+// at most the mass of its y2, below 1, so no sum overflows.
+__global__ __launch_bounds__(256) void tile_push_kernel(StepParams p, const int32_t *a_col, const float *a_w,
+                                                        TilePush tp) {
+    if (!*tp.flag) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t nq = tp.ctrl[1];
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < nq; q += nwaves) {
+        const long long pc = tp.pieces[q];
+        const int i = (int)(pc >> 32);
+        const int64_t e0 = tp.ent_e0[i] + (pc & 0xffffffffll);
+        const int64_t e1 = min(e0 + (int64_t)kTilePiece, tp.ent_e1[i]);
+        const int j = tp.ent_col[i];
+        const float zu = tp.ent_y[i];
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int32_t v = a_col[e];
+            const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
+            const int64_t zr = zrow(p, v);
+            atomicAdd(&tp.acc[zr * p.kt + j], to_fixed62(term));
+            const uint32_t bit = 1u << (zr & 31);
+            if (!(tp.bits[zr >> 5] & bit)) atomicOr(&tp.bits[zr >> 5], bit);
+        }
+    }
+}
+
+// y2 of a pushed tile as the next gathered vector: rows the push reached
+// are converted from acc (which is cleared), the others are zero.  Four
+// entries per thread: one row's (kt >= 4, 16-byte accesses), else one at a
+// time.
+__global__ __launch_bounds__(256) void tile_convert_kernel(StepParams p, TilePush tp) {
+    if (!*tp.flag) return;
+    const int kt = p.kt;
+    const int64_t total = p.n * (int64_t)kt;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < total; i0 += stride) {
+        if (kt >= 4) {
+            const int64_t zr = i0 / kt;
+            const bool live = (tp.bits[zr >> 5] >> (zr & 31)) & 1u;
+            float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (live) {
+                ulonglong2 *a = reinterpret_cast<ulonglong2 *>(tp.acc + i0);
+                const ulonglong2 lo = a[0], hi = a[1];
+                z = make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
+                                (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
+                if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
+                if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
+            }
+            *reinterpret_cast<float4 *>(p.zout + i0) = z;
+        } else {
+            for (int k = 0; k < 4 && i0 + k < total; ++k) {
+                const int64_t i = i0 + k, zr = i / kt;
+                float z = 0.0f;
+                if ((tp.bits[zr >> 5] >> (zr & 31)) & 1u) {
+                    const unsigned long long a = tp.acc[i];
+                    z = (float)((double)a * 0x1p-62);
+                    if (a) tp.acc[i] = 0ull;
+                }
+                p.zout[i] = z;
+            }
+        }
+    }
+}
+
+__global__ void fill_zero_gated_kernel(float *z, int64_t n, const int32_t *skip_on) {
+    if (skip_on && *skip_on) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = 0.0f;
 }
 
 __global__ void combine_only_kernel(StepParams p) {
@@ -1215,10 +1394,11 @@ tpa_status launch_push_first(const StepParams &p, const tpa_graph *g, int64_t nb
     const int64_t nslots = nblocks * p.ncols;
     const unsigned slot_grid = (unsigned)((nslots * 64 + 255) / 256);
     if (bits) {
-        fill_zero_kernel<<<grid_1d(nwords), 256, 0, st>>>(reinterpret_cast<float *>(bits), nwords);
+        fill_zero_gated_kernel<<<grid_1d(nwords), 256, 0, st>>>(reinterpret_cast<float *>(bits), nwords, p.skip_on);
         push_first_rows_kernel<<<slot_grid, 256, 0, st>>>(p, g->a.rowptr, g->a.col, nslots, bits);
     } else {
-        fill_zero_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt);
+        fill_zero_gated_kernel<<<grid_1d(p.n * (int64_t)p.kt), 256, 0, st>>>(p.zout, p.n * (int64_t)p.kt,
+                                                                             p.skip_on);
     }
     push_first_kernel<<<slot_grid, 256, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, nslots);
     TPA_TRY_HIP(hipGetLastError());
@@ -1247,6 +1427,73 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
     return pp;
+}
+
+namespace {
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+// pieces: one or more per plan entry, up to 4m frontier edges in all
+int64_t tile_qmax(int64_t m) { return 4 * (m / kTilePiece + 1) + kTilePlanMax; }
+}  // namespace
+
+size_t tile_push_bytes(int64_t n, int64_t m, int kt) {
+    const size_t P = kTilePlanMax;
+    return align256((size_t)n * kt * 8) + bits_bytes(n) + 256 + align256(P * 8) * 2 + align256(P * 4) * 2 +
+           align256((size_t)tile_qmax(m) * 8);
+}
+
+TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax) {
+    char *b = static_cast<char *>(base);
+    const size_t P = kTilePlanMax;
+    TilePush tp;
+    tp.acc = reinterpret_cast<unsigned long long *>(b);
+    b += align256((size_t)n * kt * 8);
+    tp.bits = reinterpret_cast<uint32_t *>(b);
+    tp.nwords = (n + 31) / 32;
+    b += bits_bytes(n);
+    tp.ctrl = reinterpret_cast<int64_t *>(b);
+    tp.flag = reinterpret_cast<int32_t *>(b + 64);
+    b += 256;
+    tp.ent_e0 = reinterpret_cast<int64_t *>(b);
+    b += align256(P * 8);
+    tp.ent_e1 = reinterpret_cast<int64_t *>(b);
+    b += align256(P * 8);
+    tp.ent_y = reinterpret_cast<float *>(b);
+    b += align256(P * 4);
+    tp.ent_col = reinterpret_cast<int32_t *>(b);
+    b += align256(P * 4);
+    tp.pieces = reinterpret_cast<int64_t *>(b);
+    tp.qmax = tile_qmax(m);
+    tp.wmax = wmax;
+    return tp;
+}
+
+tpa_status launch_tile_plan(const StepParams &p, const tpa_graph *g, const TilePush &tp, hipStream_t st) {
+    if (p.kt < 2 || p.node_block || !p.seeds || p.ncols > 64) return fail(TPA_ERR_INVALID_ARG, "tile push needs seed lists");
+    const int slot = profile_begin(122, st);
+    fill_zero_kernel<<<grid_1d(tp.nwords), 256, 0, st>>>(reinterpret_cast<float *>(tp.bits), tp.nwords);
+    tile_plan_kernel<<<1, 1024, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, tp);
+    profile_end(slot, st);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_tile_push(const StepParams &p, const tpa_graph *g, const TilePush &tp, hipStream_t st) {
+    // waves stride over the pieces: about 4 pieces per wave at the bound
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, (tp.wmax / kTilePiece + kTilePlanMax) / 16), 2048);
+    const int slot = profile_begin(123, st);
+    tile_push_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, g->a.col, g->weighted ? g->a.w : nullptr, tp);
+    profile_end(slot, st);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_tile_convert(const StepParams &p, const TilePush &tp, hipStream_t st) {
+    const int64_t total = p.n * (int64_t)p.kt;
+    const int slot = profile_begin(125, st);
+    tile_convert_kernel<<<grid_1d((total + 3) / 4), 256, 0, st>>>(p, tp);
+    profile_end(slot, st);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
 }
 
 tpa_status launch_push_steps12(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {

@@ -589,10 +589,10 @@ tpa_status ensure_wz(tpa_graph *g, hipStream_t st) {
 tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st, bool over_a) {
     Schedule *s = const_cast<Schedule *>(cs);  // an entry of g's schedule cache
     // forward: hub-first ids of A~^T (gather rows); adjoint: A~'s destination ids
-    const int32_t *src = over_a ? g->a.col : g->t_colz;
+    const int32_t *src = over_a ? (g->a_colr ? g->a_colr : g->a.col) : g->t_colz;
     if (g->gather_layout != 2 || !src || s->n_items == 0) return TPA_OK;
-    if (s->colg) {  // built before, set aside by a layout change: src has not changed
-        s->colg_src = src;
+    if (s->colg) {  // built before, set aside by a layout change
+        if (s->colg_from == src) s->colg_src = src;
         return TPA_OK;
     }
     if (g->n >= kGroupSlotMaxN || s->ew > kGroupEdges) return TPA_OK;
@@ -616,6 +616,51 @@ tpa_status ensure_group_order(tpa_graph *g, const Schedule *cs, hipStream_t st, 
     }
     s->colg = colg;
     s->colg_src = src;
+    s->colg_from = src;
+    return TPA_OK;
+}
+
+// Rank of every node by descending in-degree (the rows of A~^T), and A~'s
+// destination ids mapped through it.
+tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t st) {
+    if (g->lrank) return TPA_OK;
+    const int64_t n = g->n, m = g->m;
+    if (m >= (int64_t(1) << 32)) return TPA_OK;  // in-degree keys are 32 bits
+    uint32_t *k0 = nullptr, *k1 = nullptr;
+    int32_t *v0 = nullptr, *v1 = nullptr, *rank = nullptr, *colr = nullptr;
+    void *tmp = nullptr;
+    auto cleanup = [&]() { dfree(k0); dfree(k1); dfree(v0); dfree(v1); dfree(tmp); };
+    tpa_status rc = TPA_OK;
+    if ((rc = dalloc(&k0, n, st)) != TPA_OK || (rc = dalloc(&k1, n, st)) != TPA_OK ||
+        (rc = dalloc(&v0, n, st)) != TPA_OK || (rc = dalloc(&v1, n, st)) != TPA_OK) {
+        cleanup();
+        return rc;
+    }
+    hub_keys_kernel<<<grid_for(n), kBlock, 0, st>>>(g->t.rowptr, n, m, k0, v0);
+    rocprim::double_buffer<uint32_t> kb(k0, k1);
+    rocprim::double_buffer<int32_t> vb(v0, v1);
+    size_t bytes = 0;
+    const unsigned end_bit = (unsigned)std::min(32, key_bits(m + 1));
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, kb, vb, (size_t)n, 0u, end_bit, st);
+    if (e == hipSuccess) rc = dmalloc(&tmp, std::max<size_t>(bytes, 16), st);
+    if (e == hipSuccess && rc == TPA_OK) e = rocprim::radix_sort_pairs(tmp, bytes, kb, vb, (size_t)n, 0u, end_bit, st);
+    if (e != hipSuccess) rc = fail(TPA_ERR_HIP, std::string("radix_sort_pairs: ") + hipGetErrorString(e));
+    if (rc == TPA_OK) rc = dalloc(&rank, n, st);
+    if (rc == TPA_OK) rc = dalloc(&colr, std::max<int64_t>(m, 1), st);
+    if (rc == TPA_OK) {
+        invert_perm_kernel<<<grid_for(n), kBlock, 0, st>>>(vb.current(), n, rank);
+        map_cols_kernel<<<grid_for(m), kBlock, 0, st>>>(g->a.col, m, rank, colr);
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = fail(TPA_ERR_HIP, std::string("adjoint layout: ") + hipGetErrorString(e));
+    }
+    cleanup();
+    if (rc != TPA_OK) {
+        dfree(rank);
+        dfree(colr);
+        return rc;
+    }
+    g->lrank = rank;
+    g->a_colr = colr;
     return TPA_OK;
 }
 
@@ -634,6 +679,7 @@ void Schedule::release() {
     longs = nullptr;
     colg = nullptr;
     colg_src = nullptr;
+    colg_from = nullptr;
 }
 
 // Rows of A~^T are cut into wave items, heaviest first so they start early:
@@ -736,11 +782,15 @@ void graph_release(tpa_graph *g) {
     dfree(g->t.rowptr); dfree(g->t.col); dfree(g->t.w);
     dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
     dfree(g->zperm); dfree(g->t_colz); dfree(g->t_locz); dfree(g->t_wz);
+    dfree(g->lrank); dfree(g->a_colr);
+    g->lrank = nullptr;
+    g->a_colr = nullptr;
     g->zperm = nullptr;
     g->t_colz = nullptr;
     g->t_locz = nullptr;
     g->t_wz = nullptr;
     dfree(g->str); dfree(g->ws); dfree(g->dev_err); dfree(g->xiter);
+    tile_buf_free(&g->tbuf);
     for (auto &b : g->adj_cache) dfree(b.first);
     g->adj_cache.clear();
     g->xiter = nullptr;
@@ -964,9 +1014,12 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     add(g->t_colz, sizeof(int32_t) * m);
     add(g->t_locz, sizeof(int32_t) * m);
     add(g->t_wz, sizeof(float) * m);
+    add(g->lrank, sizeof(int32_t) * n);
+    add(g->a_colr, sizeof(int32_t) * m);
     add(g->str, sizeof(float) * n);
     add(g->dev_err, sizeof(int32_t));
     add(g->ws, g->ws_bytes);
+    add(g->tbuf.base, g->tbuf.bytes);
     add(g->xiter, sizeof(float) * g->xiter_cap);
     for (const auto &c : g->adj_cache) add(c.first, c.second);
     for (const auto *cache : {&g->sched_t, &g->sched_a}) {

@@ -24,6 +24,7 @@ struct tpa_query_graph {
     hipGraphExec_t exec = nullptr;
     float *ws = nullptr;
     size_t ws_bytes = 0;
+    tpa::TileBuf tbuf;  // its own pushed-tile buffer (seed tiles)
 };
 
 namespace tpa {
@@ -70,15 +71,17 @@ extern "C" tpa_status tpa_query_graph_create(tpa_graph_t g, const int32_t *seeds
     qg->ws_bytes = bytes;
     rc = clear_push_state(g, qg->ws, st);
     if (rc == TPA_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(TPA_ERR_HIP, "hipStreamSynchronize failed");
-    if (rc != TPA_OK) { dfree(qg->ws); delete qg; return rc; }
+    const size_t tbytes = seeds ? tile_buf_bytes(g, choose_kt(g, k), packed != 0, S) : 0;
+    if (rc == TPA_OK && tbytes) rc = tile_buf_alloc(&qg->tbuf, tbytes, choose_kt(g, k), st);
+    if (rc != TPA_OK) { tile_buf_free(&qg->tbuf); dfree(qg->ws); delete qg; return rc; }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
-        dfree(qg->ws); delete qg;
+        tile_buf_free(&qg->tbuf); dfree(qg->ws); delete qg;
         return fail(TPA_ERR_HIP, "hipStreamCreate failed");
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        rc = run_query(g, seeds, q, k, packed != 0, c, S, T, out, cs, qg->ws, qg->ws_bytes);
+        rc = run_query(g, seeds, q, k, packed != 0, c, S, T, out, cs, qg->ws, qg->ws_bytes, false, &qg->tbuf);
         hipError_t e2 = hipStreamEndCapture(cs, &qg->graph);
         if (rc == TPA_OK && e2 != hipSuccess) rc = fail(TPA_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
     } else {
@@ -90,6 +93,7 @@ extern "C" tpa_status tpa_query_graph_create(tpa_graph_t g, const int32_t *seeds
     if (rc != TPA_OK) {
         if (qg->exec) (void)hipGraphExecDestroy(qg->exec);
         if (qg->graph) (void)hipGraphDestroy(qg->graph);
+        tile_buf_free(&qg->tbuf);
         dfree(qg->ws);
         delete qg;
         return rc;
@@ -109,6 +113,7 @@ extern "C" tpa_status tpa_query_graph_destroy(tpa_query_graph_t qg) {
     (void)hipDeviceSynchronize();
     if (qg->exec) (void)hipGraphExecDestroy(qg->exec);
     if (qg->graph) (void)hipGraphDestroy(qg->graph);
+    tile_buf_free(&qg->tbuf);
     dfree(qg->ws);
     delete qg;
     return TPA_OK;

@@ -170,8 +170,66 @@ size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st
     return query_ws_bytes(g, s, kt, dense);
 }
 
+// Frontier edges up to which a seed tile pushes its second step, summed
+// over the tile's columns: by default a quarter of the edges, twice the
+// single seed's share (a pulled tile step gathers kt-wide rows per edge, so
+// it costs more than a single vector's).
+int64_t tile_wmax(const tpa_graph *g) {
+    if (g->tile_push_limit >= 0) return g->tile_push_limit;
+    return std::max<int64_t>(2048, g->m / 4);
+}
+
+bool tile_push_applies(const tpa_graph *g, int kt, bool packed, int S) {
+    return kt >= 2 && !packed && S >= 4 && tile_wmax(g) > 0;
+}
+
+size_t tile_buf_bytes(const tpa_graph *g, int kt, bool packed, int S) {
+    if (!tile_push_applies(g, kt, packed, S)) return 0;
+    const size_t bytes = tile_push_bytes(g->n, g->m, kt);
+    // the y2 accumulator is 8 bytes per entry: at most 32 GiB, and at most
+    // a quarter of the free device memory
+    size_t free_b = 0, total_b = 0;
+    if (bytes > (size_t(32) << 30)) return 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || bytes > free_b / 4) return 0;
+    return bytes;
+}
+
+tpa_status tile_buf_alloc(TileBuf *tb, size_t bytes, int kt, hipStream_t st) {
+    TPA_TRY(dmalloc(&tb->base, bytes, st));
+    tb->bytes = bytes;
+    tb->kt_cap = kt;
+    TPA_TRY_HIP(hipMemsetAsync(tb->base, 0, bytes, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));  // ordered before queries on any stream
+    return TPA_OK;
+}
+
+void tile_buf_free(TileBuf *tb) {
+    dfree(tb->base);
+    *tb = TileBuf();
+}
+
+namespace {
+
+// The handle's pushed-tile buffer for kt columns, when it may push (left
+// absent under stream capture, where nothing is allocated).
+tpa_status ensure_tile_buf(tpa_graph *g, int kt, bool packed, int S, hipStream_t st) {
+    if (g->tbuf.base && g->tbuf.kt_cap >= kt) return TPA_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return TPA_OK;
+    const size_t bytes = tile_buf_bytes(g, kt, packed, S);
+    if (bytes == 0) return TPA_OK;
+    if (g->tbuf.base) {
+        TPA_TRY_HIP(hipStreamSynchronize(st));
+        tile_buf_free(&g->tbuf);
+    }
+    return tile_buf_alloc(&g->tbuf, bytes, kt, st);
+}
+
+}  // namespace
+
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc) {
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc,
+                     TileBuf *tb) {
     TPA_TRY(check_query_args(g, c, S, T));
     if (k < 0) return fail(TPA_ERR_INVALID_ARG, "k must be >= 0");
     if (k == 0) return TPA_OK;
@@ -205,6 +263,16 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     const bool push2 = kt == 1 && !packed && !q && S >= 4 && pp.wmax > 0;
     // pulls after a push skip the rows it left zero (seed tiles of 1 and 64)
     const bool frontier = pp.wmax > 0 && (kt == 1 || kt == 64);
+    // a seed tile whose step 2 is not the last: the device pushes step 2 from
+    // the columns' seeds when the tile's frontier is small, and pulls it
+    // otherwise (steps 1 and 2 are then as without the push)
+    bool tpush = tile_push_applies(g, kt, packed, S) && !q && (!no_alloc || tb);
+    if (tpush && !tb) {
+        TPA_TRY(ensure_tile_buf(g, kt, packed, S, st));
+        tb = &g->tbuf;
+    }
+    tpush = tpush && tb && tb->base && tb->kt_cap >= kt;
+    const TilePush tp = tpush ? tile_push_at(tb->base, g->n, g->m, tb->kt_cap, tile_wmax(g)) : TilePush();
 
     StepParams p;
     p.rowptr = g->t.rowptr;
@@ -251,9 +319,30 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             p.last = step == S - 1;
             if (step == 1 && !q && !p.last) {
                 // one-hot restarts: x(1) lives on the seeds' out-edges; push it
-                if (push2) TPA_TRY(launch_push_steps12(p, g, pp, st));  // steps 1 and 2
-                else TPA_TRY(launch_push_first(p, g, packed ? g->nblocks : 1, frontier ? pp.bits : nullptr,
-                                               pp.nwords, st));
+                if (push2) {
+                    TPA_TRY(launch_push_steps12(p, g, pp, st));  // steps 1 and 2
+                } else {
+                    StepParams p1 = p;
+                    if (tpush) {
+                        TPA_TRY(launch_tile_plan(p, g, tp, st));
+                        p1.skip_on = tp.flag;  // x(1) is written only for a pulled step 2
+                    }
+                    TPA_TRY(launch_push_first(p1, g, packed ? g->nblocks : 1, frontier ? pp.bits : nullptr,
+                                              pp.nwords, st));
+                    if (tpush) TPA_TRY(launch_tile_push(p, g, tp, st));
+                }
+                continue;
+            }
+            if (step == 2 && tpush) {
+                // converted from the push, or pulled (each launch runs only in its case)
+                TPA_TRY(launch_tile_convert(p, tp, st));
+                StepParams p2 = p;
+                p2.skip_on = tp.flag;
+                p2.bits = frontier ? pp.bits : nullptr;
+                p2.bits_on = nullptr;
+                p2.col = col_gather;
+                p2.w = w_gather;
+                TPA_TRY(launch_step(*s, kFamily, false, p2, st));
                 continue;
             }
             if (step == 2 && push2) {
@@ -441,6 +530,7 @@ extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     TPA_TRY(get_schedule(g, choose_shape(g, kt), nullptr, &s));
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, nullptr));  // not buildable under capture
+    TPA_TRY(ensure_tile_buf(g, kt, false, 4, nullptr));  // for seed tiles whose step 2 may be pushed
     return ensure_ws(g, query_ws_bytes(g, s, kt, true), nullptr);  // room for dense restarts too
 }
 
@@ -511,6 +601,19 @@ extern "C" tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges) {
     return TPA_OK;
 }
 
+extern "C" tpa_status tpa_set_tile_push_limit(tpa_graph_t g, int64_t max_edges) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (max_edges < -1) return fail(TPA_ERR_INVALID_ARG, "max_edges must be >= -1");
+    g->tile_push_limit = max_edges;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_tile_push_limit(tpa_graph_t g, int64_t *max_edges) {
+    if (!g || !max_edges) return fail(TPA_ERR_INVALID_ARG, "bad argument");
+    *max_edges = g->tile_push_limit;
+    return TPA_OK;
+}
+
 extern "C" tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t st) {
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     int32_t v = 0;
@@ -576,14 +679,26 @@ extern "C" tpa_status tpa_query_noalloc(tpa_graph_t g, const int32_t *seeds, int
     if (!s)
         return fail(TPA_ERR_INVALID_ARG, "no work schedule for this seed tile yet (building one allocates): "
                                          "call tpa_reserve(g, k) or run one tpa_query of k seeds first");
-    const size_t need = query_ws_bytes(g, s, kt, false);
+    // the query workspace, then (seed tiles whose step 2 may be pushed) the
+    // pushed-tile buffer
+    const size_t wsb = (query_ws_bytes(g, s, kt, false) + 255) & ~(size_t)255;
+    const size_t tbytes = tile_push_applies(g, kt, false, S) ? tile_push_bytes(g->n, g->m, kt) : 0;
+    const size_t need = wsb + tbytes;
     if (need > kScratchBytes)
         return fail(TPA_ERR_INVALID_ARG, "the query needs " + std::to_string(need) +
                                              " bytes of workspace; tpa_query_noalloc holds at most " +
                                              std::to_string(kScratchBytes));
     void *ws = nullptr;
     TPA_TRY(scratch_address(&ws));
-    // the push accumulator must be all zero when a query starts
+    // the push accumulators must be all zero when a query starts
     TPA_TRY(launch_fill_zero(static_cast<float *>(ws), (int64_t)(push_plan_bytes(g->n, g->max_outdeg) / 4), st));
-    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st, static_cast<float *>(ws), kScratchBytes, true);
+    TileBuf tb;
+    if (tbytes) {
+        tb.base = static_cast<char *>(ws) + wsb;
+        tb.bytes = tbytes;
+        tb.kt_cap = kt;
+        TPA_TRY(launch_fill_zero(static_cast<float *>(tb.base), (int64_t)(tbytes / 4), st));
+    }
+    return run_query(g, seeds, nullptr, k, false, c, S, T, out, st, static_cast<float *>(ws), wsb, true,
+                     tbytes ? &tb : nullptr);
 }

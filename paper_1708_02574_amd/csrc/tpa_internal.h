@@ -110,6 +110,7 @@ struct Schedule {
     // The step launchers use colg only while colg_src is set (layout 2).
     int32_t *colg = nullptr;
     const int32_t *colg_src = nullptr;
+    const int32_t *colg_from = nullptr;  // the ids colg was built from (reused only for those)
     void release();
 };
 
@@ -119,6 +120,23 @@ struct Csr {
     float *w = nullptr;         // m, only when weights are not 1/outdeg
 };
 
+}  // namespace tpa
+
+namespace tpa {
+// Smallest graph whose adjoint keeps lambda in in-degree rank order.  Below
+// it lambda (at most 32 MB) stays in the caches in node order and the row
+// lookup of every store costs more than it saves (adjoint of 64 seeds on
+// R-MAT graphs: +2 % at 2^20 and 2^22 nodes; -14 % at 2^24, -43 % per step
+// at 2^27).
+constexpr int64_t kLamRankMinN = int64_t(1) << 23;
+
+// Device buffer of a seed tile's pushed second step (laid out for up to
+// kt_cap columns by tile_push_at; zeroed when allocated).
+struct TileBuf {
+    void *base = nullptr;
+    size_t bytes = 0;
+    int kt_cap = 0;
+};
 }  // namespace tpa
 
 struct tpa_graph {
@@ -146,6 +164,14 @@ struct tpa_graph {
     bool t_wz_valid = false;
     int gather_layout = 2;                  // 2 = hub-first order, group items in gather
                                             // order; 1 = hub-first order; 0 = node order
+    // adjoint gather layout (layout 2, n >= kLamRankMinN): the adjoint's
+    // lambda vectors keep node v's entry at row lrank[v], the rank of v by
+    // descending in-degree (ties by id), so the entries a pull over A~
+    // gathers most share cache lines; a_colr holds lrank[a.col] in A~'s own
+    // edge order (the sums and the edge gradient keep their order).  Built
+    // at the first tpa_backward.
+    int32_t *lrank = nullptr;               // n
+    int32_t *a_colr = nullptr;              // m
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
     bool weighted = false;                  // weights from logits (a.w, t.w set)
@@ -176,12 +202,16 @@ struct tpa_graph {
     // query workspace
     float *ws = nullptr;
     size_t ws_bytes = 0;
+    // pushed-tile state of eager queries (the fixed-point y2 tile and the
+    // plan), laid out for kt_cap columns; all-zero accumulator between queries
+    tpa::TileBuf tbuf;
     int32_t *dev_err = nullptr;             // sticky device error flag
 
     // tuning
     int seed_tile = 0;                      // 0 = automatic
     int edges_per_item = 0;                 // 0 = automatic
     int64_t push_limit = -1;                // -1 = automatic, 0 = never push
+    int64_t tile_push_limit = -1;           // seed tiles: -1 = automatic, 0 = never push
 };
 
 namespace tpa {
@@ -193,8 +223,20 @@ SchedShape choose_shape(const tpa_graph *g, int kt);
 // Query driver; ws == nullptr uses (and grows) the handle's workspace.
 // no_alloc: allocate nothing (the work schedule must exist already and the
 // group-ordered ids are used only if built; ws must be given).
+// tb: the pushed-tile buffer to use (null: the handle's own, allocated on
+// demand outside capture; under no_alloc, none); seed tiles push step 2
+// only with a buffer of at least kt columns.
 tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t k, bool packed, double c,
-                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc = false);
+                     int S, int T, float *out, hipStream_t st, float *ws, size_t ws_bytes, bool no_alloc = false,
+                     TileBuf *tb = nullptr);
+// Whether a query of kt columns from seed lists may push its tile's step 2,
+// and the bytes of its buffer (0 when it may not: tile width 1, a packed
+// graph, S < 4, pushes off, or a buffer above the size limit).
+size_t tile_buf_bytes(const tpa_graph *g, int kt, bool packed, int S);
+bool tile_push_applies(const tpa_graph *g, int kt, bool packed, int S);
+// Allocate and zero a pushed-tile buffer of `bytes` for kt columns.
+tpa_status tile_buf_alloc(TileBuf *tb, size_t bytes, int kt, hipStream_t st);
+void tile_buf_free(TileBuf *tb);
 size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st);
 // Zero the push state at the front of a fresh query workspace.
 tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st);
@@ -219,6 +261,8 @@ tpa_status ensure_group_order(tpa_graph *g, const Schedule *s, hipStream_t strea
 void drop_group_order(tpa_graph *g);
 // Build t_wz from the current weights when the graph is weighted.
 tpa_status ensure_wz(tpa_graph *g, hipStream_t stream);
+// Build lrank and a_colr (synchronises `stream`); a no-op when present.
+tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

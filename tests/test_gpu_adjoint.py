@@ -276,3 +276,93 @@ def test_backward_with_kept_iterates_is_bitwise_equal(g10, tpa, torch, weighted)
     finally:
         gg.set_keep_iterates(False)
         gg.set_logits(None)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+@pytest.mark.parametrize("kt,epi", [(1, 0), (1, 64), (16, 0), (64, 0), (64, 64)])
+def test_backward_lambda_order_is_bitwise_equal(g10, tpa, torch, weighted, kt, epi):
+    """Gather layout 2 (on this small graph: the adjoint's group items read
+    their column ids in gather order, each row's sum in edge order) gives
+    gradients bit for bit those of layout 1, for seeds, dense restarts and
+    checkpoints, with short and long (chunked) rows; and they stay within the
+    bar of the oracle."""
+    og, gg = g10
+    theta = ti.draw_logits(og.m, 95) if weighted else None
+    og.set_logits(theta.astype(np.float64) if weighted else None)
+    gg.set_logits(torch.from_numpy(theta).cuda() if weighted else None)
+    og.preprocess(c, T, EPS)
+    k = 1 if kt == 1 else 5
+    seeds_np = ti.draw_seeds(og.export()["padded"] == 0, k, 96)
+    seeds = torch.from_numpy(seeds_np).cuda()
+    W = ti.draw_loss_weights((k, og.n), 97)
+    Wd = torch.from_numpy(W).cuda()
+    rng = np.random.default_rng(98)
+    Q = rng.random((2, og.n))
+    Q /= Q.sum(axis=1, keepdims=True)
+    Qd = torch.from_numpy(Q.astype(np.float32)).cuda()
+    W2 = torch.from_numpy(ti.draw_loss_weights((2, og.n), 99)).cuda()
+    gg.set_tuning(seed_tile=kt, edges_per_item=epi)
+    try:
+        out = {}
+        for layout in (1, 2):
+            gg.set_gather_layout(layout)
+            gg.preprocess(c, T)
+            out[layout] = (gg.backward(Wd, c, S, T, seeds=seeds),
+                           gg.backward(Wd, c, S, T, seeds=seeds, checkpoint_every=7),
+                           gg.backward(W2, c, S, T, q=Qd))
+        for a2, b2 in zip(out[1], out[2]):
+            for a, b in zip(a2, b2):
+                assert torch.equal(a, b)
+        dth, dq = out[2][0]
+        odth, _, odq = og.backward(onehot(og.n, seeds_np), W.astype(np.float64), c, S, T, og.K)
+        assert nl1(dth.cpu().numpy(), odth) <= TOL
+        assert nl1(dq.cpu().numpy(), odq) <= TOL
+    finally:
+        gg.set_gather_layout(2)
+        gg.set_tuning(0, 0)
+        gg.set_logits(None)
+        og.set_logits(None)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_backward_lambda_rank_order_large_graph(tpa, torch, weighted):
+    """From 2^23 nodes gather layout 2 keeps the adjoint's lambda vectors in
+    descending in-degree order (rows looked up per store, A~'s column ids
+    mapped): the gradients are bit for bit those of layout 1 (node order),
+    for a single seed and a tile of 4, and within the bar of the oracle.  The
+    edges join a dense core of 2048 nodes to the top node ids, so lambda
+    rows at both ends of the order are gathered."""
+    n = 1 << 23
+    rng = np.random.default_rng(48)
+    core = rng.integers(0, 2048, size=(2, 40000))
+    top = n - 1 - rng.integers(0, 2048, size=20000)
+    low = rng.integers(0, 2048, size=20000)
+    src = np.concatenate([core[0], top, low]).astype(np.int32)
+    dst = np.concatenate([core[1], low, top]).astype(np.int32)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    og = oracle.Graph(n, src, dst)
+    assert og.m == gg.m
+    theta = ti.draw_logits(og.m, 49) if weighted else None
+    og.set_logits(theta.astype(np.float64) if weighted else None)
+    gg.set_logits(torch.from_numpy(theta).cuda() if weighted else None)
+    seeds_np = np.array([3, 100, n - 1, n - 7], np.int32)
+    seeds = torch.from_numpy(seeds_np).cuda()
+    W = ti.draw_loss_weights((4, n), 50)
+    Wd = torch.from_numpy(W).cuda()
+    out = {}
+    try:
+        for layout in (1, 2):
+            gg.set_gather_layout(layout)
+            gg.preprocess(c, T)
+            out[layout] = (gg.backward(Wd, c, S, T, seeds=seeds), gg.backward(Wd[:1], c, S, T, seeds=seeds[:1]))
+    finally:
+        gg.set_gather_layout(2)
+    for a2, b2 in zip(out[1], out[2]):
+        for a, b in zip(a2, b2):
+            assert torch.equal(a, b)
+    og.preprocess(c, T, EPS)
+    odth, _, odq = og.backward(onehot(n, seeds_np), W.astype(np.float64), c, S, T, og.K)
+    dth, dq = out[2][0]
+    assert nl1(dth.cpu().numpy(), odth) <= TOL
+    assert nl1(dq.cpu().numpy(), odq) <= TOL
+    gg.close()

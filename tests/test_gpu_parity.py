@@ -383,22 +383,129 @@ def test_frontier_skip_is_bitwise_neutral(rmat13, torch, kt, Sq):
     """The pull after a pushed first step skips the rows the push left zero.
     The skipped terms are exact zeros, so the results equal the unskipped
     pull (push limit 0 turns the skip off) bit for bit, and match the
-    oracle."""
+    oracle (tiles pull their second step here)."""
     og, gg = rmat13
     sd = seeds_for(og, 70 if kt == 64 else 6, 404)
     seeds = torch.from_numpy(sd).cuda()
     res = []
     try:
         gg.set_tuning(seed_tile=kt)
+        gg.set_tile_push_limit(0)
         for limit in (-1, 0):
             gg.set_push_limit(limit)
             res.append(gg.query(seeds, c, Sq, T))
     finally:
         gg.set_push_limit(-1)
+        gg.set_tile_push_limit(-1)
         gg.set_tuning(0, 0)
     assert torch.equal(res[0], res[1])
     expect = np.stack([og.query(int(s), c, Sq, T) for s in sd])
     assert np.all(l1_rows(res[0].cpu().numpy(), expect) <= TOL)
+
+
+def tile_runs(gg, torch, seeds, kt, Sq, limits):
+    """Queries of one batch under several tile push limits."""
+    out = {}
+    try:
+        gg.set_tuning(seed_tile=kt)
+        for limit in limits:
+            gg.set_tile_push_limit(limit)
+            assert gg.get_tile_push_limit() == limit
+            out[limit] = gg.query(seeds, c, Sq, T)
+    finally:
+        gg.set_tile_push_limit(-1)
+        gg.set_tuning(0, 0)
+    return out
+
+
+@pytest.mark.parametrize("kt,Sq", [(2, 5), (16, 4), (16, 5), (64, 5), (64, 8)])
+def test_tile_second_step_push_and_pull(rmat13, torch, kt, Sq):
+    """Seed tiles with step 2 always pushed (a tile limit above every tile's
+    frontier), always pulled (0) and chosen per tile (the median tile
+    frontier): all within L1 of the oracle, push and pull within FP32
+    rounding of each other, the pushed batch bitwise reproducible, and each
+    tile of the per-tile choice equal bit for bit to the direction its
+    frontier picks.  70 seeds leave a ragged last tile; the largest
+    out-degree's seed and a dangling node's seed are among them."""
+    og, gg = rmat13
+    ex = og.export()
+    sd = np.concatenate([seeds_for(og, 68, 606),
+                         [int(np.argmax(np.diff(ex["a_rowptr"]))), int(np.flatnonzero(ex["padded"])[0])]])
+    sd = sd.astype(np.int32)
+    k = sd.size
+    tiles = [range(t, min(k, t + kt)) for t in range(0, k, kt)]
+    W = np.array([sum(frontier_edges(ex, int(sd[i])) for i in t) for t in tiles])
+    mid, big = int(np.median(W)), int(W.max())
+    seeds = torch.from_numpy(sd).cuda()
+    runs = tile_runs(gg, torch, seeds, kt, Sq, (big, 0, mid))
+    again = tile_runs(gg, torch, seeds, kt, Sq, (big,))
+    assert torch.equal(runs[big], again[big])
+    expect = np.stack([og.query(int(s), c, Sq, T) for s in sd])
+    res = {lim: r.cpu().numpy() for lim, r in runs.items()}
+    for lim, r in res.items():
+        assert np.all(l1_rows(r, expect) <= TOL), lim
+    pushed, pulled, mixed = res[big], res[0], res[mid]
+    assert np.abs(pushed - pulled).max() <= 1e-6
+    assert not np.array_equal(pushed, pulled)  # the pushed sums round differently somewhere
+    for t, w in zip(tiles, W):
+        rows = list(t)
+        assert np.array_equal(mixed[rows], (pushed if w <= mid else pulled)[rows]), (rows[0], w, mid)
+
+
+@pytest.mark.parametrize("kt", [4, 64])
+def test_tile_second_step_push_weighted(tpa, torch, kt):
+    """Row-softmax edge weights: the tile's plan takes each y1 entry from
+    its A~ edge weight and the push multiplies by the frontier edge's
+    weight; pushed and pulled tiles match the oracle."""
+    og = oracle.Graph.rmat(10, 12000, 23)
+    gg = tpa.Graph.rmat(10, 12000, 23)
+    theta = ti.draw_logits(og.m, 9)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    sd = seeds_for(og, 40, 3)
+    runs = tile_runs(gg, torch, torch.from_numpy(sd).cuda(), kt, S, (4 * og.m, 0))
+    expect = np.stack([og.query(int(s), c, S, T) for s in sd])
+    for lim, r in runs.items():
+        assert np.all(l1_rows(r.cpu().numpy(), expect) <= TOL), lim
+    assert (runs[4 * og.m] - runs[0]).abs().max().item() <= 1e-6
+
+
+def test_tile_push_plan_limit(tpa, torch):
+    """The device plans a tile's push with one entry per frontier node, at
+    most 16384: a tile of 64 seeds with 300 out-edges each (19264 entries)
+    pulls, one of 54 of them (16254 entries) pushes.  Their out-neighbours
+    include nodes of 600 out-edges, whose edges are pushed in three pieces.
+    Both match the oracle; the first equals the pulled tile bit for bit,
+    the second does not."""
+    rng = np.random.default_rng(98)
+    n = 20000
+    src, dst = [], []
+    for s in range(64):
+        src.append(np.full(300, s))
+        dst.append(np.concatenate([64 + rng.choice(36, 4, replace=False), 100 + rng.choice(n - 100, 296, replace=False)]))
+    for h in range(64, 100):
+        src.append(np.full(600, h))
+        dst.append(rng.choice(n, 600, replace=False))
+    rest = np.arange(100, n)
+    src.append(np.repeat(rest, 3))
+    dst.append(rng.integers(0, n, size=3 * rest.size))
+    src, dst = np.concatenate(src).astype(np.int32), np.concatenate(dst).astype(np.int32)
+    og = oracle.Graph(n, src, dst)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    gg.preprocess(c, T)
+    ex = og.export()
+    assert int(np.diff(ex["a_rowptr"])[:64].min()) == 300
+    for cols in (64, 54):
+        sd = np.arange(cols, dtype=np.int32)
+        runs = tile_runs(gg, torch, torch.from_numpy(sd).cuda(), 64, S, (1 << 40, 0))
+        expect = np.stack([og.query(int(s), c, S, T) for s in sd])
+        for lim, r in runs.items():
+            assert np.all(l1_rows(r.cpu().numpy(), expect) <= TOL), (cols, lim)
+        same = torch.equal(runs[1 << 40], runs[0])
+        assert same == (cols == 64), cols
 
 
 # ---------------------------------------------------------------- gather layout
