@@ -98,14 +98,13 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax);
 // entries, at most qmax pieces) and the tile's frontier edges W = sum over
 // j of sum over F_j of outdeg number at most wmax, the flag is set and the
 // pieces are pushed into acc.  acc holds y2 in gathered form, by gather row,
-// [n][kt] in 2^62 fixed point, all zero between queries; bits receives the
-// rows the push reached.
+// [n][kt] in 2^62 fixed point, all zero between queries; mark[r] is set (a
+// plain byte store, no atomic) for every row r the push reached.
 constexpr int kTilePlanMax = 16384;
 constexpr int kTilePiece = 256;
 struct TilePush {
     unsigned long long *acc = nullptr;  // [n][kt] by gather row
-    uint32_t *bits = nullptr;           // [ceil(n/32)]
-    int64_t nwords = 0;
+    uint8_t *mark = nullptr;            // [n] by gather row, cleared by the plan launch
     int64_t *ent_e0 = nullptr;          // [kTilePlanMax] first A~ edge of the entry's node
     int64_t *ent_e1 = nullptr;          // end of its edges
     float *ent_y = nullptr;             // its y1 value, gathered form
@@ -123,7 +122,7 @@ size_t tile_push_bytes(int64_t n, int64_t m, int kt);
 TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax);
 
 // Steps 1 and 2 of a seed tile, pushed when the device's plan allows:
-// clears bits, plans (flag, ctrl, the restart terms c e_s of y2 in acc) and
+// clears mark, plans (flag, ctrl, the restart terms c e_s of y2 in acc) and
 // pushes the plan's pieces (nothing when the flag is clear).  The caller
 // launches the pushed first step (launch_push_first) between the plan and
 // the push with p.skip_on = tp.flag, so it runs only when step 2 is pulled.

@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(1024) void tile_plan_kernel(StepParams p, const int
         if (s >= 0 && (int64_t)s < p.n) {
             const int64_t zr = zrow(p, s);
             atomicAdd(&tp.acc[zr * p.kt + tid], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
-            atomicOr(&tp.bits[zr >> 5], 1u << (zr & 31));
+            tp.mark[zr] = 1;
         }
     }
 }
@@ -1137,8 +1137,10 @@ __global__ __launch_bounds__(1024) void tile_plan_kernel(StepParams p, const int
 // The pushed second step of a seed tile: waves stride over the plan's
 // pieces; lanes take a piece's edges in order and add each edge's term of
 // column j to acc in 2^62 fixed point (no atomic result awaited), marking
-// its row in bits.  Every term lies in [0, 1] and column j's terms add up to
-// at most the mass of its y2, below 1, so no sum overflows.
+// its row with a byte store (an atomic OR into a bitmap word, which the
+// rows of 32 hub-ranked nodes share, serialises: it tripled the launch).
+// Every term lies in [0, 1] and column j's terms add up to at most the mass
+// of its y2, below 1, so no sum overflows.
 __global__ __launch_bounds__(256) void tile_push_kernel(StepParams p, const int32_t *a_col, const float *a_w,
                                                         TilePush tp) {
     if (!*tp.flag) return;
@@ -1157,8 +1159,7 @@ __global__ __launch_bounds__(256) void tile_push_kernel(StepParams p, const int3
             const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
             const int64_t zr = zrow(p, v);
             atomicAdd(&tp.acc[zr * p.kt + j], to_fixed62(term));
-            const uint32_t bit = 1u << (zr & 31);
-            if (!(tp.bits[zr >> 5] & bit)) atomicOr(&tp.bits[zr >> 5], bit);
+            tp.mark[zr] = 1;
         }
     }
 }
@@ -1175,7 +1176,7 @@ __global__ __launch_bounds__(256) void tile_convert_kernel(StepParams p, TilePus
     for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < total; i0 += stride) {
         if (kt >= 4) {
             const int64_t zr = i0 / kt;
-            const bool live = (tp.bits[zr >> 5] >> (zr & 31)) & 1u;
+            const bool live = tp.mark[zr] != 0;
             float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
             if (live) {
                 ulonglong2 *a = reinterpret_cast<ulonglong2 *>(tp.acc + i0);
@@ -1190,7 +1191,7 @@ __global__ __launch_bounds__(256) void tile_convert_kernel(StepParams p, TilePus
             for (int k = 0; k < 4 && i0 + k < total; ++k) {
                 const int64_t i = i0 + k, zr = i / kt;
                 float z = 0.0f;
-                if ((tp.bits[zr >> 5] >> (zr & 31)) & 1u) {
+                if (tp.mark[zr]) {
                     const unsigned long long a = tp.acc[i];
                     z = (float)((double)a * 0x1p-62);
                     if (a) tp.acc[i] = 0ull;
@@ -1437,7 +1438,7 @@ int64_t tile_qmax(int64_t m) { return 4 * (m / kTilePiece + 1) + kTilePlanMax; }
 
 size_t tile_push_bytes(int64_t n, int64_t m, int kt) {
     const size_t P = kTilePlanMax;
-    return align256((size_t)n * kt * 8) + bits_bytes(n) + 256 + align256(P * 8) * 2 + align256(P * 4) * 2 +
+    return align256((size_t)n * kt * 8) + align256((size_t)n) + 256 + align256(P * 8) * 2 + align256(P * 4) * 2 +
            align256((size_t)tile_qmax(m) * 8);
 }
 
@@ -1447,9 +1448,8 @@ TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax) {
     TilePush tp;
     tp.acc = reinterpret_cast<unsigned long long *>(b);
     b += align256((size_t)n * kt * 8);
-    tp.bits = reinterpret_cast<uint32_t *>(b);
-    tp.nwords = (n + 31) / 32;
-    b += bits_bytes(n);
+    tp.mark = reinterpret_cast<uint8_t *>(b);
+    b += align256((size_t)n);
     tp.ctrl = reinterpret_cast<int64_t *>(b);
     tp.flag = reinterpret_cast<int32_t *>(b + 64);
     b += 256;
@@ -1470,7 +1470,8 @@ TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax) {
 tpa_status launch_tile_plan(const StepParams &p, const tpa_graph *g, const TilePush &tp, hipStream_t st) {
     if (p.kt < 2 || p.node_block || !p.seeds || p.ncols > 64) return fail(TPA_ERR_INVALID_ARG, "tile push needs seed lists");
     const int slot = profile_begin(122, st);
-    fill_zero_kernel<<<grid_1d(tp.nwords), 256, 0, st>>>(reinterpret_cast<float *>(tp.bits), tp.nwords);
+    const int64_t mwords = (p.n + 3) / 4;  // mark as 4-byte words (its bytes are 256-aligned)
+    fill_zero_kernel<<<grid_1d(mwords), 256, 0, st>>>(reinterpret_cast<float *>(tp.mark), mwords);
     tile_plan_kernel<<<1, 1024, 0, st>>>(p, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr, tp);
     profile_end(slot, st);
     TPA_TRY_HIP(hipGetLastError());
