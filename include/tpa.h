@@ -307,11 +307,12 @@ tpa_status tpa_get_tuning(tpa_graph_t g, int *seed_tile, int *edges_per_item);
  * restores the default (m/8, at least 1024), 0 always pulls.  The pushed
  * sums are exact fixed-point additions of FP32 terms, so results are
  * reproducible but may differ from the pulled step in the last bits.
- * The pull that follows a push (step 3 after a pushed step 2, step 2 after
- * the pushed step 1 of a seed tile of 1 or 64) skips the gathers of rows
- * the push left zero, using a bitmap the push fills; the skipped terms are
- * exact zeros, so the sums are unchanged.  max_edges = 0 also turns this
- * skip off.
+ * The pull that follows a push (step 3 after a pushed step 2 when it is
+ * not pushed itself, see tpa_set_third_push_limit; step 2 after the pushed
+ * step 1 of a seed tile of 1 or 64) skips the gathers of rows the push
+ * left zero, using a bitmap the push fills; the skipped terms are exact
+ * zeros, so the sums are unchanged.  max_edges = 0 also turns this skip
+ * off.
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
 
@@ -334,6 +335,21 @@ tpa_status tpa_set_push_limit(tpa_graph_t g, int64_t max_edges);
  * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
 tpa_status tpa_set_tile_push_limit(tpa_graph_t g, int64_t max_edges);
 tpa_status tpa_get_tile_push_limit(tpa_graph_t g, int64_t *max_edges);
+
+/* Direction of the third family step of a single-seed query whose second
+ * step was pushed (S >= 5, so that step 3 is not the last).  x(2) lives on
+ * the rows the push reached; the device lists them (with their out-edges,
+ * W3 in all) from the step's bitmap and pushes step 3 over those edges
+ * when W3 <= `max_edges` (Section 2.3's CPI step, as for step 2), else it
+ * pulls the step with the frontier skip.  max_edges = -1 restores the
+ * default: m/20 on graphs of at least 2^28 edges, where a pulled step
+ * costs far more than the list, push and conversion launches, and always
+ * pull on smaller ones; 0 always pulls; tpa_set_push_limit(g, 0) turns this
+ * push off as well.  Pushed sums are exact fixed-point additions
+ * of FP32 terms (reproducible, within FP32 rounding of the pull).
+ * Errors: INVALID_ARG (NULL graph, max_edges < -1). */
+tpa_status tpa_set_third_push_limit(tpa_graph_t g, int64_t max_edges);
+tpa_status tpa_get_third_push_limit(tpa_graph_t g, int64_t *max_edges);
 
 /* Keep the stranger chain's iterates (Algorithm 2's x'(0) .. x'(K-1), node
  * order, K x n floats) on the handle at the next tpa_preprocess, so that

@@ -71,6 +71,8 @@ _SIGS = {
     "tpa_get_push_limit": (_i, [_vp, _vp]),
     "tpa_set_tile_push_limit": (_i, [_vp, _i64]),
     "tpa_get_tile_push_limit": (_i, [_vp, _vp]),
+    "tpa_set_third_push_limit": (_i, [_vp, _i64]),
+    "tpa_get_third_push_limit": (_i, [_vp, _vp]),
     "tpa_get_device_error": (_i, [_vp, _vp]),
     "tpa_cpi": (_i, [_vp, C.c_int32, _vp, _d, _i, _i, _d, _vp, _vp]),
     "tpa_cpi_batch": (_i, [_vp, _vp, _vp, _i64, _d, _i, _i, _d, _vp, _vp]),
@@ -496,6 +498,18 @@ class Graph:
     def get_tile_push_limit(self) -> int:
         v = C.c_int64()
         _call("tpa_get_tile_push_limit", self._h, C.byref(v))
+        return v.value
+
+    def set_third_push_limit(self, max_edges: int = -1):
+        """Single-seed queries whose second step was pushed push their third
+        step too when y2's support has at most max_edges out-edges (-1:
+        default m/20 on graphs of at least 2^28 edges, else pull; 0: always
+        pull)."""
+        _call("tpa_set_third_push_limit", self._h, max_edges)
+
+    def get_third_push_limit(self) -> int:
+        v = C.c_int64()
+        _call("tpa_get_third_push_limit", self._h, C.byref(v))
         return v.value
 
     def get_tuning(self):

@@ -81,14 +81,26 @@ struct PushPlan {
     unsigned long long *acc = nullptr;  // [n] by gather row, zero between queries
     uint32_t *bits = nullptr;           // [ceil(n/32)]: rows of the pushed vector that may be non-zero
     int64_t nwords = 0;
-    int64_t *ctrl = nullptr;            // {W, |F|}
+    int64_t *ctrl = nullptr;            // {W, |F|, W3, pieces3}
     int32_t *flag = nullptr;            // 1: step 2 is pushed (the gated step converts acc)
     int64_t wmax = 0;                   // push only when W <= wmax
+    // The third step after a pushed second one: the rows of y2's support
+    // (bits) become a list of pieces of at most kTilePiece out-edges of A~
+    // (node << 32 | offset of the first edge), W3 = their out-edges in all.
+    // Step 3 is pushed into acc (cleared by the step-2 conversion) when W3 <=
+    // wmax3 and the pieces fit (flag3 = 1), and pulled otherwise.
+    int64_t *pieces3 = nullptr;         // [qmax3]
+    int64_t qmax3 = 0;
+    int64_t wmax3 = 0;                  // 0: step 3 is always pulled
+    int32_t *flag3 = nullptr;
 };
 
-// Bytes of the push state (kept at the front of the query workspace).
-size_t push_plan_bytes(int64_t n, int64_t max_outdeg);
-PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax);
+// Bytes of the push state (kept at the front of the query workspace), and
+// of its leading part that must be zero before the first query (acc, ctrl,
+// flags, bits; the pieces need no clearing).
+size_t push_plan_bytes(int64_t n, int64_t m);
+size_t push_plan_clear_bytes(int64_t n);
+PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wmax3);
 
 // Device state of the pushed first two family steps of a seed tile (kt >= 2,
 // one-hot seeds, unpacked graph).  Column j's x(1) lives on F_j = out(s_j)
@@ -120,6 +132,14 @@ struct TilePush {
 // (256-byte aligned).
 size_t tile_push_bytes(int64_t n, int64_t m, int kt);
 TilePush tile_push_at(void *base, int64_t n, int64_t m, int kt, int64_t wmax);
+
+// Step 3 of a single seed after a pushed step 2 (p.zin = y2 gathered, p.zout
+// = y3 gathered): the frontier list and the push (nothing unless step 2 was
+// pushed and the frontier is small enough), then the conversion of every
+// row from acc, or (launched with p.skip_on = pp.flag3 by the caller) the
+// frontier-skipped pull.
+tpa_status launch_push_third(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st);
+tpa_status launch_convert_third(const StepParams &p, const PushPlan &pp, hipStream_t st);
 
 // Steps 1 and 2 of a seed tile, pushed when the device's plan allows:
 // clears mark, plans (flag, ctrl, the restart terms c e_s of y2 in acc) and

@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
-    if (wid >= n_items) return;
+    if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
     const Item it = items[wid];
     if (item_kind(it.meta) == kItemBlock) {
         block_row_1<MODE, FIRST, WEIGHTED>(p, it, lane, wv, lds);
@@ -984,6 +984,9 @@ __global__ __launch_bounds__(256) void push_steps12_kernel(StepParams p, const i
     if (blockIdx.x == 0 && tid == 0) {
         pp.ctrl[0] = W;
         pp.ctrl[1] = nf;
+        pp.ctrl[2] = 0;  // the third step's frontier list starts empty
+        pp.ctrl[3] = 0;
+        *pp.flag3 = 0;
         *pp.flag = push ? 1 : 0;
         // the restart term of y2 (other blocks may already be adding to the row)
         if (push) atomicAdd(&pp.acc[zrow(p, s)], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
@@ -1027,6 +1030,153 @@ __global__ __launch_bounds__(256) void push_steps12_kernel(StepParams p, const i
         // for uniform weights)
         const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
         atomicAdd(&pp.acc[zrow(p, v)], to_fixed62(term));
+    }
+}
+
+// ------------------------------------------------------------ pushed third step
+// Whether step 3 of the current single-seed query is pushed: step 2 was,
+// and its support's out-edges and pieces are within the limits.  The
+// counters are final once the list launch has ended.
+__device__ __forceinline__ bool third_pushed(const PushPlan &pp) {
+    return pp.wmax3 > 0 && *pp.flag && pp.ctrl[2] <= pp.wmax3 && pp.ctrl[3] <= pp.qmax3;
+}
+
+// The frontier list of y2: every row set in bits (written by the step-2
+// conversion) gives its node u (through zinv, the node at each gather row)
+// and ceil(outdeg(u) / kTilePiece) pieces.  Threads take rows (row r of
+// round i at r = (i * gridDim.x + block) * 256 + thread), so the live rows'
+// lookups run in parallel; each block walks its rows twice, first counting
+// its pieces and out-edges (one block scan, one atomic per counter for the
+// whole block: counters that every wave bumped serialised the list), then
+// writing the pieces from its reserved base.  The list order is arbitrary;
+// the fixed-point sums do not depend on it.
+__device__ __forceinline__ bool list_row(const PushPlan &pp, const int32_t *zinv, const int64_t *a_rowptr, int64_t zr,
+                                         int64_t n, int64_t &u, int64_t &deg) {
+    if (zr >= n || !((pp.bits[zr >> 5] >> (zr & 31)) & 1u)) return false;
+    u = zinv ? (int64_t)zinv[zr] : zr;
+    deg = a_rowptr[u + 1] - a_rowptr[u];
+    return true;
+}
+
+__global__ __launch_bounds__(256) void frontier_list_kernel(StepParams p, PushPlan pp, const int64_t *a_rowptr,
+                                                            const int32_t *zinv) {
+    __shared__ long long swq[4], sww[4];
+    __shared__ long long sbase;
+    __shared__ int sover;
+    if (!*pp.flag || pp.wmax3 <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t r0 = (int64_t)blockIdx.x * 256 + tid;
+    // past the limit the step is pulled: nothing to list (one read for the
+    // whole block, so that every wave meets the barriers below)
+    if (tid == 0) sover = __hip_atomic_load(&pp.ctrl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > pp.wmax3;
+    __syncthreads();
+    if (sover) return;
+    long long tq = 0, tw = 0;  // this thread's pieces and out-edges
+    constexpr int R = 8;       // rows whose bitmap words are read together
+    for (int64_t zb = r0; zb < p.n; zb += R * stride) {
+        bool live[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int64_t zr = zb + i * stride;
+            live[i] = zr < p.n && ((pp.bits[zr >> 5] >> (zr & 31)) & 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            int64_t u = 0, deg = 0;
+            if (live[i] && list_row(pp, zinv, a_rowptr, zb + i * stride, p.n, u, deg)) {
+                tq += (deg + kTilePiece - 1) / kTilePiece;
+                tw += deg;
+            }
+        }
+    }
+    const long long iq = wave_scan_incl(tq, lane);
+    const long long iw = wave_scan_incl(tw, lane);
+    if (lane == 63) {
+        swq[wv] = iq;
+        sww[wv] = iw;
+    }
+    __syncthreads();
+    long long before = 0, bq = 0, bw = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wv) before += swq[w];
+        bq += swq[w];
+        bw += sww[w];
+    }
+    if (tid == 0) {
+        sbase = bq ? (long long)atomicAdd(reinterpret_cast<unsigned long long *>(&pp.ctrl[3]), (unsigned long long)bq) : 0;
+        const long long wsum =
+            bw ? (long long)atomicAdd(reinterpret_cast<unsigned long long *>(&pp.ctrl[2]), (unsigned long long)bw) + bw : 0;
+        sover = wsum > pp.wmax3;  // already past the limit: the pieces will not be pushed
+    }
+    __syncthreads();
+    if (bq == 0 || sover) return;
+    long long q = sbase + before + iq - tq;  // this thread's first piece
+    if (tq == 0) return;
+    for (int64_t zb = r0; zb < p.n; zb += R * stride) {  // the same rows in the same order
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            int64_t u = 0, deg = 0;
+            if (list_row(pp, zinv, a_rowptr, zb + i * stride, p.n, u, deg))
+                for (int64_t off = 0; off < deg; off += kTilePiece, ++q)
+                    if (q < pp.qmax3) pp.pieces3[q] = (long long)(u << 32) | off;
+        }
+    }
+}
+
+// The pushed third step: waves stride over the pieces; each lane adds its
+// edge's (1-c) term of y2 (gathered from p.zin) to acc at the destination's
+// gather row in 2^62 fixed point; one thread adds the restart term c e_s.
+// The terms of y3 add up to at most its mass, below 1.
+__global__ __launch_bounds__(256) void push_third_kernel(StepParams p, PushPlan pp, const int64_t *a_rowptr,
+                                                         const int32_t *a_col, const float *a_w) {
+    if (!third_pushed(pp)) return;
+    const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t s = p.seeds[0];
+        atomicAdd(&pp.acc[zrow(p, s)], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
+        *pp.flag3 = 1;
+    }
+    const int64_t nq = pp.ctrl[3];
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < nq; q += nwaves) {
+        const long long pc = pp.pieces3[q];
+        const int64_t u = pc >> 32;
+        const int64_t e0 = a_rowptr[u] + (pc & 0xffffffffll);
+        const int64_t e1 = min(e0 + (int64_t)kTilePiece, a_rowptr[u + 1]);
+        const float zu = p.zin[zrow(p, u)];
+        for (int64_t e = e0 + lane; e < e1; e += 64) {
+            const int32_t v = a_col[e];
+            const float term = a_w ? p.omc * (zu * a_w[e]) : (p.omc * zu) * p.inv[v];
+            atomicAdd(&pp.acc[zrow(p, v)], to_fixed62(term));
+        }
+    }
+}
+
+// y3 from acc as the next gathered vector, every row (acc cleared).
+// Nothing unless step 3 was pushed (flag3 is cleared by the next query's
+// first launch).
+__global__ __launch_bounds__(256) void convert_third_kernel(StepParams p, PushPlan pp) {
+    if (!*pp.flag3) return;
+    // four rows per thread (two 16-byte loads, one 16-byte store) where aligned
+    const bool vec = (reinterpret_cast<uintptr_t>(p.zout) & 15) == 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+    for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; r0 < p.n; r0 += stride) {
+        if (vec && r0 + 3 < p.n) {
+            ulonglong2 *a = reinterpret_cast<ulonglong2 *>(pp.acc + r0);
+            const ulonglong2 lo = a[0], hi = a[1];
+            *reinterpret_cast<float4 *>(p.zout + r0) =
+                make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
+                            (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
+            if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
+            if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
+        } else {
+            for (int64_t r = r0; r < r0 + 4 && r < p.n; ++r) {
+                const unsigned long long a = pp.acc[r];
+                p.zout[r] = (float)((double)a * 0x1p-62);
+                if (a) pp.acc[r] = 0ull;
+            }
+        }
     }
 }
 
@@ -1410,23 +1560,35 @@ namespace {
 size_t bits_bytes(int64_t n) { return (((size_t)(n + 31) / 32) * 4 + 255) & ~(size_t)255; }
 }  // namespace
 
-size_t push_plan_bytes(int64_t n, int64_t max_outdeg) {
-    (void)max_outdeg;
+// Pieces of the pushed third step: one or more per node of y2's support
+// (at most 2^22 nodes counted), and one per kTilePiece of m/20 edges.
+int64_t third_qmax(int64_t n, int64_t m) {
+    return std::min<int64_t>(n, int64_t(1) << 22) + m / 20 / kTilePiece + 2;
+}
+
+size_t push_plan_clear_bytes(int64_t n) {
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     return a + 256 + bits_bytes(n);
 }
 
-PushPlan push_plan_at(void *base, int64_t n, int64_t max_outdeg, int64_t wmax) {
-    (void)max_outdeg;
+size_t push_plan_bytes(int64_t n, int64_t m) {
+    return push_plan_clear_bytes(n) + (((size_t)third_qmax(n, m) * 8 + 255) & ~(size_t)255);
+}
+
+PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wmax3) {
     char *b = static_cast<char *>(base);
     const size_t a = ((size_t)n * 8 + 255) & ~(size_t)255;
     PushPlan pp;
     pp.acc = reinterpret_cast<unsigned long long *>(b);
     pp.ctrl = reinterpret_cast<int64_t *>(b + a);
     pp.flag = reinterpret_cast<int32_t *>(b + a + 64);
+    pp.flag3 = reinterpret_cast<int32_t *>(b + a + 68);
     pp.bits = reinterpret_cast<uint32_t *>(b + a + 256);
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
+    pp.pieces3 = reinterpret_cast<int64_t *>(b + push_plan_clear_bytes(n));
+    pp.qmax3 = third_qmax(n, m);
+    pp.wmax3 = wmax3;
     return pp;
 }
 
@@ -1524,6 +1686,26 @@ tpa_status launch_gated_step(const Schedule &s, const StepParams &p0, const Push
         profile_end(slot, st);
     }
     if (s.n_long > 0) gated_finish_kernel<<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p, pp);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_push_third(const StepParams &p, const tpa_graph *g, const PushPlan &pp, hipStream_t st) {
+    if (p.kt != 1 || p.node_block || !p.seeds || p.last)
+        return fail(TPA_ERR_INVALID_ARG, "a pushed third step is a single-seed non-last family step");
+    const int slot = profile_begin(126, st);
+    const int64_t lblocks = std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, 1024));
+    frontier_list_kernel<<<(unsigned)lblocks, 256, 0, st>>>(p, pp, g->a.rowptr, g->zperm && p.zperm ? g->zinv : nullptr);
+    // waves stride over the pieces
+    const int64_t blocks = std::min<int64_t>(std::max<int64_t>(1, pp.qmax3 / 16), 1024);
+    push_third_kernel<<<(unsigned)blocks, 256, 0, st>>>(p, pp, g->a.rowptr, g->a.col, g->weighted ? g->a.w : nullptr);
+    profile_end(slot, st);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status launch_convert_third(const StepParams &p, const PushPlan &pp, hipStream_t st) {
+    convert_third_kernel<<<(unsigned)std::min<int64_t>((p.n + 1023) / 1024, 2048), 256, 0, st>>>(p, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

@@ -525,6 +525,10 @@ tpa_status ensure_zlayout(tpa_graph *g, hipStream_t st) {
     invert_perm_kernel<<<grid_for(n), kBlock, 0, st>>>(vb.current(), n, rank);
     map_cols_kernel<<<grid_for(m), kBlock, 0, st>>>(g->t.col, m, rank, colz);
     e = hipStreamSynchronize(st);
+    // the sorted ids are the node at each gather row: kept
+    int32_t *zinv = vb.current();
+    if (zinv == v0) v0 = nullptr;
+    else v1 = nullptr;
     cleanup();
     // each row's edges in ascending hub rank: the first edges of every row
     // then read the same few cache lines of the gathered vector; each edge's
@@ -560,15 +564,17 @@ tpa_status ensure_zlayout(tpa_graph *g, hipStream_t st) {
         dfree(k2b);
         dfree(tmp2);
         if (e != hipSuccess && rc == TPA_OK) rc = fail(TPA_ERR_HIP, std::string("row sort: ") + hipGetErrorString(e));
-        if (rc != TPA_OK) { dfree(rank); dfree(colz); dfree(loc); return rc; }
+        if (rc != TPA_OK) { dfree(rank); dfree(zinv); dfree(colz); dfree(loc); return rc; }
     }
     if (e != hipSuccess) {
         dfree(rank);
+        dfree(zinv);
         dfree(colz);
         dfree(loc);
         return fail(TPA_ERR_HIP, std::string("gather layout: ") + hipGetErrorString(e));
     }
     g->zperm = rank;
+    g->zinv = zinv;
     g->t_colz = colz;
     g->t_locz = loc;
     g->t_wz_valid = false;
@@ -781,7 +787,8 @@ void graph_release(tpa_graph *g) {
     dfree(g->a.rowptr); dfree(g->a.col); dfree(g->a.w);
     dfree(g->t.rowptr); dfree(g->t.col); dfree(g->t.w);
     dfree(g->t2a); dfree(g->inv_deg); dfree(g->padded);
-    dfree(g->zperm); dfree(g->t_colz); dfree(g->t_locz); dfree(g->t_wz);
+    dfree(g->zperm); dfree(g->zinv); dfree(g->t_colz); dfree(g->t_locz); dfree(g->t_wz);
+    g->zinv = nullptr;
     dfree(g->lrank); dfree(g->a_colr);
     g->lrank = nullptr;
     g->a_colr = nullptr;
@@ -1011,6 +1018,7 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     add(g->node_block, sizeof(int32_t) * n);
     add(g->restart_pr, sizeof(float) * n);
     add(g->zperm, sizeof(int32_t) * n);
+    add(g->zinv, sizeof(int32_t) * n);
     add(g->t_colz, sizeof(int32_t) * m);
     add(g->t_locz, sizeof(int32_t) * m);
     add(g->t_wz, sizeof(float) * m);

@@ -100,7 +100,7 @@ int choose_kt(const tpa_graph *g, int64_t k) {
 
 // The push accumulator must be zero before the first query on a workspace.
 tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st) {
-    TPA_TRY_HIP(hipMemsetAsync(ws, 0, push_plan_bytes(g->n, g->max_outdeg), st));
+    TPA_TRY_HIP(hipMemsetAsync(ws, 0, push_plan_clear_bytes(g->n), st));
     return TPA_OK;
 }
 
@@ -111,6 +111,24 @@ tpa_status clear_push_state(const tpa_graph *g, void *ws, hipStream_t st) {
 int64_t push_wmax(const tpa_graph *g) {
     if (g->push_limit >= 0) return g->push_limit;
     return std::max<int64_t>(1024, g->m / 8);
+}
+
+// Largest out-edge count of y2's support for which step 3 of a single seed
+// (after a pushed step 2) is pushed: m/20 (a pushed edge costs about 20
+// times a pulled one: an atomic and two gathers against a coalesced index
+// and one gather), and never when pushes are off.  By default only graphs
+// of at least kThirdPushMinEdges edges try it: the list, push and
+// conversion launches cost a fixed 20-25 us per query even when the step is
+// then pulled, more than the pulls they save on R-MAT graphs of 1.7e7 and
+// 6.7e7 edges (125 against 152, 585 against 601 us per query); on 2.2e9
+// edges a query takes 28.7 against 30.9 ms.
+constexpr int64_t kThirdPushMinEdges = int64_t(1) << 28;
+
+int64_t third_wmax(const tpa_graph *g) {
+    if (push_wmax(g) <= 0) return 0;
+    if (g->third_push_limit >= 0) return g->third_push_limit;
+    if (g->m < kThirdPushMinEdges) return 0;
+    return std::max<int64_t>(1024, g->m / 20);
 }
 
 namespace {
@@ -127,7 +145,7 @@ size_t query_ws_floats_before_qt(const tpa_graph *g, const Schedule *s, int kt) 
 
 size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, bool dense) {
     const size_t qf = dense ? (size_t)g->n * kt : 0;
-    return push_plan_bytes(g->n, g->max_outdeg) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) + 256;
+    return push_plan_bytes(g->n, g->m) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) + 256;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -252,8 +270,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
         TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt, q != nullptr), st));
         ws = g->ws;
     }
-    const PushPlan pp = push_plan_at(ws, g->n, g->max_outdeg, push_wmax(g));
-    float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->max_outdeg));
+    const PushPlan pp = push_plan_at(ws, g->n, g->m, push_wmax(g), third_wmax(g));
+    float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->m));
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
     float *qT = z0 + query_ws_floats_before_qt(g, s, kt);  // used by dense restarts only
@@ -261,6 +279,8 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     // the seed's neighbourhood when it is small, pull otherwise (decided on
     // the device, so the launch sequence is fixed and capturable)
     const bool push2 = kt == 1 && !packed && !q && S >= 4 && pp.wmax > 0;
+    // and its third step when that is not the last either
+    const bool push3 = push2 && S >= 5 && pp.wmax3 > 0;
     // pulls after a push skip the rows it left zero (seed tiles of 1 and 64)
     const bool frontier = pp.wmax > 0 && (kt == 1 || kt == 64);
     // a seed tile whose step 2 is not the last: the device pushes step 2 from
@@ -343,6 +363,20 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                 p2.col = col_gather;
                 p2.w = w_gather;
                 TPA_TRY(launch_step(*s, kFamily, false, p2, st));
+                continue;
+            }
+            if (step == 3 && push3) {
+                // pushed over y2's support when it is small, else pulled
+                // with the frontier skip (each launch runs only in its case)
+                StepParams p3 = p;
+                p3.col = col_gather;
+                p3.w = w_gather;
+                TPA_TRY(launch_push_third(p3, g, pp, st));
+                TPA_TRY(launch_convert_third(p3, pp, st));
+                p3.bits = pp.bits;
+                p3.bits_on = pp.flag;
+                p3.skip_on = pp.flag3;
+                TPA_TRY(launch_step(*s, kFamily, false, p3, st));
                 continue;
             }
             if (step == 2 && push2) {
@@ -614,6 +648,19 @@ extern "C" tpa_status tpa_get_tile_push_limit(tpa_graph_t g, int64_t *max_edges)
     return TPA_OK;
 }
 
+extern "C" tpa_status tpa_set_third_push_limit(tpa_graph_t g, int64_t max_edges) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (max_edges < -1) return fail(TPA_ERR_INVALID_ARG, "max_edges must be >= -1");
+    g->third_push_limit = max_edges;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_third_push_limit(tpa_graph_t g, int64_t *max_edges) {
+    if (!g || !max_edges) return fail(TPA_ERR_INVALID_ARG, "bad argument");
+    *max_edges = g->third_push_limit;
+    return TPA_OK;
+}
+
 extern "C" tpa_status tpa_get_device_error(tpa_graph_t g, hipStream_t st) {
     if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
     int32_t v = 0;
@@ -691,7 +738,7 @@ extern "C" tpa_status tpa_query_noalloc(tpa_graph_t g, const int32_t *seeds, int
     void *ws = nullptr;
     TPA_TRY(scratch_address(&ws));
     // the push accumulators must be all zero when a query starts
-    TPA_TRY(launch_fill_zero(static_cast<float *>(ws), (int64_t)(push_plan_bytes(g->n, g->max_outdeg) / 4), st));
+    TPA_TRY(launch_fill_zero(static_cast<float *>(ws), (int64_t)(push_plan_clear_bytes(g->n) / 4), st));
     TileBuf tb;
     if (tbytes) {
         tb.base = static_cast<char *>(ws) + wsb;

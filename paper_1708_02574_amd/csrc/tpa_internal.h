@@ -158,6 +158,7 @@ struct tpa_graph {
     // each entry's position in its original row, and t_wz the per-edge
     // weights in that order (logit weights; rebuilt at preprocessing)
     int32_t *zperm = nullptr;               // n
+    int32_t *zinv = nullptr;                // n: node at each gather row (zperm's inverse)
     int32_t *t_colz = nullptr;              // m
     int32_t *t_locz = nullptr;              // m
     float *t_wz = nullptr;                  // m, weighted graphs
@@ -212,6 +213,7 @@ struct tpa_graph {
     int edges_per_item = 0;                 // 0 = automatic
     int64_t push_limit = -1;                // -1 = automatic, 0 = never push
     int64_t tile_push_limit = -1;           // seed tiles: -1 = automatic, 0 = never push
+    int64_t third_push_limit = -1;          // step 3 of a single seed: -1 = automatic, 0 = never push
 };
 
 namespace tpa {

@@ -47,6 +47,8 @@ def test_header_status_codes_match_binding():
     lambda L: L.tpa_get_push_limit(None, None),
     lambda L: L.tpa_set_tile_push_limit(None, -1),
     lambda L: L.tpa_get_tile_push_limit(None, None),
+    lambda L: L.tpa_set_third_push_limit(None, -1),
+    lambda L: L.tpa_get_third_push_limit(None, None),
     lambda L: L.tpa_set_gather_layout(None, 1),
     lambda L: L.tpa_cpi(None, 0, None, 0.15, 0, -1, 1e-9, None, None),
     lambda L: L.tpa_topk(None, 1, 10, 0, None, None, None),

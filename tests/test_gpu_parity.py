@@ -297,6 +297,87 @@ def test_second_step_push_weighted(tpa, torch):
     assert np.abs(res[0] - res[1]).max() <= 1e-6
 
 
+def support_edges(ex, s):
+    """Out-edges of y2's support F2 = out(F) + {s}, F = out(s) + {s}: the
+    work of a pushed step 3 (every y2 term is positive, so F2 is exactly
+    the support)."""
+    rp, col = ex["a_rowptr"], ex["a_col"]
+    nb = col[rp[s]:rp[s + 1]]
+    f = nb if s in nb else np.append(nb, s)
+    f2 = np.unique(np.concatenate([col[rp[u]:rp[u + 1]] for u in f] + [[s]]))
+    return int(np.diff(rp)[f2].sum()), f.size
+
+
+@pytest.mark.parametrize("Sq,layout", [(5, 2), (8, 2), (5, 0)])
+def test_third_step_push_and_pull(rmat13, torch, Sq, layout):
+    """Single seeds whose second step is pushed, with step 3 always pushed
+    (a limit above every frontier), always pulled (0) and chosen per seed
+    (the median frontier W3 = out-edges of y2's support): all within L1 of
+    the oracle, push and pull within FP32 rounding of each other, the
+    pushed queries bitwise reproducible in any order, and each seed of the
+    per-seed choice equal bit for bit to the direction its W3 picks (seeds
+    whose step 2 is pulled, F over 2048 nodes, pull step 3 too).  Layout 0
+    lists y2's support by node id, layout 2 through the gather rows."""
+    og, gg = rmat13
+    ex = og.export()
+    seeds = [int(s) for s in seeds_for(og, 12, 707)]
+    seeds += [int(np.argmax(np.diff(ex["a_rowptr"]))), int(np.flatnonzero(ex["padded"])[0])]
+    w3, nf = zip(*[support_edges(ex, s) for s in seeds])
+    w3, step2_pushed = np.array(w3), np.array(nf) <= 2048
+    mid, big = int(np.median(w3)), int(w3.max())
+    assert (w3 <= mid).any() and (w3 > mid).any()
+    expect = np.stack([og.query(s, c, Sq, T) for s in seeds])
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    runs = {}
+    try:
+        gg.set_gather_layout(layout)
+        gg.set_push_limit(og.m)
+        for limit in (big, 0, mid):
+            gg.set_third_push_limit(limit)
+            assert gg.get_third_push_limit() == limit
+            R = run_single(gg, torch, sd, Sq, list(range(len(seeds))))
+            R2 = run_single(gg, torch, sd, Sq, list(reversed(range(len(seeds)))))
+            assert torch.equal(R, R2), limit
+            runs[limit] = R.cpu().numpy()
+            assert np.all(l1_rows(runs[limit], expect) <= TOL), limit
+    finally:
+        gg.set_third_push_limit(-1)
+        gg.set_push_limit(-1)
+        gg.set_gather_layout(2)
+    pushed, pulled, mixed = runs[big], runs[0], runs[mid]
+    assert np.abs(pushed - pulled).max() <= 1e-6
+    assert not np.array_equal(pushed, pulled)
+    for i, w in enumerate(w3):
+        if not step2_pushed[i]:
+            assert np.array_equal(pushed[i], pulled[i]), i
+        assert np.array_equal(mixed[i], (pushed if w <= mid else pulled)[i]), (i, w, mid)
+
+
+def test_third_step_push_weighted(tpa, torch):
+    """Row-softmax edge weights in the pushed third step."""
+    og = oracle.Graph.rmat(10, 12000, 24)
+    gg = tpa.Graph.rmat(10, 12000, 24)
+    theta = ti.draw_logits(og.m, 10)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    seeds = [int(s) for s in seeds_for(og, 8, 4)]
+    expect = np.stack([og.query(s, c, S, T) for s in seeds])
+    sd = torch.tensor(seeds, dtype=torch.int32).cuda()
+    res = []
+    gg.set_push_limit(og.m)
+    try:
+        for limit in (4 * og.m, 0):
+            gg.set_third_push_limit(limit)
+            res.append(run_single(gg, torch, sd, S, list(range(len(seeds)))).cpu().numpy())
+            assert np.all(l1_rows(res[-1], expect) <= TOL), limit
+    finally:
+        gg.set_third_push_limit(-1)
+        gg.set_push_limit(-1)
+    assert np.abs(res[0] - res[1]).max() <= 1e-6
+
+
 def test_push_plan_size_limit(tpa, torch):
     """Each block of the pushed first two steps plans the seed's frontier
     F = out(s) + {s} in LDS, up to 2048 nodes.  Seeds with 2047 out-edges
