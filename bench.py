@@ -153,6 +153,20 @@ def profiled(tpa, torch, fn, codes, period=1):
     return out
 
 
+# launches outside the step-kernel numbering (tpa_profile_read codes)
+CODE_GATED_PULL = 118  # a pull that does nothing when the device pushed its step
+CODE_GATED, CODE_TILE_PLAN, CODE_TILE_PUSH, CODE_PUSH12, CODE_TILE_CONVERT, CODE_PUSH3 = 120, 122, 123, 124, 125, 126
+
+
+def breakdown(prof: dict, labels: dict) -> dict:
+    """{label: {launches timed, average us}} for the codes in labels."""
+    out = {}
+    for name, code in labels.items():
+        cnt, ms = prof.get(code, (0, 0.0))
+        out[name] = {"launches": cnt, "avg_us": round(ms * 1e3 / cnt, 2) if cnt else None}
+    return out
+
+
 def build_timed(torch, make):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -250,7 +264,18 @@ def headline(tpa, torch, np, ti, args) -> dict:
     say("kernel timing pass (separate from the timed steps)")
     cs, cf16, cf1 = tpa.profile_code(1, 1, False, False), tpa.profile_code(16, 0, False, False), \
         tpa.profile_code(1, 0, False, False)
-    prof = profiled(tpa, torch, step, [cs, cf16, cf1])
+    cf16l, cf1l = tpa.profile_code(16, 0, False, False, last=True), tpa.profile_code(1, 0, False, False, last=True)
+    plain_codes = {"push_steps_1_2": CODE_PUSH12, "step_2_gated": CODE_GATED, "step_3_list_and_push": CODE_PUSH3,
+                   "step_3_pull_unless_pushed": CODE_GATED_PULL, "step_4_pull_and_combine": cf1l}
+    batch_codes = {"tile_plan": CODE_TILE_PLAN, "tile_push_step_2": CODE_TILE_PUSH,
+                   "tile_convert_step_2": CODE_TILE_CONVERT, "step_3_pull": cf16, "step_4_pull_and_combine": cf16l}
+    # the plain and batched queries run in separate passes: the gated-pull
+    # code is shared by the single seeds' step 3 and the tiles' step 2
+    prof = profiled(tpa, torch, lambda: [g.query(seeds[i:i + 1], C_RESTART, S_FAM, T_STR, out=out_plain[i:i + 1])
+                                         for i in range(k)], list(plain_codes.values()))
+    prof.update(profiled(tpa, torch, lambda: g.query(seeds, C_RESTART, S_FAM, T_STR, out=out_batch),
+                         list(batch_codes.values())))
+    prof.update(profiled(tpa, torch, lambda: g.preprocess(C_RESTART, T_STR), [cs]))
     rec = {
         "metric": "TPA query GTEPS & seeds/s, batched vs 1-seed, at L1 <=1e-5 vs FP64 oracle",
         "value": round((K + 2 * k * (S_FAM - 1)) * m / (ms_step * 1e-3) / 1e9, 3),
@@ -280,11 +305,15 @@ def headline(tpa, torch, np, ti, args) -> dict:
         "roofline": roofline("step_kernel_1<stranger> (preprocessing CPI step, one vector)",
                              bytes_stranger(n, m, K, T_STR), *prof[cs],
                              traffic_from_profile("step_kernel_1_stranger_rmat27_traffic")),
-        "roofline_batched": roofline(f"step_kernel_kt<16, family> ({k}-seed tile CPI step)",
+        "roofline_batched": roofline(f"step_kernel_kt<16, family> ({k}-seed tile CPI step 3)",
                                      bytes_sweep(n, m, 16), *prof[cf16],
                                      traffic_from_profile("step_kernel_16_family_rmat27_traffic")),
-        "roofline_plain": roofline("step_kernel_1<family> (single-seed CPI step)", bytes_sweep(n, m, 1),
-                                   *prof[cf1]),
+        "roofline_batched_last": roofline(f"step_kernel_kt<16, family, last> ({k}-seed tile CPI step 4 with the "
+                                          "combine)", bytes_sweep(n, m, 16), *prof[cf16l]),
+        "roofline_plain": roofline("step_kernel_1<family, last> (single-seed CPI step 4 with the combine)",
+                                   bytes_sweep(n, m, 1), *prof[cf1l]),
+
+        "kernels_per_query": {"plain": breakdown(prof, plain_codes), "batched": breakdown(prof, batch_codes)},
         "checks": checks,
     }
     if not args.no_extras:
@@ -351,7 +380,12 @@ def rmat20(tpa, torch, np, ti, args, oracle_out) -> dict:
     ms_step, t_pre, t_pl, t_bat = tims[len(tims) // 2]
     cf1, cf64, cs = tpa.profile_code(1, 0, False, False), tpa.profile_code(64, 0, False, False), \
         tpa.profile_code(1, 1, False, False)
-    prof = profiled(tpa, torch, step, [cf1, cf64, cs], period=8)
+    cf1l, cf64l = tpa.profile_code(1, 0, False, False, last=True), tpa.profile_code(64, 0, False, False, last=True)
+    plain_codes = {"push_steps_1_2": CODE_PUSH12, "step_2_gated": CODE_GATED, "step_3_frontier_skipped_pull": cf1,
+                   "step_4_pull_and_combine": cf1l}
+    batch_codes = {"tile_plan": CODE_TILE_PLAN, "tile_push_step_2": CODE_TILE_PUSH,
+                   "tile_convert_step_2": CODE_TILE_CONVERT, "step_3_pull": cf64, "step_4_pull_and_combine": cf64l}
+    prof = profiled(tpa, torch, step, [cs] + list(plain_codes.values()) + list(batch_codes.values()), period=8)
     me = mass_expected(K)
     checks = {"mass_max_err": float(max((out_plain.double().sum(1) - me).abs().max().item(),
                                         (out_batch.double().sum(1) - me).abs().max().item())),
@@ -374,10 +408,16 @@ def rmat20(tpa, torch, np, ti, args, oracle_out) -> dict:
                   f"batched_{k}": round(t_bat, 3), "graph_build": round(build_ms, 1)},
            "gteps_step": round((K + 2 * k * (S_FAM - 1)) * m / (ms_step * 1e-3) / 1e9, 2),
            "seeds_per_s": {"plain": round(k / (t_pl * 1e-3), 1), "batched": round(k / (t_bat * 1e-3), 1)},
-           "roofline": roofline("step_kernel_1<family> (single-seed CPI step)", bytes_sweep(n, m, 1), *prof[cf1],
+           "roofline": roofline("step_kernel_1<family> (single-seed CPI step 3, frontier-skipped pull)",
+                                bytes_sweep(n, m, 1), *prof[cf1],
                                 traffic_from_profile("step_kernel_1_family_rmat20_traffic")),
-           "roofline_batched": roofline("step_kernel_64<family> (64-seed tile CPI step)", bytes_sweep(n, m, 64),
+           "roofline_step4": roofline("step_kernel_1<family, last> (single-seed CPI step 4 with the combine)",
+                                      bytes_sweep(n, m, 1), *prof[cf1l]),
+           "roofline_batched": roofline("step_kernel_64<family> (64-seed tile CPI step 3)", bytes_sweep(n, m, 64),
                                         *prof[cf64], traffic_from_profile("step_kernel_64_family_rmat20_traffic")),
+           "roofline_batched_last": roofline("step_kernel_64<family, last> (64-seed tile CPI step 4 with the "
+                                             "combine)", bytes_sweep(n, m, 64), *prof[cf64l]),
+           "kernels_per_query": {"plain": breakdown(prof, plain_codes), "batched_per_tile": breakdown(prof, batch_codes)},
            "roofline_preprocess": roofline("step_kernel_1<stranger> (preprocessing CPI step)",
                                            bytes_stranger(n, m, K, T_STR), *prof[cs],
                                            traffic_from_profile("step_kernel_1_stranger_rmat20_traffic")),
@@ -455,7 +495,10 @@ def rmat22(tpa, torch, np, ti, args) -> dict:
     torch.cuda.synchronize()
     ms = time_ms(torch, qg.launch, reps=5, stat="median")
     code = tpa.profile_code(tile, 0, False, False)
-    prof = profiled(tpa, torch, lambda: g.query(sd, C_RESTART, S_FAM, T_STR, out=out), [code])
+    batch_codes = {"tile_plan": CODE_TILE_PLAN, "tile_push_step_2": CODE_TILE_PUSH,
+                   "tile_convert_step_2": CODE_TILE_CONVERT, "step_3_pull": code,
+                   "step_4_pull_and_combine": tpa.profile_code(tile, 0, False, False, last=True)}
+    prof = profiled(tpa, torch, lambda: g.query(sd, C_RESTART, S_FAM, T_STR, out=out), list(batch_codes.values()))
     qg.close()
     me = mass_expected(K)
     mass_err = float((out.double().sum(1) - me).abs().max().item())
@@ -483,9 +526,10 @@ def rmat22(tpa, torch, np, ti, args) -> dict:
            "gteps": {"batched": round(1024 * (S_FAM - 1) * m / (ms * 1e-3) / 1e9, 1),
                      "plain": round(64 * (S_FAM - 1) * m / (ms1 * 1e-3) / 1e9, 1),
                      "preprocess": round(K * m / (pre_ms * 1e-3) / 1e9, 1)},
-           "roofline_batched": roofline(f"step_kernel tile {tile} <family> ({tile}-seed tile CPI step)",
+           "roofline_batched": roofline(f"step_kernel tile {tile} <family> ({tile}-seed tile CPI step 3)",
                                         bytes_sweep(n, m, tile), *prof[code],
                                         traffic_from_profile(f"step_kernel_{tile}_family_rmat22_traffic")),
+           "kernels_per_tile": breakdown(prof, batch_codes),
            "roofline_plain": roofline("step_kernel_1<family> (single-seed CPI step)", bytes_sweep(n, m, 1),
                                       *prof1[cf1]),
            "checks": {"mass_max_err": mass_err, "plain_vs_batched_l1_max": diff}}

@@ -466,10 +466,17 @@ tpa_status tpa_row_l1(const float *x, const float *y, int64_t rows, int64_t n, d
  * (mode 0 = online family step, 1 = preprocessing stranger step, 2 =
  * plain step keeping its iterate, 3 = adjoint step; first = the gather-free
  * first step from one-hot seeds, or for mode 3 = with the edge gradient;
- * weighted = explicit edge weights); codes 120 and 121 are the gated
- * launch of a single seed's second family step, which converts the pushed
- * sums or pulls (uniform, explicit weights), 124 the launch that pushes a
- * single seed's first two steps, and 127 the long-row finish pass.  tpa_profile_read synchronises the
+ * weighted = explicit edge weights), except the last family step of a
+ * single seed and of seed tiles of 16 and 64, which is 112 + 2*t +
+ * weighted (t = 0, 1, 2 for kt = 1, 16, 64), and a pull launched under a
+ * device-side gate (a step the device may have pushed instead; its launch
+ * then does nothing), which is 118 + weighted; codes 120 and 121 are the
+ * gated launch of a single seed's second family step, which converts the
+ * pushed sums or pulls (uniform, explicit weights), 122 a seed tile's push
+ * plan, 123 its push, 124 the launch that pushes a single seed's first two
+ * steps, 125 a pushed tile's conversion, 126 the frontier list and push of
+ * a single seed's third step, and 127 the long-row finish pass.
+ * tpa_profile_read synchronises the
  * recorded events, adds their durations into per-code totals and returns
  * them (launches timed, milliseconds).  tpa_profile_reset clears the
  * totals.  Errors: INVALID_ARG (capacity outside 1..2^20, sample_period

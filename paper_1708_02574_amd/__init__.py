@@ -160,8 +160,11 @@ def neighbor_scale(c: float, S: int, T: int) -> float:
     return v.value
 
 
-def profile_code(kt: int, mode: int, first: bool, weighted: bool) -> int:
-    """Variant code of a CPI step kernel for tpa_profile_read."""
+def profile_code(kt: int, mode: int, first: bool, weighted: bool, last: bool = False) -> int:
+    """Variant code of a CPI step kernel for tpa_profile_read (the last
+    family step of a single seed and of tiles of 16 and 64 has its own)."""
+    if last and mode == 0 and kt in (1, 16, 64):
+        return 112 + 2 * {1: 0, 16: 1, 64: 2}[kt] + int(weighted)
     return 16 * (int(kt).bit_length() - 1) + 4 * mode + 2 * int(first) + int(weighted)
 
 

@@ -623,9 +623,13 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
     if (hub) TPA_TRY(ensure_group_order(g, sf1, st));
-    // layout 2 on large graphs: lambda in rank order by in-degree (built
-    // before the adjoint's group-ordered ids, which are taken from a_colr then)
-    const bool lam_rank = g->gather_layout == 2 && g->n >= kLamRankMinN;
+    // layout 2 on large unpacked graphs: lambda in rank order by in-degree
+    // (built before the adjoint's group-ordered ids, which are taken from
+    // a_colr then).  A packed graph keeps node order: each block's lambda is
+    // a contiguous slice that its own pulls gather from, which a global rank
+    // order would scatter (256 packed R-MAT graphs of 14.4M nodes in all:
+    // 213 against 231 ms per adjoint).
+    const bool lam_rank = g->gather_layout == 2 && g->n >= kLamRankMinN && g->nblocks == 1;
     if (lam_rank) TPA_TRY(ensure_lam_layout(g, st));
     const bool lam_hub = lam_rank && g->a_colr;
     const int32_t *a_col = lam_hub ? g->a_colr : g->a.col;

@@ -707,8 +707,13 @@ __device__ __forceinline__ EpiPre epi_shfl(const EpiPre &q, int r) {
 
 constexpr int kShortRowKt = 32;  // rows up to this many edges take one sub-group
 
-template <int KT, int MODE, bool FIRST, bool WEIGHTED>
-__device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int64_t wid, int lane) {
+// STAGED (the last family step): a group item's outputs are kept in the
+// wave's LDS slice, [row][KT] with row stride KT + 1, and written column by
+// column, each column's run of the item's rows with one coalesced store,
+// instead of KT scattered 4-byte stores per row (seed-major output).
+template <int KT, int MODE, bool FIRST, bool WEIGHTED, bool STAGED = false>
+__device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int64_t wid, int lane,
+                                        float *buf = nullptr) {
     constexpr int SUBS = 64 / KT;
     const int j = lane % KT, sub = lane / KT;
     const int kind = (int)item_kind(it.meta);
@@ -729,7 +734,11 @@ __device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int6
             const EpiPre qr = epi_shfl(q, r);
             if (mine) {
                 const float s = row_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0 + b, it.e0 + en, j);
-                epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
+                if (STAGED) {
+                    if (j < p.ncols) buf[r * (KT + 1) + j] = family_out_value(p, it.row0 + r, j, s, qr, seed_pre);
+                } else {
+                    epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
+                }
             }
         }
         // longer rows: the whole wave, sub-groups striding over the edges
@@ -740,7 +749,19 @@ __device__ __forceinline__ void item_kt(const StepParams &p, const Item it, int6
             const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel, r + 1);
             const EpiPre qr = epi_readlane(q, r);
             const float s = range_sum_kt<KT, FIRST, WEIGHTED>(p, it.e0 + b, it.e0 + en, sub, j);
-            if (sub == 0) epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
+            if (sub == 0) {
+                if (STAGED) {
+                    if (j < p.ncols) buf[r * (KT + 1) + j] = family_out_value(p, it.row0 + r, j, s, qr, seed_pre);
+                } else {
+                    epi_store<MODE>(p, it.row0 + r, j, s, qr, seed_pre);
+                }
+            }
+        }
+        if (STAGED) {
+            wave_sync();
+            for (int jj = 0; jj < p.ncols; ++jj)
+                if (lane < nrows) p.out[(p.out_col0 + jj) * p.n + it.row0 + lane] = buf[lane * (KT + 1) + jj];
+            wave_sync();  // the slice is reused by the wave's next item
         }
         return;
     }
@@ -762,6 +783,18 @@ __global__ __launch_bounds__(kThreads) void step_kernel_kt(const Item *__restric
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
     if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
     item_kt<KT, MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane);
+}
+
+// The last family step of a tile of KT columns, its outputs staged per item
+// (a group item holds at most 63 rows).
+template <int KT, bool FIRST, bool WEIGHTED>
+__global__ __launch_bounds__(kThreads) void last_step_kernel_kt(const Item *__restrict__ items, int64_t n_items,
+                                                                StepParams p) {
+    __shared__ float stage[kWaves][64 * (KT + 1)];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
+    item_kt<KT, kFamily, FIRST, WEIGHTED, true>(p, items[wid], wid, lane, stage[wv]);
 }
 
 __global__ void stranger_init_kernel(int64_t n, float c, const float *restart_pr, float inv_n,
@@ -1390,6 +1423,15 @@ inline unsigned grid_1d(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
 }
 
+// tiles of 2..32 columns: the last family step stages its outputs
+#define KT_LAUNCH(K)                                                                                   \
+    do {                                                                                               \
+        if (MODE == kFamily && p.last)                                                                 \
+            last_step_kernel_kt<K, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p);             \
+        else                                                                                           \
+            step_kernel_kt<K, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p);            \
+    } while (0)
+
 template <int MODE, bool FIRST, bool WEIGHTED>
 void launch_kt(const Schedule &s, const StepParams &p, hipStream_t st) {
     const unsigned grid = blocks_for(s.n_items);
@@ -1397,11 +1439,11 @@ void launch_kt(const Schedule &s, const StepParams &p, hipStream_t st) {
     const int64_t ni = s.n_items;
     switch (p.kt) {
         case 1: step_kernel_1<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
-        case 2: step_kernel_kt<2, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
-        case 4: step_kernel_kt<4, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
-        case 8: step_kernel_kt<8, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
-        case 16: step_kernel_kt<16, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
-        case 32: step_kernel_kt<32, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 2: KT_LAUNCH(2); break;
+        case 4: KT_LAUNCH(4); break;
+        case 8: KT_LAUNCH(8); break;
+        case 16: KT_LAUNCH(16); break;
+        case 32: KT_LAUNCH(32); break;
         case 64: step_kernel_64<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
         default: break;
     }
@@ -1443,7 +1485,15 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (s.n_items > 0) {
         int lg = 0;
         while ((1 << lg) < p.kt) ++lg;
-        const int slot = profile_begin(16 * lg + 4 * mode + 2 * (first ? 1 : 0) + (p.w ? 1 : 0), st);
+        // the last family step of a single seed and of tiles of 16 and 64 has its own code
+        const bool last_code = mode == kFamily && p.last && (p.kt == 1 || p.kt == 16 || p.kt == 64);
+        // and a pull launched under a device-side gate (empty when the device
+        // pushed that step) has one shared code, so that the others time
+        // only steps that ran
+        const int code = p.skip_on ? 118 + (p.w ? 1 : 0)
+                         : last_code ? 112 + 2 * (p.kt == 1 ? 0 : p.kt == 16 ? 1 : 2) + (p.w ? 1 : 0)
+                                     : 16 * lg + 4 * mode + 2 * (first ? 1 : 0) + (p.w ? 1 : 0);
+        const int slot = profile_begin(code, st);
         if (mode == kFamily) {
             if (first) launch_w<kFamily, true>(s, p, st);
             else launch_w<kFamily, false>(s, p, st);

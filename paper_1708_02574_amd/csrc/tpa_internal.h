@@ -165,7 +165,7 @@ struct tpa_graph {
     bool t_wz_valid = false;
     int gather_layout = 2;                  // 2 = hub-first order, group items in gather
                                             // order; 1 = hub-first order; 0 = node order
-    // adjoint gather layout (layout 2, n >= kLamRankMinN): the adjoint's
+    // adjoint gather layout (layout 2, n >= kLamRankMinN, unpacked): the adjoint's
     // lambda vectors keep node v's entry at row lrank[v], the rank of v by
     // descending in-degree (ties by id), so the entries a pull over A~
     // gathers most share cache lines; a_colr holds lrank[a.col] in A~'s own
