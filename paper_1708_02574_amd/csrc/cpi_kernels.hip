@@ -533,8 +533,32 @@ __device__ __forceinline__ void stage_write(const StepParams &p, const float *bu
     wave_sync();
 }
 
-template <int MODE, bool FIRST, bool WEIGHTED>
-__device__ __forceinline__ void item_64(const StepParams &p, const Item it, int64_t wid, int lane, float *buf) {
+// SPARSE: the launch's frontier skip is on (a gather per live row only); the
+// dense walk is compiled without the per-edge test.  The item's fields are
+// wave-uniform and kept in scalar registers, so its loop bounds and row
+// boundaries cost scalar compares only.
+// One batch of U row gathers of a 64-edge strip (column ids colv; lane j
+// takes column j of each edge's row).  SPARSE zeroes, and does not load,
+// the rows the frontier bitmap marks dead.
+template <bool FIRST, bool WEIGHTED, bool SPARSE, int U>
+__device__ __forceinline__ void gather_batch(const StepParams &p, int32_t colv, float wv, uint64_t live, int t0,
+                                             int lane, int32_t seed_plain, float cinv_plain, float (&v)[U]) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
+        const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
+        v[k] = (!SPARSE || ((live >> (t0 + k)) & 1ull)) ? walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain)
+                                                        : 0.0f;
+    }
+}
+
+template <int MODE, bool FIRST, bool WEIGHTED, bool SPARSE>
+__device__ __forceinline__ void item_64(const StepParams &p, const Item it0, int64_t wid, int lane, float *buf) {
+    Item it;
+    it.e0 = ((int64_t)__builtin_amdgcn_readfirstlane((int32_t)(it0.e0 >> 32)) << 32) |
+            (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)it0.e0);
+    it.row0 = __builtin_amdgcn_readfirstlane(it0.row0);
+    it.meta = __builtin_amdgcn_readfirstlane(it0.meta);
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     int32_t seed_plain = -1;
@@ -544,7 +568,7 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         if (!WEIGHTED && seed_plain >= 0 && (int64_t)seed_plain < p.n) cinv_plain = p.c * p.inv[seed_plain];
     }
     constexpr int U = 32;  // row gathers in flight per wave
-    const bool sparse = !FIRST && frontier_on(p);
+    constexpr bool sparse = SPARSE && !FIRST;
     // the epilogue's per-row operands are loaded ahead, one row per lane, and
     // each lane's seed once: no memory round trip at a row boundary
     const int32_t seed_pre = MODE == kFamily ? seed_ahead(p, lane) : kSeedLookup;
@@ -562,18 +586,16 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
             const int32_t colv = lane < cnt ? p.col[it.e0 + base + lane] : 0;
             const float wv = (WEIGHTED && lane < cnt) ? p.w[it.e0 + base + lane] : 0.0f;
             const uint64_t live = sparse ? __ballot(lane < cnt && row_live(p, colv)) : ~0ull;
+            // one copy of the row-closing code per edge of a batch (unrolling
+            // the strip's two batches as well doubled the kernel's code and
+            // slowed it)
             for (int t0 = 0; t0 < cnt; t0 += U) {
                 float v[U];
-#pragma unroll
-                for (int k = 0; k < U; ++k) {
-                    const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
-                    const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
-                    v[k] = ((live >> (t0 + k)) & 1ull) ? walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain)
-                                                       : 0.0f;
-                }
+                gather_batch<FIRST, WEIGHTED, sparse, U>(p, colv, wv, live, t0, lane, seed_plain, cinv_plain, v);
 #pragma unroll
                 for (int k = 0; k < U; ++k) {
                     if (t0 + k < cnt) {
+                        // close every row that ends before this edge, then add its value
                         const int e = base + t0 + k;
                         while (e >= rend) {
                             const EpiPre qr = epi_readlane(q, r);
@@ -621,13 +643,7 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
         const uint64_t live = sparse ? __ballot(lane < cnt && row_live(p, colv)) : ~0ull;
         for (int t0 = 0; t0 < cnt; t0 += U) {
             float v[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int32_t u = __builtin_amdgcn_readlane(colv, t0 + k);
-                const float w = WEIGHTED ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wv), t0 + k)) : 0.0f;
-                v[k] = ((live >> (t0 + k)) & 1ull) ? walk_value<FIRST, WEIGHTED>(p, u, w, lane, seed_plain, cinv_plain)
-                                                   : 0.0f;
-            }
+            gather_batch<FIRST, WEIGHTED, sparse, U>(p, colv, wv, live, t0, lane, seed_plain, cinv_plain, v);
 #pragma unroll
             for (int k = 0; k < U; ++k)
                 if (t0 + k < cnt) s += v[k];
@@ -642,14 +658,24 @@ __device__ __forceinline__ void item_64(const StepParams &p, const Item it, int6
 // 7 resident blocks per CU (at most 72 VGPRs): the walk is bound by the
 // latency of its gather batches, and a seventh wave per SIMD beats the
 // registers it costs (24.0 against 25.1 ms for 1024 seeds on rmat20).
-template <int MODE, bool FIRST, bool WEIGHTED>
+// WALK: 0 = the frontier skip decided per launch on the device (bits_on),
+// 1 = sparse (skip on), 2 = dense.  The host picks it, so that each variant
+// gets its own registers: one kernel holding both walks spilled, and the
+// dense walk without the per-edge frontier test is 12 % faster (64-seed tile
+// on 2^20 nodes: 511 to 450 us per step).
+template <int MODE, bool FIRST, bool WEIGHTED, int WALK>
 __global__ __launch_bounds__(kThreads, 7) void step_kernel_64(const Item *__restrict__ items, int64_t n_items,
                                                            StepParams p) {
     __shared__ float stage[kWaves][kStageRows * kStageStride];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
     if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
-    item_64<MODE, FIRST, WEIGHTED>(p, items[wid], wid, lane, stage[wv]);
+    if (WALK == 0) {
+        if (!FIRST && frontier_on(p)) item_64<MODE, FIRST, WEIGHTED, true>(p, items[wid], wid, lane, stage[wv]);
+        else item_64<MODE, FIRST, WEIGHTED, false>(p, items[wid], wid, lane, stage[wv]);
+    } else {
+        item_64<MODE, FIRST, WEIGHTED, WALK == 1>(p, items[wid], wid, lane, stage[wv]);
+    }
 }
 
 // ------------------------------------------------------------ kt = 2..32
@@ -1444,7 +1470,13 @@ void launch_kt(const Schedule &s, const StepParams &p, hipStream_t st) {
         case 8: KT_LAUNCH(8); break;
         case 16: KT_LAUNCH(16); break;
         case 32: KT_LAUNCH(32); break;
-        case 64: step_kernel_64<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 64: {
+            const int walk = FIRST ? 2 : p.bits ? (p.bits_on ? 0 : 1) : 2;
+            if (walk == 0) step_kernel_64<MODE, FIRST, WEIGHTED, 0><<<grid, kThreads, 0, st>>>(it, ni, p);
+            else if (walk == 1) step_kernel_64<MODE, FIRST, WEIGHTED, 1><<<grid, kThreads, 0, st>>>(it, ni, p);
+            else step_kernel_64<MODE, FIRST, WEIGHTED, 2><<<grid, kThreads, 0, st>>>(it, ni, p);
+            break;
+        }
         default: break;
     }
 }
