@@ -258,9 +258,42 @@ __device__ __forceinline__ float adj_range_kt(const AdjParams &p, int64_t row, i
     return s;
 }
 
+// One short row by one sub-group of KT lanes (lane j = column j): its edges
+// in order, 4 gathers of lambda(i) rows in flight; each edge's gradient term
+// is reduced over the sub-group's lanes alone (xor offsets below KT, all in
+// the sub-group, which runs the row's trip count as a whole).
+constexpr int kShortRowAdjKt = 32;  // rows up to this many edges take one sub-group
+
+template <int KT, bool WEIGHTED, bool WITHG>
+__device__ __forceinline__ float adj_row_kt(const AdjParams &p, int64_t row, int64_t e0, int64_t e1, int j) {
+    constexpr int UNR = 4;
+    const float xr = WITHG ? p.omc * p.xprev[row * KT + j] : 0.0f;
+    float s = 0.0f;
+    for (int64_t base = e0; base < e1; base += UNR) {
+        int32_t v[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) v[k] = base + k < e1 ? p.col[base + k] : -1;
+        float l[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) l[k] = v[k] >= 0 ? p.lam_in[(int64_t)v[k] * KT + j] : 0.0f;
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            if (WITHG) {
+                float d = xr * l[k];
+#pragma unroll
+                for (int off = 1; off < KT; off <<= 1) d += __shfl_xor(d, off, 64);
+                if (v[k] >= 0 && j == 0) p.G[base + k] += d;
+            }
+            if (v[k] >= 0) s += WEIGHTED ? p.w[base + k] * l[k] : l[k];
+        }
+    }
+    return s;
+}
+
 template <int KT, bool WEIGHTED, bool WITHG>
 __global__ __launch_bounds__(kThreads) void adj_kernel_kt(const Item *__restrict__ items, int64_t n_items,
                                                           AdjParams p) {
+    constexpr int SUBS = 64 / KT;
     const int lane = threadIdx.x & 63;
     const int j = lane % KT, sub = lane / KT;
     const int64_t wid = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
@@ -269,10 +302,28 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_kt(const Item *__restrict
     const int kind = (int)item_kind(it.meta);
     const int nnz = (int)item_nnz(it.meta);
     if (kind == (int)kItemGroup) {
+        // short rows: SUBS rows at a time, one per sub-group; longer rows:
+        // the whole wave, sub-groups striding over the edges.  (A row at a
+        // time for the whole wave left most lanes idle on rows of a few edges
+        // and serialised the rows' gathers.)
         const int nrows = (int)item_nrows(it.meta);
-        for (int r = 0; r < nrows; ++r) {
+        const int rel = lane <= nrows ? (int)(p.rowptr[it.row0 + lane] - it.e0) : nnz;
+        const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
+        for (int rb = 0; rb < nrows; rb += SUBS) {
+            const int r = min(rb + sub, 63);
+            const int b = __shfl(rel, r, 64), en = __shfl(rel_next, r, 64);
+            if (rb + sub < nrows && en - b <= kShortRowAdjKt) {
+                const float s = adj_row_kt<KT, WEIGHTED, WITHG>(p, it.row0 + r, it.e0 + b, it.e0 + en, j);
+                adj_epilogue(p, it.row0 + r, j, s);
+            }
+        }
+        uint64_t big = __ballot(lane < nrows && rel_next - rel > kShortRowAdjKt);
+        while (big) {
+            const int r = __builtin_ctzll(big);
+            big &= big - 1;
+            const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel, r + 1);
             const int64_t row = it.row0 + r;
-            const float s = adj_range_kt<KT, WEIGHTED, WITHG>(p, row, p.rowptr[row], p.rowptr[row + 1], sub, j);
+            const float s = adj_range_kt<KT, WEIGHTED, WITHG>(p, row, it.e0 + b, it.e0 + en, sub, j);
             if (sub == 0) adj_epilogue(p, row, j, s);
         }
         return;
