@@ -1449,10 +1449,12 @@ inline unsigned grid_1d(int64_t n) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 20));
 }
 
-// tiles of 2..32 columns: the last family step stages its outputs
+// tiles of 2..16 columns: the last family step stages its outputs (a
+// 32-column stage takes 34 KB of LDS per block, and the occupancy it costs
+// made that step slower than the unstaged one)
 #define KT_LAUNCH(K)                                                                                   \
     do {                                                                                               \
-        if (MODE == kFamily && p.last)                                                                 \
+        if (MODE == kFamily && p.last && (K) <= 16)                                                    \
             last_step_kernel_kt<K, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p);             \
         else                                                                                           \
             step_kernel_kt<K, MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p);            \
