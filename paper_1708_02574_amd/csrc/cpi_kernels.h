@@ -93,6 +93,11 @@ struct PushPlan {
     int64_t qmax3 = 0;
     int64_t wmax3 = 0;                  // 0: step 3 is always pulled
     int32_t *flag3 = nullptr;
+    // 1: step 3 was pushed and y3's support is small (W3 <= n/16, and each
+    // row of the support takes at least one of those edges), so step 4
+    // skips the gathers of the rows the bitmap marks zero; with a larger
+    // support the per-edge bitmap reads cost more than the gathers saved
+    int32_t *flag4 = nullptr;
 };
 
 // Bytes of the push state (kept at the front of the query workspace), and

@@ -244,6 +244,43 @@ __device__ __forceinline__ bool push_convert_row(const StepParams &p, const Push
     return a != 0ull;
 }
 
+// Rows [base, base + 256) of acc (2^62 fixed point) into the gathered
+// vector p.zout, acc cleared, and the span's eight words of the frontier
+// bitmap (rows past n left clear).  One wave: lane i converts rows 4i..4i+3
+// (two 16-byte loads, one 16-byte store where aligned), and lanes 0..7 write
+// word w from the 4 row bits of lanes 8w..8w+7.
+__device__ __forceinline__ void convert_span(const StepParams &p, const PushPlan &pp, int64_t base, int lane,
+                                             bool vec) {
+    const int64_t r0 = base + 4 * lane;
+    uint32_t live4 = 0u;  // bit k: row r0 + k is non-zero
+    if (vec && r0 + 3 < p.n) {
+        ulonglong2 *a = reinterpret_cast<ulonglong2 *>(pp.acc + r0);
+        const ulonglong2 lo = a[0], hi = a[1];
+        *reinterpret_cast<float4 *>(p.zout + r0) =
+            make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
+                        (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
+        if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
+        if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
+        live4 = (lo.x != 0ull ? 1u : 0u) | (lo.y != 0ull ? 2u : 0u) | (hi.x != 0ull ? 4u : 0u) |
+                (hi.y != 0ull ? 8u : 0u);
+    } else {
+        for (int k = 0; k < 4; ++k)
+            if (r0 + k < p.n && push_convert_row(p, pp, r0 + k)) live4 |= 1u << k;
+    }
+    uint64_t b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = __ballot((live4 >> k) & 1u);
+    if (lane < 8) {
+        uint32_t word = 0u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) word |= (uint32_t)((b[k] >> (8 * lane + j)) & 1ull) << (4 * j + k);
+        const int64_t w = (base >> 5) + lane;
+        if (w < pp.nwords) pp.bits[w] = word;
+    }
+}
+
 // ------------------------------------------------------------ kt == 1
 template <int MODE, bool FIRST, bool WEIGHTED>
 __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64_t wid, int lane, float *my) {
@@ -421,44 +458,12 @@ __global__ __launch_bounds__(kThreads) void gated_step_kernel_1(const Item *__re
     __shared__ float lds[kWaves][kGroupMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (*pp.flag) {
-        // pushed: convert every gather row, coalesced, no work items.  A wave
-        // takes 256-row spans: lane i converts rows 4i..4i+3 (two 16-byte
-        // loads, one 16-byte store), and lanes 0..7 write the span's eight
-        // words of the frontier bitmap, word w from the 4 bits of lanes
-        // 8w..8w+7 (rows past n are left clear).
+        // pushed: convert every gather row, coalesced, no work items
         const bool vec = (reinterpret_cast<uintptr_t>(p.zout) & 15) == 0;
         const int64_t first = ((int64_t)blockIdx.x * kWaves + wv) * 256;
         const int64_t step = (int64_t)gridDim.x * kWaves * 256;
-        for (int64_t base = first; base < p.n; base += step) {  // wave-uniform trip count
-            const int64_t r0 = base + 4 * lane;
-            uint32_t live4 = 0u;  // bit k: row r0 + k is non-zero
-            if (vec && r0 + 3 < p.n) {
-                ulonglong2 *a = reinterpret_cast<ulonglong2 *>(pp.acc + r0);
-                const ulonglong2 lo = a[0], hi = a[1];
-                *reinterpret_cast<float4 *>(p.zout + r0) =
-                    make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
-                                (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
-                if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
-                if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
-                live4 = (lo.x != 0ull ? 1u : 0u) | (lo.y != 0ull ? 2u : 0u) | (hi.x != 0ull ? 4u : 0u) |
-                        (hi.y != 0ull ? 8u : 0u);
-            } else {
-                for (int k = 0; k < 4; ++k)
-                    if (r0 + k < p.n && push_convert_row(p, pp, r0 + k)) live4 |= 1u << k;
-            }
-            uint64_t b[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) b[k] = __ballot((live4 >> k) & 1u);
-            if (lane < 8) {
-                uint32_t word = 0u;
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) word |= (uint32_t)((b[k] >> (8 * lane + j)) & 1ull) << (4 * j + k);
-                const int64_t w = (base >> 5) + lane;
-                if (w < pp.nwords) pp.bits[w] = word;
-            }
-        }
+        for (int64_t base = first; base < p.n; base += step)  // wave-uniform trip count
+            convert_span(p, pp, base, lane, vec);
         return;
     }
     const int64_t slots = (n_items + kWaves - 1) / kWaves;
@@ -1046,6 +1051,7 @@ __global__ __launch_bounds__(256) void push_steps12_kernel(StepParams p, const i
         pp.ctrl[2] = 0;  // the third step's frontier list starts empty
         pp.ctrl[3] = 0;
         *pp.flag3 = 0;
+        *pp.flag4 = 0;
         *pp.flag = push ? 1 : 0;
         // the restart term of y2 (other blocks may already be adding to the row)
         if (push) atomicAdd(&pp.acc[zrow(p, s)], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
@@ -1195,6 +1201,7 @@ __global__ __launch_bounds__(256) void push_third_kernel(StepParams p, PushPlan 
         const int32_t s = p.seeds[0];
         atomicAdd(&pp.acc[zrow(p, s)], to_fixed62(a_w ? p.c : p.c * p.inv[s]));
         *pp.flag3 = 1;
+        *pp.flag4 = pp.ctrl[2] <= p.n / 16 ? 1 : 0;
     }
     const int64_t nq = pp.ctrl[3];
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1212,31 +1219,18 @@ __global__ __launch_bounds__(256) void push_third_kernel(StepParams p, PushPlan 
     }
 }
 
-// y3 from acc as the next gathered vector, every row (acc cleared).
-// Nothing unless step 3 was pushed (flag3 is cleared by the next query's
-// first launch).
+// y3 from acc as the next gathered vector, every row (acc cleared), and the
+// rows of its support in the frontier bitmap.  Nothing unless step 3 was
+// pushed (flag3 is cleared by the next query's first launch).
 __global__ __launch_bounds__(256) void convert_third_kernel(StepParams p, PushPlan pp) {
     if (!*pp.flag3) return;
-    // four rows per thread (two 16-byte loads, one 16-byte store) where aligned
+    // y3's support into the frontier bitmap as well, for step 4's skip
+    const int lane = threadIdx.x & 63;
     const bool vec = (reinterpret_cast<uintptr_t>(p.zout) & 15) == 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-    for (int64_t r0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; r0 < p.n; r0 += stride) {
-        if (vec && r0 + 3 < p.n) {
-            ulonglong2 *a = reinterpret_cast<ulonglong2 *>(pp.acc + r0);
-            const ulonglong2 lo = a[0], hi = a[1];
-            *reinterpret_cast<float4 *>(p.zout + r0) =
-                make_float4((float)((double)lo.x * 0x1p-62), (float)((double)lo.y * 0x1p-62),
-                            (float)((double)hi.x * 0x1p-62), (float)((double)hi.y * 0x1p-62));
-            if (lo.x | lo.y) a[0] = make_ulonglong2(0ull, 0ull);
-            if (hi.x | hi.y) a[1] = make_ulonglong2(0ull, 0ull);
-        } else {
-            for (int64_t r = r0; r < r0 + 4 && r < p.n; ++r) {
-                const unsigned long long a = pp.acc[r];
-                p.zout[r] = (float)((double)a * 0x1p-62);
-                if (a) pp.acc[r] = 0ull;
-            }
-        }
-    }
+    const int64_t first = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 256;
+    const int64_t step = (((int64_t)gridDim.x * blockDim.x) >> 6) * 256;
+    for (int64_t base = first; base < p.n; base += step)  // wave-uniform trip count
+        convert_span(p, pp, base, lane, vec);
 }
 
 // ------------------------------------------------------------ pushed tiles
@@ -1667,6 +1661,7 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wm
     pp.ctrl = reinterpret_cast<int64_t *>(b + a);
     pp.flag = reinterpret_cast<int32_t *>(b + a + 64);
     pp.flag3 = reinterpret_cast<int32_t *>(b + a + 68);
+    pp.flag4 = reinterpret_cast<int32_t *>(b + a + 72);
     pp.bits = reinterpret_cast<uint32_t *>(b + a + 256);
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
@@ -1789,7 +1784,8 @@ tpa_status launch_push_third(const StepParams &p, const tpa_graph *g, const Push
 }
 
 tpa_status launch_convert_third(const StepParams &p, const PushPlan &pp, hipStream_t st) {
-    convert_third_kernel<<<(unsigned)std::min<int64_t>((p.n + 1023) / 1024, 2048), 256, 0, st>>>(p, pp);
+    // a wave per 256-row span, at most 2048 blocks striding
+    convert_third_kernel<<<(unsigned)std::max<int64_t>(1, std::min<int64_t>((p.n + 1023) / 1024, 2048)), 256, 0, st>>>(p, pp);
     TPA_TRY_HIP(hipGetLastError());
     return TPA_OK;
 }

@@ -400,6 +400,12 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                 p.bits = pp.bits;
                 p.bits_on = push2 ? pp.flag : nullptr;
             }
+            // and step 4 after a pushed step 3 with a small support (its
+            // conversion wrote that support into the bitmap)
+            if (push3 && step == 4) {
+                p.bits = pp.bits;
+                p.bits_on = pp.flag4;
+            }
             // one-hot restart: the first step needs no gather
             const bool first = step == 1 && !q;
             p.col = first ? g->t.col : col_gather;
