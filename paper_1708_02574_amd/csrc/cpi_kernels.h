@@ -100,11 +100,13 @@ struct PushPlan {
     int32_t *flag4 = nullptr;
 };
 
-// Bytes of the push state (kept at the front of the query workspace), and
-// of its leading part that must be zero before the first query (acc, ctrl,
-// flags, bits; the pieces need no clearing).
-size_t push_plan_bytes(int64_t n, int64_t m);
+// Bytes of the push state (kept at the front of the query workspace; the
+// third step's pieces only when that step may be pushed), and of its leading
+// part that must be zero before the first query (acc, ctrl, flags, bits; the
+// pieces need no clearing).
+size_t push_plan_bytes(int64_t n, int64_t m, bool third);
 size_t push_plan_clear_bytes(int64_t n);
+// wmax3 > 0 requires the pieces (push_plan_bytes with third).
 PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wmax3);
 
 // Device state of the pushed first two family steps of a seed tile (kt >= 2,

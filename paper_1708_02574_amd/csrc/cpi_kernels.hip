@@ -1649,8 +1649,8 @@ size_t push_plan_clear_bytes(int64_t n) {
     return a + 256 + bits_bytes(n);
 }
 
-size_t push_plan_bytes(int64_t n, int64_t m) {
-    return push_plan_clear_bytes(n) + (((size_t)third_qmax(n, m) * 8 + 255) & ~(size_t)255);
+size_t push_plan_bytes(int64_t n, int64_t m, bool third) {
+    return push_plan_clear_bytes(n) + (third ? (((size_t)third_qmax(n, m) * 8 + 255) & ~(size_t)255) : 0);
 }
 
 PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wmax3) {
@@ -1666,7 +1666,7 @@ PushPlan push_plan_at(void *base, int64_t n, int64_t m, int64_t wmax, int64_t wm
     pp.nwords = (n + 31) / 32;
     pp.wmax = wmax;
     pp.pieces3 = reinterpret_cast<int64_t *>(b + push_plan_clear_bytes(n));
-    pp.qmax3 = third_qmax(n, m);
+    pp.qmax3 = wmax3 > 0 ? third_qmax(n, m) : 0;
     pp.wmax3 = wmax3;
     return pp;
 }

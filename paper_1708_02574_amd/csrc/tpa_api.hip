@@ -145,7 +145,8 @@ size_t query_ws_floats_before_qt(const tpa_graph *g, const Schedule *s, int kt) 
 
 size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, bool dense) {
     const size_t qf = dense ? (size_t)g->n * kt : 0;
-    return push_plan_bytes(g->n, g->m) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) + 256;
+    return push_plan_bytes(g->n, g->m, third_wmax(g) > 0) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) +
+           256;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -271,7 +272,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
         ws = g->ws;
     }
     const PushPlan pp = push_plan_at(ws, g->n, g->m, push_wmax(g), third_wmax(g));
-    float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->m));
+    float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->m, pp.wmax3 > 0));
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
     float *qT = z0 + query_ws_floats_before_qt(g, s, kt);  // used by dense restarts only

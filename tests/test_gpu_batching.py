@@ -65,6 +65,37 @@ def test_captured_query_replays(rmat13, torch, k, kt):
         gg.set_tuning(0, 0)
 
 
+def test_captured_query_with_pushed_steps(rmat13, torch):
+    """A captured single-seed query whose third step may be pushed (limit
+    forced on this small graph) and a captured 16-seed tile whose second
+    step may be pushed: replays with new seeds, eager work in between, equal
+    bit for bit to eager queries, whichever direction the device takes."""
+    og, gg = rmat13
+    eligible = og.export()["padded"] == 0
+    gg.set_push_limit(og.m)
+    gg.set_third_push_limit(og.m)
+    try:
+        for k in (1, 16):
+            seeds_buf = torch.from_numpy(ti.draw_seeds(eligible, k, 300 + k)).cuda()
+            out = torch.empty((k, gg.n), dtype=torch.float32, device="cuda")
+            qg = gg.capture_query(c, S, T, out, seeds=seeds_buf)
+            for rep in range(3):
+                new = torch.from_numpy(ti.draw_seeds(eligible, k, 400 + 10 * k + rep)).cuda()
+                seeds_buf.copy_(new)
+                qg.launch()
+                torch.cuda.synchronize()
+                scratch = torch.randn(1000, device="cuda").sum()
+                torch.cuda.synchronize()
+                eager = gg.query(new, c, S, T)
+                torch.cuda.synchronize()
+                assert torch.equal(out, eager), (k, rep)
+                assert float(scratch) == float(scratch)
+            qg.close()
+    finally:
+        gg.set_third_push_limit(-1)
+        gg.set_push_limit(-1)
+
+
 def test_captured_dense_and_packed(tpa, torch):
     params = [(9, 4000, 1, 400), (10, 9000, 2, 0)]
     ggs = []

@@ -553,6 +553,27 @@ def test_tile_second_step_push_weighted(tpa, torch, kt):
     assert (runs[4 * og.m] - runs[0]).abs().max().item() <= 1e-6
 
 
+@pytest.mark.parametrize("kt", [4, 64])
+def test_tile_push_with_invalid_seeds(rmat13, tpa, torch, kt):
+    """A tile whose columns include out-of-range seeds: the plan gives those
+    columns no entries, their rows come out NaN with the sticky error raised,
+    and every valid column matches the oracle whether step 2 is pushed or
+    pulled."""
+    og, gg = rmat13
+    sd = seeds_for(og, 10, 808).astype(np.int32)
+    sd[2], sd[7] = -1, og.n  # invalid
+    valid = [i for i in range(sd.size) if 0 <= sd[i] < og.n]
+    runs = tile_runs(gg, torch, torch.from_numpy(sd).cuda(), kt, S, (1 << 40, 0))
+    expect = np.stack([og.query(int(sd[i]), c, S, T) for i in valid])
+    for lim, r in runs.items():
+        r = r.cpu().numpy()
+        assert np.all(np.isnan(r[2])) and np.all(np.isnan(r[7])), lim
+        assert np.all(l1_rows(r[valid], expect) <= TOL), lim
+    with pytest.raises(tpa.TPAError):
+        gg.device_error()
+    gg.device_error()  # cleared
+
+
 def test_tile_push_plan_limit(tpa, torch):
     """The device plans a tile's push with one entry per frontier node, at
     most 16384: a tile of 64 seeds with 300 out-edges each (19264 entries)

@@ -105,3 +105,25 @@ def test_noalloc_error_paths(tpa, torch):
     r = big.query(one, c, S, T)[0]
     alpha = (1 - (1 - c) ** T) / (1 - (1 - c) ** S)
     assert abs(float(r[123]) - (alpha * (1 - (1 - c) ** S) + ((1 - c) ** T - (1 - c) ** 117) / big.n)) < 1e-6
+
+
+def test_noalloc_with_pushed_steps(tpa, torch):
+    """With the third step's push forced on a small graph (its frontier list
+    lives in the fixed array too) and a seed tile whose second step may be
+    pushed, tpa_query_noalloc still equals tpa_query bit for bit and the
+    oracle within L1 <= 1e-5, on consecutive calls."""
+    scale, samples, gseed = ti.GRAPHS["rmat13"]
+    og = oracle.Graph.rmat(scale, samples, gseed)
+    og.preprocess(c, T, EPS)
+    g = tpa.Graph.rmat(scale, samples, gseed)
+    g.preprocess(c, T)
+    g.set_push_limit(og.m)
+    g.set_third_push_limit(og.m)
+    try:
+        g.reserve(16)
+        seeds = ti.draw_seeds(og.export()["padded"] == 0, 16, 64)
+        for sd in (seeds[:1], seeds, seeds[3:4]):
+            check(tpa, torch, og, g, sd)
+    finally:
+        g.set_third_push_limit(-1)
+        g.set_push_limit(-1)
