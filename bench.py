@@ -54,8 +54,8 @@ def source_hash(path: str = KERNEL_SRC) -> str:
 
 
 # ---------------------------------------------------------------- byte models
-# Algorithmic bytes of one launch.  "model" is the survey's compulsory-traffic
-# model of a CPI sweep (per edge a 4-byte column id and a 4-byte weight, int64
+# Algorithmic bytes of one launch.  "model" is the compulsory-traffic model of
+# a CPI sweep (per edge a 4-byte column id and a 4-byte weight, int64
 # row offsets, every vector read and written once); "design" is what this
 # design must move at least (1/outdeg weights are folded into the gathered
 # vector, so no per-edge weight is read).
@@ -77,7 +77,7 @@ def bytes_stranger(n: int, m: int, K: int, T: int) -> dict:
 
 
 def bytes_adjoint(n: int, m: int, kt: int, with_grad: bool = True, weighted: bool = False) -> dict:
-    """One adjoint step (a pull over A~): the survey's model counts the
+    """One adjoint step (a pull over A~): the compulsory-traffic model counts the
     column ids, the weights and the edge gradient read and written (16m)
     and lambda plus the iterate (16 n kt) plus 8n; the design reads the
     column ids (and the weights when they are logits), the edge gradient
@@ -91,7 +91,7 @@ def bytes_adjoint(n: int, m: int, kt: int, with_grad: bool = True, weighted: boo
 def roofline(kernel: str, bytes_: dict, launches: int, total_ms: float, traffic=None) -> dict:
     us = total_ms * 1e3 / launches if launches else None
     rec = {"kernel": kernel, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "bytes_model": "survey compulsory-traffic model (8 B per edge, int64 row offsets, vectors once)",
+           "bytes_model": "compulsory-traffic model (8 B per edge, int64 row offsets, vectors once)",
            "algorithmic_bytes_per_launch": bytes_["model"],
            "design_bytes_per_launch": bytes_["design"],
            "avg_launch_us": round(us, 2) if us else None, "launches_timed": launches,
@@ -629,8 +629,8 @@ def main():
                     help="after timing, run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the seed and block axes would shard with no communication; see DESIGN.md).",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(seed tiles and the blocks of a packed batch would shard without communication).",
               file=sys.stderr)
         sys.exit(2)
     configs = [c.strip() for c in args.configs.split(",") if c.strip()]
