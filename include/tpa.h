@@ -392,6 +392,30 @@ tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
  * (layout not 0, 1 or 2), OOM, HIP. */
 tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first);
 tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
+
+/* XCD-sliced sweep of the stranger chain (Section 3.3's preprocessing CPI,
+ * Algorithm 2; the same chain recomputed by tpa_backward).  The chip deals
+ * the workgroups of a launch to its 8 XCDs in turn and each XCD caches in an
+ * L2 of its own, so a cache line gathered by blocks on several XCDs is
+ * fetched into each of their L2s.  In the sliced sweep every row of A~^T
+ * with more edges than a group item (512 by default) is summed as 8 runs,
+ * one per slice of the hub-first gather rows (rows below 8192 by row mod 8,
+ * the others by blocks of 1024 rows), and slice x's runs run on XCD x, so
+ * that each L2 holds its own eighth of the gathered vector; a finish pass
+ * adds each row's run sums in slice order.  It needs one more int32[m] copy
+ * of the hub-first column ids (each long row's edges stably partitioned by
+ * slice) and the work items, built at the first sweep that takes them
+ * (synchronous; when the copy takes at most a quarter of the free device
+ * memory, and never under stream capture).  Only graphs with 1/outdeg
+ * weights in the hub-first gather layout take it.  mode: 0 off, 1 (the
+ * default) from 2^23 nodes, 2 on every such graph.  The results agree with
+ * the unsliced sweep up to FP32 rounding (the long rows are added in
+ * another order).  tpa_get_sliced_sweep reports the mode and, in *active
+ * (may be NULL), whether the sliced schedule is built and in use for the
+ * graph's current work-item shape.  Errors: INVALID_ARG (mode not 0, 1 or
+ * 2, NULL handle). */
+tpa_status tpa_set_sliced_sweep(tpa_graph_t g, int mode);
+tpa_status tpa_get_sliced_sweep(tpa_graph_t g, int *mode, int *active);
 tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);
 
 /* Sticky device-side error (synchronises `stream`): TPA_ERR_INVALID_ARG if

@@ -68,6 +68,8 @@ _SIGS = {
     "tpa_set_keep_iterates": (_i, [_vp, _i]),
     "tpa_set_gather_layout": (_i, [_vp, _i]),
     "tpa_get_gather_layout": (_i, [_vp, _vp]),
+    "tpa_set_sliced_sweep": (_i, [_vp, _i]),
+    "tpa_get_sliced_sweep": (_i, [_vp, _vp, _vp]),
     "tpa_get_push_limit": (_i, [_vp, _vp]),
     "tpa_set_tile_push_limit": (_i, [_vp, _i64]),
     "tpa_get_tile_push_limit": (_i, [_vp, _vp]),
@@ -486,6 +488,19 @@ class Graph:
         v = C.c_int()
         _call("tpa_get_gather_layout", self._h, C.byref(v))
         return v.value
+
+    def set_sliced_sweep(self, mode: int = 1):
+        """XCD-sliced sweep of the stranger chain: 0 off, 1 (default) from
+        2^23 nodes, 2 always (graphs with 1/outdeg weights in the hub-first
+        layout)."""
+        _call("tpa_set_sliced_sweep", self._h, int(mode))
+
+    def get_sliced_sweep(self):
+        """(mode, active): the mode and whether the sliced schedule is built
+        and in use."""
+        v, a = C.c_int(), C.c_int()
+        _call("tpa_get_sliced_sweep", self._h, C.byref(v), C.byref(a))
+        return v.value, bool(a.value)
 
     def get_push_limit(self) -> int:
         v = C.c_int64()

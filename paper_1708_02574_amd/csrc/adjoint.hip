@@ -674,6 +674,12 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     TPA_TRY(get_schedule(g, choose_shape(g, 1), st, &sf1, false));
     TPA_TRY(get_schedule(g, adj_shape, st, &sa1, true));
     if (hub) TPA_TRY(ensure_group_order(g, sf1, st));
+    // the stranger chain is recomputed as preprocessing computed it (in XCD
+    // slices on large graphs), so the iterates are bitwise the kept ones
+    const Schedule *sx = nullptr;
+    const int32_t *colx = nullptr;
+    if (hub) TPA_TRY(ensure_sliced_sweep(g, st, &sx, &colx));
+    const Schedule *sfs = sx ? sx : sf1;
     // layout 2 on large unpacked graphs: lambda in rank order by in-degree
     // (built before the adjoint's group-ordered ids, which are taken from
     // a_colr then).  A packed graph keeps node order: each block's lambda is
@@ -744,7 +750,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(sc.get(&lam0, n, st));
         TPA_TRY(sc.get(&lam1, n, st));
         TPA_TRY(sc.get(&comp, n, st));
-        TPA_TRY(sc.get(&part_f, sf1->n_chunk_items, st));
+        TPA_TRY(sc.get(&part_f, sfs->n_chunk_items, st));
         TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         // forward pass: checkpoints x'(0), x'(C), ...
@@ -752,7 +758,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         fp.zperm = hub ? g->zperm : nullptr;
         TPA_TRY(launch_stranger_init(g, (float)c, 1, z0, ck, comp, fp.zperm, st));
         fp.rowptr = g->t.rowptr;
-        fp.col = hub ? g->t_colz : g->t.col;
+        fp.col = colx ? colx : hub ? g->t_colz : g->t.col;
         fp.w = w_gather;
         fp.inv = g->inv_deg;
         fp.partials = part_f;
@@ -766,7 +772,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             fp.zin = zc;
             fp.zout = zn;
             fp.xs_out = (i % C == 0) ? ck + (size_t)(i / C) * n : nullptr;
-            TPA_TRY(launch_step(*sf1, kPlain, false, fp, st));
+            TPA_TRY(launch_step(*sfs, kPlain, false, fp, st));
             std::swap(zc, zn);
         }
         // backward over segments
@@ -798,7 +804,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
                     fp.zin = a;
                     fp.zout = b;
                     fp.xs_out = seg + (size_t)(i - lo) * n;
-                    TPA_TRY(launch_step(*sf1, kPlain, false, fp, st));
+                    TPA_TRY(launch_step(*sfs, kPlain, false, fp, st));
                     std::swap(a, b);
                 }
             }

@@ -30,6 +30,8 @@ struct StepParams {
     int col_slots = 0;                 // kt == 1: col is a schedule's colg (group items in
                                        // gather order with LDS slots); set by the launchers
     float *partials = nullptr;         // [chunk items][kt] chunk sums of long rows
+    int chunk_slot_in_item = 0;        // kt == 1: a chunk item's partial slot is its row0
+                                       // (XCD-sliced schedules); set by the launchers
     float omc = 0.f;                   // 1 - c
     float c = 0.f;
     int kt = 1;

@@ -381,7 +381,7 @@ __device__ __forceinline__ void item_1(const StepParams &p, const Item it, int64
         if (kind == (int)kItemRow)
             epi_store<MODE>(p, it.row0, 0, s, q, seed_pre);
         else
-            p.partials[wid] = s;
+            p.partials[p.chunk_slot_in_item ? (int64_t)it.row0 : wid] = s;
     }
 }
 
@@ -1488,10 +1488,12 @@ void launch_w(const Schedule &s, const StepParams &p, hipStream_t st) {
 namespace {
 
 // The single-vector kernels read a schedule's group-ordered column ids in
-// place of the hub-first ones they were built from.
+// place of the hub-first ones they were built from, and take the chunk
+// slots of an XCD-sliced schedule from its items.
 StepParams with_group_order(const Schedule &s, const StepParams &p) {
     StepParams q = p;
     q.col_slots = 0;
+    q.chunk_slot_in_item = s.chunk_slot_in_item ? 1 : 0;
     if (q.kt == 1 && s.colg && q.col == s.colg_src) {
         q.col = s.colg;
         q.col_slots = 1;
@@ -1506,6 +1508,7 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (p.kt != 1 && p.kt != 2 && p.kt != 4 && p.kt != 8 && p.kt != 16 && p.kt != 32 && p.kt != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
+    if (s.chunk_slot_in_item && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "an XCD-sliced schedule is single-column");
     if (p.kt == 1 && s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
     if (p.kt != 1 && s.eb > s.el) return fail(TPA_ERR_INVALID_ARG, "block items need a single-column step");
     if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)

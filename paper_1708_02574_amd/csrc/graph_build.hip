@@ -670,6 +670,256 @@ tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t st) {
     return TPA_OK;
 }
 
+namespace {
+
+constexpr int kSliceSegment = 8192;  // edges of a long row per counting wave
+
+// Edges per source slice of each segment of a long row (one wave per
+// segment; cnt[seg][x]).
+__global__ __launch_bounds__(256) void slice_count_kernel(const int64_t *__restrict__ seg_e0,
+                                                          const int32_t *__restrict__ seg_len, int64_t nseg,
+                                                          const int32_t *__restrict__ col, int32_t *__restrict__ cnt) {
+    const int lane = threadIdx.x & 63;
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sg >= nseg) return;
+    const int64_t e0 = seg_e0[sg];
+    const int len = seg_len[sg];
+    int c[kSliceCount] = {};
+    for (int b = 0; b < len; b += 64) {
+        const int e = b + lane;
+        const int x = e < len ? gather_slice(col[e0 + e]) : -1;
+#pragma unroll
+        for (int k = 0; k < kSliceCount; ++k) c[k] += __popcll(__ballot(x == k));
+    }
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < kSliceCount; ++k)
+        if (lane == k) mine = c[k];
+    if (lane < kSliceCount) cnt[sg * kSliceCount + lane] = mine;
+}
+
+// Stable partition of each segment's edges by source slice: slice x's
+// edges of segment sg go, in order, from colx[seg_out[sg][x]] on.
+__global__ __launch_bounds__(256) void slice_scatter_kernel(const int64_t *__restrict__ seg_e0,
+                                                            const int32_t *__restrict__ seg_len, int64_t nseg,
+                                                            const int64_t *__restrict__ seg_out,
+                                                            const int32_t *__restrict__ col,
+                                                            int32_t *__restrict__ colx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sg >= nseg) return;
+    const int64_t e0 = seg_e0[sg];
+    const int len = seg_len[sg];
+    int64_t o[kSliceCount];
+#pragma unroll
+    for (int k = 0; k < kSliceCount; ++k) o[k] = seg_out[sg * kSliceCount + k];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int b = 0; b < len; b += 64) {
+        const int e = b + lane;
+        const int32_t u = e < len ? col[e0 + e] : 0;
+        const int x = e < len ? gather_slice(u) : -1;
+#pragma unroll
+        for (int k = 0; k < kSliceCount; ++k) {
+            const uint64_t mk = __ballot(x == k);
+            if (x == k) colx[o[k] + __popcll(mk & below)] = u;
+            o[k] += __popcll(mk);
+        }
+    }
+}
+
+}  // namespace
+
+tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **out, const int32_t **out_col) {
+    *out = nullptr;
+    *out_col = nullptr;
+    if (g->sliced_sweep == 0 || (g->sliced_sweep == 1 && g->n < kSliceMinN)) return TPA_OK;
+    if (!g->gather_layout || !g->zperm || !g->t_colz || g->weighted || g->n == 0) return TPA_OK;
+    const int ew = choose_shape(g, 1).ew;
+    if (g->sched_x_ew == ew && (g->sched_x_none || g->sched_x.items)) {
+        if (!g->sched_x_none) {
+            *out = &g->sched_x;
+            *out_col = g->t_colx;
+        }
+        return TPA_OK;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return TPA_OK;
+    const int64_t n = g->n, m = g->m;
+    std::vector<int64_t> rp(n + 1);
+    TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->t.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    // long rows (more edges than a group item) and their counting segments
+    std::vector<int32_t> lrows;
+    std::vector<int64_t> first_seg, seg_e0;
+    std::vector<int32_t> seg_len;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d <= ew) continue;
+        lrows.push_back((int32_t)r);
+        first_seg.push_back((int64_t)seg_e0.size());
+        for (int64_t off = 0; off < d; off += kSliceSegment) {
+            seg_e0.push_back(rp[r] + off);
+            seg_len.push_back((int32_t)std::min<int64_t>(kSliceSegment, d - off));
+        }
+    }
+    first_seg.push_back((int64_t)seg_e0.size());
+    if (lrows.empty()) {
+        g->sched_x.release();
+        g->sched_x = Schedule();
+        g->sched_x_ew = ew;
+        g->sched_x_none = true;
+        return TPA_OK;
+    }
+    // an optional copy: built only when it takes at most a quarter of the free memory
+    size_t free_b = 0, total_b = 0;
+    if (!g->t_colx && (hipMemGetInfo(&free_b, &total_b) != hipSuccess || (size_t)m * sizeof(int32_t) > free_b / 4))
+        return TPA_OK;
+    const int64_t nseg = (int64_t)seg_e0.size();
+    int64_t *d_e0 = nullptr, *d_out = nullptr;
+    int32_t *d_len = nullptr, *d_cnt = nullptr;
+    auto cleanup = [&]() { dfree(d_e0); dfree(d_out); dfree(d_len); dfree(d_cnt); };
+    tpa_status rc = TPA_OK;
+    if ((rc = dalloc(&d_e0, nseg, st)) != TPA_OK || (rc = dalloc(&d_len, nseg, st)) != TPA_OK ||
+        (rc = dalloc(&d_cnt, nseg * kSliceCount, st)) != TPA_OK || (rc = dalloc(&d_out, nseg * kSliceCount, st)) != TPA_OK) {
+        cleanup();
+        return rc;
+    }
+    std::vector<int32_t> cnt((size_t)nseg * kSliceCount);
+    hipError_t e = hipMemcpyAsync(d_e0, seg_e0.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_len, seg_len.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        slice_count_kernel<<<(unsigned)((nseg + 3) / 4), 256, 0, st>>>(d_e0, d_len, nseg, g->t_colz, d_cnt);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(TPA_ERR_HIP, std::string("sliced sweep: ") + hipGetErrorString(e));
+    }
+    // each long row: slice x's run follows slices 0..x-1, cut into chunks
+    // of at most 4*EW edges; chunk slots of a row are consecutive, in
+    // slice then chunk order (the finish pass adds them in that order)
+    const int64_t chunk = 4 * (int64_t)ew;
+    std::vector<int64_t> seg_out((size_t)nseg * kSliceCount);
+    std::vector<Item> lists[kSliceCount];
+    std::vector<LongRow> longs;
+    longs.reserve(lrows.size());
+    int64_t slot = 0;
+    for (size_t l = 0; l < lrows.size(); ++l) {
+        const int64_t r = lrows[l], d = rp[r + 1] - rp[r];
+        int64_t tot[kSliceCount] = {};
+        for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg)
+            for (int x = 0; x < kSliceCount; ++x) tot[x] += cnt[(size_t)sg * kSliceCount + x];
+        int64_t sum = 0;
+        for (int x = 0; x < kSliceCount; ++x) sum += tot[x];
+        if (sum != d) {
+            cleanup();
+            return fail(TPA_ERR_HIP, "sliced sweep: slice counts do not add up to the row length");
+        }
+        const int64_t first_slot = slot;
+        int64_t start = rp[r];
+        for (int x = 0; x < kSliceCount; ++x) {
+            int64_t pos = start;
+            for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg) {
+                seg_out[(size_t)sg * kSliceCount + x] = pos;
+                pos += cnt[(size_t)sg * kSliceCount + x];
+            }
+            for (int64_t off = 0; off < tot[x]; off += chunk) {
+                const int64_t len = std::min(chunk, tot[x] - off);
+                lists[x].push_back({start + off, (int32_t)slot, item_meta(1, (uint32_t)len, kItemChunk)});
+                ++slot;
+            }
+            start += tot[x];
+        }
+        if (slot > INT32_MAX) {
+            cleanup();
+            return fail(TPA_ERR_INDEX_OVERFLOW, "too many chunk items");
+        }
+        longs.push_back({(int32_t)r, (int32_t)(slot - first_slot), (int32_t)first_slot, 0});
+    }
+    // block b of the sliced region holds slice b % 8's chunks (empty group
+    // items pad the shorter slices), then the group items of the short rows
+    size_t per = 0;
+    for (int x = 0; x < kSliceCount; ++x) per = std::max(per, (lists[x].size() + 3) / 4);
+    const Item pad = {0, 0, item_meta(0, 0, kItemGroup)};
+    std::vector<Item> all;
+    all.reserve(per * 4 * kSliceCount + (size_t)(m / std::max(ew, 1)) + 64);
+    for (size_t j = 0; j < per; ++j)
+        for (int x = 0; x < kSliceCount; ++x)
+            for (size_t w = 0; w < 4; ++w) {
+                const size_t i = j * 4 + w;
+                all.push_back(i < lists[x].size() ? lists[x][i] : pad);
+            }
+    int64_t gstart = -1, gnnz = 0;
+    auto close_group = [&](int64_t end) {
+        if (gstart >= 0 && end > gstart)
+            all.push_back({rp[gstart], (int32_t)gstart, item_meta((uint32_t)(end - gstart), (uint32_t)gnnz, kItemGroup)});
+        gstart = -1;
+        gnnz = 0;
+    };
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d > ew) {
+            close_group(r);
+            continue;
+        }
+        if (gstart >= 0 && (r - gstart >= 63 || gnnz + d > ew)) close_group(r);
+        if (gstart < 0) gstart = r;
+        gnnz += d;
+    }
+    close_group(n);
+    if ((uint64_t)((all.size() + 3) / 4) * 256 > UINT32_MAX) {
+        cleanup();
+        return fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch");
+    }
+    if (!g->t_colx && (rc = dalloc(&g->t_colx, m, st)) != TPA_OK) {
+        cleanup();
+        return rc;
+    }
+    g->sched_x.release();
+    g->sched_x = Schedule();
+    g->sched_x_ew = 0;
+    g->sched_x_none = false;
+    Schedule sx;
+    sx.ew = ew;
+    sx.ds = std::min(32, ew);
+    sx.el = ew;
+    sx.chunk = (int)chunk;
+    sx.eb = ew;
+    sx.chunk_slot_in_item = true;
+    sx.n_items = (int64_t)all.size();
+    sx.n_chunk_items = slot;
+    sx.n_long = (int64_t)longs.size();
+    rc = dalloc(&sx.items, sx.n_items, st);
+    if (rc == TPA_OK) rc = dalloc(&sx.longs, sx.n_long, st);
+    if (rc != TPA_OK) {
+        sx.release();
+        cleanup();
+        return rc;
+    }
+    e = hipMemcpyAsync(d_out, seg_out.data(), sizeof(int64_t) * seg_out.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(g->t_colx, g->t_colz, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        slice_scatter_kernel<<<(unsigned)((nseg + 3) / 4), 256, 0, st>>>(d_e0, d_len, nseg, d_out, g->t_colz, g->t_colx);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(sx.items, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(sx.longs, longs.data(), sizeof(LongRow) * longs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) {
+        sx.release();
+        return fail(TPA_ERR_HIP, std::string("sliced sweep: ") + hipGetErrorString(e));
+    }
+    g->sched_x = sx;
+    g->sched_x_ew = ew;
+    *out = &g->sched_x;
+    *out_col = g->t_colx;
+    return TPA_OK;
+}
+
 void drop_group_order(tpa_graph *g) {
     // the copies stay allocated (query graphs captured before may read them)
     for (auto &kv : g->sched_t) kv.second.colg_src = nullptr;
@@ -792,6 +1042,11 @@ void graph_release(tpa_graph *g) {
     dfree(g->lrank); dfree(g->a_colr);
     g->lrank = nullptr;
     g->a_colr = nullptr;
+    dfree(g->t_colx);
+    g->t_colx = nullptr;
+    g->sched_x.release();
+    g->sched_x_ew = 0;
+    g->sched_x_none = false;
     g->zperm = nullptr;
     g->t_colz = nullptr;
     g->t_locz = nullptr;
@@ -1024,6 +1279,9 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     add(g->t_wz, sizeof(float) * m);
     add(g->lrank, sizeof(int32_t) * n);
     add(g->a_colr, sizeof(int32_t) * m);
+    add(g->t_colx, sizeof(int32_t) * m);
+    add(g->sched_x.items, sizeof(Item) * (size_t)g->sched_x.n_items);
+    add(g->sched_x.longs, sizeof(LongRow) * (size_t)g->sched_x.n_long);
     add(g->str, sizeof(float) * n);
     add(g->dev_err, sizeof(int32_t));
     add(g->ws, g->ws_bytes);

@@ -469,6 +469,11 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     }
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     if (hub) TPA_TRY(ensure_group_order(g, s, st));
+    // large graphs sweep in XCD slices (when the graph takes them)
+    const Schedule *sx = nullptr;
+    const int32_t *colx = nullptr;
+    if (hub) TPA_TRY(ensure_sliced_sweep(g, st, &sx, &colx));
+    if (sx) s = sx;
     if (!g->str) TPA_TRY(dalloc(&g->str, g->n, st));
     float *tmp = nullptr;
     const size_t n = (size_t)g->n;
@@ -479,7 +484,7 @@ extern "C" tpa_status tpa_preprocess_ex(tpa_graph_t g, double c, int T, double e
     if (rc == TPA_OK) rc = launch_stranger_init(g, (float)c, T == 0, z0, g->str, comp, hub ? g->zperm : nullptr, st);
     StepParams p;
     p.rowptr = g->t.rowptr;
-    p.col = hub ? g->t_colz : g->t.col;
+    p.col = colx ? colx : hub ? g->t_colz : g->t.col;
     p.zperm = hub ? g->zperm : nullptr;
     p.w = g->weighted ? (hub ? g->t_wz : g->t.w) : nullptr;
     p.inv = g->inv_deg;
@@ -613,6 +618,24 @@ extern "C" tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first) {
 extern "C" tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first) {
     if (!g || !hub_first) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
     *hub_first = g->gather_layout;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_set_sliced_sweep(tpa_graph_t g, int mode) {
+    if (!g) return fail(TPA_ERR_INVALID_ARG, "graph is NULL");
+    if (mode < 0 || mode > 2) return fail(TPA_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+    g->sliced_sweep = mode;
+    return TPA_OK;
+}
+
+extern "C" tpa_status tpa_get_sliced_sweep(tpa_graph_t g, int *mode, int *active) {
+    if (!g || !mode) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
+    *mode = g->sliced_sweep;
+    if (active) {
+        const bool hub = g->gather_layout && g->zperm && !g->weighted;
+        *active = (g->sliced_sweep == 2 || (g->sliced_sweep == 1 && g->n >= kSliceMinN)) && hub && g->t_colx &&
+                  !g->sched_x_none && g->sched_x.items && g->sched_x_ew == choose_shape(g, 1).ew;
+    }
     return TPA_OK;
 }
 

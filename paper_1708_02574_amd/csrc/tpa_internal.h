@@ -111,8 +111,27 @@ struct Schedule {
     int32_t *colg = nullptr;
     const int32_t *colg_src = nullptr;
     const int32_t *colg_from = nullptr;  // the ids colg was built from (reused only for those)
+    // XCD-sliced schedules: chunk items carry their partial slot in row0,
+    // and n_chunk_items counts the slots
+    bool chunk_slot_in_item = false;
     void release();
 };
+
+// XCD-sliced single-vector sweep.  The workgroups of a launch are dealt to
+// the chip's 8 XCDs round-robin (block b runs on XCD b % 8), and each XCD
+// has an L2 of its own, so gathers of one cache line from blocks on
+// different XCDs fetch it into every L2.  Rows of A~^T longer than a group
+// item are cut into one run per source slice (their edges stably
+// partitioned by the slice of the gather row, rank order kept within a
+// slice), and slice x's chunks are placed in blocks that run on XCD x: each
+// XCD's L2 then holds the lines of its own eighth of the gathered vector.
+// The hub rows (below 8192, gathered everywhere and cached by every XCD)
+// alternate by row so that the slices carry equal work; the others go by
+// blocks of 1024 rows.  Used from kSliceMinN nodes (1/outdeg graphs in the
+// hub-first layout): below that the whole vector stays in the caches.
+constexpr int kSliceCount = 8;
+constexpr int64_t kSliceMinN = int64_t(1) << 23;
+__host__ __device__ inline int gather_slice(int32_t r) { return r < 8192 ? (r & 7) : ((r >> 10) & 7); }
 
 struct Csr {
     int64_t *rowptr = nullptr;  // n+1
@@ -173,6 +192,16 @@ struct tpa_graph {
     // at the first tpa_backward.
     int32_t *lrank = nullptr;               // n
     int32_t *a_colr = nullptr;              // m
+    // XCD-sliced sweep of the stranger chain (preprocessing and the
+    // adjoint's recomputation): t_colx is t_colz with the edges of each row
+    // longer than a group item partitioned by source slice, sched_x its
+    // schedule (built for group edge budget sched_x_ew; sched_x_none: that
+    // budget leaves no such rows)
+    int sliced_sweep = 1;                   // 0 off, 1 from kSliceMinN nodes, 2 always
+    int32_t *t_colx = nullptr;              // m
+    tpa::Schedule sched_x;
+    int sched_x_ew = 0;
+    bool sched_x_none = false;
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
     bool weighted = false;                  // weights from logits (a.w, t.w set)
@@ -265,6 +294,10 @@ void drop_group_order(tpa_graph *g);
 tpa_status ensure_wz(tpa_graph *g, hipStream_t stream);
 // Build lrank and a_colr (synchronises `stream`); a no-op when present.
 tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t stream);
+// The XCD-sliced schedule and column ids of the single-vector sweep over
+// A~^T when the graph takes one (else *s = nullptr, *col = nullptr); built
+// on first use (synchronous), never under stream capture.
+tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t stream, const Schedule **s, const int32_t **col);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

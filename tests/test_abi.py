@@ -56,6 +56,8 @@ def test_header_status_codes_match_binding():
     lambda L: L.tpa_row_l1(None, None, -1, 10, 1.0, None, None),
     lambda L: L.tpa_row_l1(None, None, 2, 10, 1.0, None, None),
     lambda L: L.tpa_get_gather_layout(None, None),
+    lambda L: L.tpa_set_sliced_sweep(None, 1),
+    lambda L: L.tpa_get_sliced_sweep(None, None, None),
     lambda L: L.tpa_graph_device_bytes(None, None),
     lambda L: L.tpa_graph_blocks(None, None),
     lambda L: L.tpa_graph_export(None, 0, None, None, None, None),

@@ -366,3 +366,32 @@ def test_backward_lambda_rank_order_large_graph(tpa, torch, weighted):
     assert nl1(dth.cpu().numpy(), odth) <= TOL
     assert nl1(dq.cpu().numpy(), odq) <= TOL
     gg.close()
+
+
+def test_backward_sliced_sweep(tpa, torch):
+    """The adjoint recomputes the stranger chain in XCD slices as
+    preprocessing computed it: the gradients are bitwise equal with the
+    iterates kept, recomputed or checkpointed, and match the oracle's."""
+    og = oracle.Graph.rmat(12, 1 << 16, 41)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(12, 1 << 16, 41)
+    gg.set_tuning(1, 64)
+    gg.set_sliced_sweep(2)
+    seeds = ti.draw_seeds(og.export()["padded"] == 0, 4, 42)
+    W = ti.draw_loss_weights((4, og.n), 43)
+    Wt, sd = torch.from_numpy(W).cuda(), torch.from_numpy(seeds).cuda()
+    try:
+        gg.preprocess(c, T)
+        assert gg.get_sliced_sweep() == (2, True)
+        ref = gg.backward(Wt, c, S, T, seeds=sd)
+        ck = gg.backward(Wt, c, S, T, seeds=sd, checkpoint_every=11)
+        gg.set_keep_iterates(True)
+        gg.preprocess(c, T)
+        kept = gg.backward(Wt, c, S, T, seeds=sd)
+        for a, b, d in zip(ref, ck, kept):
+            assert torch.equal(a, b) and torch.equal(a, d)
+    finally:
+        gg.set_keep_iterates(False)
+    odth, _, odq = og.backward(onehot(og.n, seeds), W.astype(np.float64), c, S, T, og.K)
+    assert nl1(ref[0].cpu().numpy(), odth) <= TOL
+    assert nl1(ref[1].cpu().numpy(), odq) <= TOL

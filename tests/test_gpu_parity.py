@@ -846,3 +846,68 @@ def test_bad_seed_gives_nan_row_and_sticky_error(tpa, torch):
     with pytest.raises(tpa.TPAError):
         gg.device_error()
     gg.device_error()  # cleared
+
+
+# ---------------------------------------------------------------- XCD-sliced sweep
+@pytest.mark.parametrize("nn,scale,samples,ew", [
+    (None, 15, 1 << 19, 128), (None, 15, 1 << 19, 512), (20000, 15, 1 << 18, 64), (5000, 13, 1 << 17, 64)])
+def test_sliced_sweep_stranger_parity(tpa, torch, nn, scale, samples, ew):
+    """Rows of A~^T longer than a group item summed as 8 runs, one per
+    source slice (ranks below 8192 by row mod 8, the others by blocks of
+    1024), each slice's runs in the blocks of one XCD, then a finish pass in
+    slice order: the stranger vector and queries against the oracle, with
+    ragged node counts and group budgets from 32 to 512 edges; mode 0 gives
+    back the unsliced sweep bit for bit."""
+    kw = {} if nn is None else {"n_nodes": nn}
+    og = oracle.Graph.rmat(scale, samples, 0x51C + scale, **kw)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(scale, samples, 0x51C + scale, **kw)
+    gg.set_tuning(1, ew)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (1, False)  # off below 2^23 nodes by default
+    base = gg.stranger().cpu().numpy()
+    gg.set_sliced_sweep(2)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (2, True)
+    st = gg.stranger().cpu().numpy()
+    assert l1_rows(base, og.str) <= TOL
+    assert l1_rows(st, og.str) <= TOL, l1_rows(st, og.str)
+    assert st.min() >= 0
+    assert np.all(np.abs(st - base) <= 1e-5 * base + 1e-12)
+    seeds = seeds_for(og, 4, 31)
+    gg.set_tuning(0, 0)
+    R = gg.query(torch.from_numpy(seeds), c, S, T).cpu().numpy()
+    for i, s in enumerate(seeds):
+        assert l1_rows(R[i], og.query(int(s), c, S, T)) <= TOL
+    gg.set_tuning(1, ew)
+    gg.set_sliced_sweep(0)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (0, False)
+    assert np.array_equal(gg.stranger().cpu().numpy(), base)
+
+
+def test_sliced_sweep_skips_weighted_and_node_order(tpa, torch):
+    """Graphs with logit weights, and the node-order layout, keep the
+    unsliced sweep (the sliced copy holds hub-first ids of 1/outdeg graphs)."""
+    og = oracle.Graph.rmat(12, 1 << 16, 9)
+    gg = tpa.Graph.rmat(12, 1 << 16, 9)
+    gg.set_tuning(1, 64)
+    gg.set_sliced_sweep(2)
+    theta = ti.draw_logits(og.m, 3)
+    og.set_logits(theta.astype(np.float64))
+    gg.set_logits(torch.from_numpy(theta).cuda())
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (2, False)
+    assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
+    gg.set_logits(None)
+    og.set_logits(None)
+    gg.set_gather_layout(0)
+    og.preprocess(c, T, EPS)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (2, False)
+    assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
+    gg.set_gather_layout(2)
+    gg.preprocess(c, T)
+    assert gg.get_sliced_sweep() == (2, True)
+    assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
