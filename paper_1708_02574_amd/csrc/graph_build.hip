@@ -729,17 +729,29 @@ __global__ __launch_bounds__(256) void slice_scatter_kernel(const int64_t *__res
 
 }  // namespace
 
+namespace {
+bool takes_sliced_sweep(const tpa_graph *g) {
+    if (g->sliced_sweep == 0 || (g->sliced_sweep == 1 && g->n < kSliceMinN)) return false;
+    return g->gather_layout && g->zperm && g->t_colz && !g->weighted && g->n > 0;
+}
+}  // namespace
+
+const Schedule *find_sliced_sweep(const tpa_graph *g, const int32_t **col) {
+    *col = nullptr;
+    if (!takes_sliced_sweep(g) || g->sched_x_none || !g->sched_x.items || !g->t_colx ||
+        g->sched_x_ew != choose_shape(g, 1).ew)
+        return nullptr;
+    *col = g->t_colx;
+    return &g->sched_x;
+}
+
 tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **out, const int32_t **out_col) {
     *out = nullptr;
     *out_col = nullptr;
-    if (g->sliced_sweep == 0 || (g->sliced_sweep == 1 && g->n < kSliceMinN)) return TPA_OK;
-    if (!g->gather_layout || !g->zperm || !g->t_colz || g->weighted || g->n == 0) return TPA_OK;
+    if (!takes_sliced_sweep(g)) return TPA_OK;
     const int ew = choose_shape(g, 1).ew;
     if (g->sched_x_ew == ew && (g->sched_x_none || g->sched_x.items)) {
-        if (!g->sched_x_none) {
-            *out = &g->sched_x;
-            *out_col = g->t_colx;
-        }
+        *out = find_sliced_sweep(g, out_col);
         return TPA_OK;
     }
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

@@ -135,18 +135,24 @@ namespace {
 
 // Workspace layout: push state (push_plan_bytes, the same for every tile
 // width, so its all-zero accumulator survives queries of any width) |
-// z0 [n*kt] | z1 [n*kt] | partials [chunk items * kt] | (dense restarts)
+// z0 [n*kt] | z1 [n*kt] | partials [slots * kt] | (dense restarts)
 // c*q^T [n*kt] at the next 256-byte boundary (floats)
-size_t query_ws_floats_before_qt(const tpa_graph *g, const Schedule *s, int kt) {
+size_t query_ws_floats_before_qt(const tpa_graph *g, int64_t slots, int kt) {
     const size_t zf = (size_t)g->n * kt;
-    const size_t pf = (size_t)std::max<int64_t>(s->n_chunk_items, 1) * kt;
+    const size_t pf = (size_t)std::max<int64_t>(slots, 1) * kt;
     return ((2 * zf + pf) + 63) & ~(size_t)63;
 }
 
-size_t query_ws_bytes(const tpa_graph *g, const Schedule *s, int kt, bool dense) {
+size_t query_ws_bytes(const tpa_graph *g, int64_t slots, int kt, bool dense) {
     const size_t qf = dense ? (size_t)g->n * kt : 0;
-    return push_plan_bytes(g->n, g->m, third_wmax(g) > 0) + sizeof(float) * (query_ws_floats_before_qt(g, s, kt) + qf) +
-           256;
+    return push_plan_bytes(g->n, g->m, third_wmax(g) > 0) +
+           sizeof(float) * (query_ws_floats_before_qt(g, slots, kt) + qf) + 256;
+}
+
+// Partial slots per column of a query's chunk items: the schedule's, and
+// those of the XCD-sliced schedule when single-seed pulls take it.
+int64_t query_slots(const Schedule *s, const Schedule *sx) {
+    return sx ? std::max(s->n_chunk_items, sx->n_chunk_items) : s->n_chunk_items;
 }
 
 tpa_status ensure_ws(tpa_graph *g, size_t bytes, hipStream_t st) {
@@ -186,7 +192,7 @@ size_t query_workspace_bytes(tpa_graph *g, int64_t k, bool dense, hipStream_t st
     const int kt = choose_kt(g, k);
     const Schedule *s = nullptr;
     if (get_schedule(g, choose_shape(g, kt), st, &s) != TPA_OK) return 0;
-    return query_ws_bytes(g, s, kt, dense);
+    return query_ws_bytes(g, s->n_chunk_items, kt, dense);
 }
 
 // Frontier edges up to which a seed tile pushes its second step, summed
@@ -265,17 +271,22 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     } else {
         TPA_TRY(get_schedule(g, choose_shape(g, kt), st, &s));
     }
+    // single seeds on the handle's own workspace pull their dense family
+    // steps in XCD slices when preprocessing built them (never built here)
+    const int32_t *colx = nullptr;
+    const Schedule *sx = !ws && kt == 1 && !packed ? find_sliced_sweep(g, &colx) : nullptr;
+    const int64_t slots = query_slots(s, sx);
     if (ws) {
-        if (ws_bytes < query_ws_bytes(g, s, kt, q != nullptr)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
+        if (ws_bytes < query_ws_bytes(g, slots, kt, q != nullptr)) return fail(TPA_ERR_INVALID_ARG, "workspace too small");
     } else {
-        TPA_TRY(ensure_ws(g, query_ws_bytes(g, s, kt, q != nullptr), st));
+        TPA_TRY(ensure_ws(g, query_ws_bytes(g, slots, kt, q != nullptr), st));
         ws = g->ws;
     }
     const PushPlan pp = push_plan_at(ws, g->n, g->m, push_wmax(g), third_wmax(g));
     float *z0 = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + push_plan_bytes(g->n, g->m, pp.wmax3 > 0));
     float *z1 = z0 + (size_t)g->n * kt;
     float *part = z1 + (size_t)g->n * kt;
-    float *qT = z0 + query_ws_floats_before_qt(g, s, kt);  // used by dense restarts only
+    float *qT = z0 + query_ws_floats_before_qt(g, slots, kt);  // used by dense restarts only
     // a single seed whose step 2 is not the last: push steps 1 and 2 from
     // the seed's neighbourhood when it is small, pull otherwise (decided on
     // the device, so the launch sequence is fixed and capturable)
@@ -318,6 +329,15 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     p.str = g->str;
     p.out = out;
     p.n = g->n;
+    // a pulled family step that gathers hub-first ids: sliced when available
+    auto pull = [&](const StepParams &pp) -> tpa_status {
+        if (sx && pp.col == g->t_colz) {
+            StepParams px = pp;
+            px.col = colx;
+            return launch_step(*sx, kFamily, false, px, st);
+        }
+        return launch_step(*s, kFamily, false, pp, st);
+    };
     for (int64_t base = 0; base < k; base += kt) {
         p.seeds = seeds ? seeds + base : nullptr;
         p.qdense = q ? q + base * g->n : nullptr;
@@ -377,7 +397,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                 p3.bits = pp.bits;
                 p3.bits_on = pp.flag;
                 p3.skip_on = pp.flag3;
-                TPA_TRY(launch_step(*s, kFamily, false, p3, st));
+                TPA_TRY(pull(p3));
                 continue;
             }
             if (step == 2 && push2) {
@@ -411,7 +431,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             const bool first = step == 1 && !q;
             p.col = first ? g->t.col : col_gather;
             p.w = first ? (g->weighted ? g->t.w : nullptr) : w_gather;
-            TPA_TRY(launch_step(*s, kFamily, first, p, st));
+            TPA_TRY(first ? launch_step(*s, kFamily, true, p, st) : pull(p));
         }
     }
     return TPA_OK;
@@ -577,7 +597,9 @@ extern "C" tpa_status tpa_reserve(tpa_graph_t g, int64_t k) {
     const bool hub = g->gather_layout && g->zperm && (!g->weighted || g->t_wz_valid);
     if (hub && kt == 1) TPA_TRY(ensure_group_order(g, s, nullptr));  // not buildable under capture
     TPA_TRY(ensure_tile_buf(g, kt, false, 4, nullptr));  // for seed tiles whose step 2 may be pushed
-    return ensure_ws(g, query_ws_bytes(g, s, kt, true), nullptr);  // room for dense restarts too
+    const int32_t *colx = nullptr;
+    const Schedule *sx = kt == 1 ? find_sliced_sweep(g, &colx) : nullptr;
+    return ensure_ws(g, query_ws_bytes(g, query_slots(s, sx), kt, true), nullptr);  // room for dense restarts too
 }
 
 extern "C" tpa_status tpa_set_tuning(tpa_graph_t g, int seed_tile, int edges_per_item) {
@@ -632,9 +654,8 @@ extern "C" tpa_status tpa_get_sliced_sweep(tpa_graph_t g, int *mode, int *active
     if (!g || !mode) return fail(TPA_ERR_INVALID_ARG, "NULL argument");
     *mode = g->sliced_sweep;
     if (active) {
-        const bool hub = g->gather_layout && g->zperm && !g->weighted;
-        *active = (g->sliced_sweep == 2 || (g->sliced_sweep == 1 && g->n >= kSliceMinN)) && hub && g->t_colx &&
-                  !g->sched_x_none && g->sched_x.items && g->sched_x_ew == choose_shape(g, 1).ew;
+        const int32_t *colx = nullptr;
+        *active = find_sliced_sweep(g, &colx) != nullptr;
     }
     return TPA_OK;
 }
@@ -758,7 +779,7 @@ extern "C" tpa_status tpa_query_noalloc(tpa_graph_t g, const int32_t *seeds, int
                                          "call tpa_reserve(g, k) or run one tpa_query of k seeds first");
     // the query workspace, then (seed tiles whose step 2 may be pushed) the
     // pushed-tile buffer
-    const size_t wsb = (query_ws_bytes(g, s, kt, false) + 255) & ~(size_t)255;
+    const size_t wsb = (query_ws_bytes(g, s->n_chunk_items, kt, false) + 255) & ~(size_t)255;
     const size_t tbytes = tile_push_applies(g, kt, false, S) ? tile_push_bytes(g->n, g->m, kt) : 0;
     const size_t need = wsb + tbytes;
     if (need > kScratchBytes)

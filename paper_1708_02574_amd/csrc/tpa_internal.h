@@ -298,6 +298,8 @@ tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t stream);
 // A~^T when the graph takes one (else *s = nullptr, *col = nullptr); built
 // on first use (synchronous), never under stream capture.
 tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t stream, const Schedule **s, const int32_t **col);
+// The same when already built for the current shape, else null (never builds).
+const Schedule *find_sliced_sweep(const tpa_graph *g, const int32_t **col);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

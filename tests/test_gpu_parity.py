@@ -911,3 +911,45 @@ def test_sliced_sweep_skips_weighted_and_node_order(tpa, torch):
     gg.preprocess(c, T)
     assert gg.get_sliced_sweep() == (2, True)
     assert l1_rows(gg.stranger().cpu().numpy(), og.str) <= TOL
+
+
+@pytest.mark.parametrize("ew", [64, 512])
+def test_sliced_single_seed_pulls(tpa, torch, ew):
+    """Once preprocessing built the sliced schedule, single-seed queries pull
+    their dense family steps with it: plain pulls, the pulls after pushed
+    second and third steps (with their frontier skips), and dense restarts,
+    against the oracle and against the unsliced pulls to FP32 rounding."""
+    og = oracle.Graph.rmat(15, 1 << 19, 0x51D)
+    og.preprocess(c, T, EPS)
+    gg = tpa.Graph.rmat(15, 1 << 19, 0x51D)
+    gg.set_tuning(1, ew)
+    seeds = seeds_for(og, 6, 77)
+    sd = torch.from_numpy(seeds).cuda()
+    expect = np.stack([og.query(int(s), c, S, T) for s in seeds])
+    rng = np.random.default_rng(78)
+    Q = rng.random((2, og.n))
+    Q /= Q.sum(axis=1, keepdims=True)
+    expect_q = np.stack([og.query_q(q, c, S, T) for q in Q])
+    res = {}
+    try:
+        for mode in (0, 2):
+            gg.set_sliced_sweep(mode)
+            gg.preprocess(c, T)
+            assert gg.get_sliced_sweep() == (mode, mode == 2)
+            for third in (0, og.m):
+                gg.set_third_push_limit(third)
+                for push in (-1, 0):
+                    gg.set_push_limit(push)
+                    R = gg.query(sd, c, S, T).cpu().numpy()
+                    assert np.all(l1_rows(R, expect) <= TOL), (mode, third, push, l1_rows(R, expect))
+                    res[(mode, third, push)] = R.astype(np.float64)
+            Rq = gg.query_dense(torch.from_numpy(Q.astype(np.float32)), c, S, T).cpu().numpy()
+            assert np.all(l1_rows(Rq, expect_q) <= TOL)
+            res[(mode, "q")] = Rq.astype(np.float64)
+    finally:
+        gg.set_push_limit(-1)
+        gg.set_third_push_limit(-1)
+    for key, a in res.items():
+        if key[0] == 2:
+            b = res[(0,) + key[1:]]
+            assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 1e-9), key
