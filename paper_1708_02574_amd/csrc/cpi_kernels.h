@@ -32,6 +32,8 @@ struct StepParams {
     float *partials = nullptr;         // [chunk items][kt] chunk sums of long rows
     int chunk_slot_in_item = 0;        // kt == 1: a chunk item's partial slot is its row0
                                        // (XCD-sliced schedules); set by the launchers
+    const int64_t *rowptr_x = nullptr; // XCD-sliced schedules: short-row offsets and band
+    const int32_t *xrel = nullptr;     // tables (set by the launchers)
     float omc = 0.f;                   // 1 - c
     float c = 0.f;
     int kt = 1;

@@ -446,6 +446,113 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
     item_1<MODE, FIRST, WEIGHTED>(p, it, wid, lane, lds[wv]);
 }
 
+// ------------------------------------------------------------ XCD-sliced, kt == 1
+// Group-kind items of an XCD-sliced schedule (kt == 1, 1/outdeg weights,
+// never a first step): BAND, slice x's runs of up to 63 medium rows into
+// their partial slots; otherwise consecutive rows whose offsets come from
+// rowptr_x, summed only for the short rows (medium and long rows have no
+// edges in that section and take their epilogue in the finish pass).  The
+// products go through the wave's LDS slice as in a group item.
+template <int MODE, bool BAND>
+__device__ __forceinline__ void item_1x(const StepParams &p, const Item it, int lane, float *my) {
+    constexpr int NS = kGroupMax / 64;
+    const int nrows = (int)item_nrows(it.meta);
+    const int nnz = (int)item_nnz(it.meta);
+    const int32_t *col = p.col + it.e0;
+    const int32_t seed_pre = MODE == kFamily ? seed_ahead(p, 0) : kSeedLookup;
+    int rel;
+    bool own = false;  // the lane's row takes its epilogue here
+    int64_t slot0 = 0;
+    if (BAND) {
+        const int32_t *tab = p.xrel + it.row0;
+        slot0 = tab[0];
+        rel = lane <= nrows ? tab[1 + lane] : nnz;
+    } else {
+        const int64_t rx = lane <= nrows ? p.rowptr_x[it.row0 + lane] : 0;
+        rel = lane <= nrows ? (int)((rx & kRowxMask) - it.e0) : nnz;
+        own = lane < nrows && !((rx >> kRowxForeignBit) & 1);
+    }
+    int32_t u[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int e = s * 64 + lane;
+        u[s] = e < nnz ? col[e] : -1;
+    }
+    EpiPre q;
+    if (!BAND && own) q = epi_load<MODE>(p, it.row0 + lane);
+    if (frontier_on(p)) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (u[s] >= 0 && !row_live(p, u[s])) u[s] = -1;  // a zero row: its term is 0
+    }
+    float v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = u[s] >= 0 ? edge_value<false, false, 1>(p, 0, u[s], 0) : 0.0f;
+    wave_sync();  // the previous item's LDS reads are done
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+        if (s * 64 + lane < nnz) my[s * 64 + lane] = v[s];
+    const int rel_next = __shfl(rel, lane + 1 < 64 ? lane + 1 : 63, 64);
+    wave_sync();
+    const int len = rel_next - rel;
+    if (lane < nrows && len <= 32) {
+        float acc = 0.0f;
+        for (int k = rel; k < rel_next; ++k) acc += my[k];
+        if (BAND) p.partials[slot0 + 8 * lane] = acc;
+        else if (own) epi_store<MODE>(p, it.row0 + lane, 0, acc, q, seed_pre);
+    }
+    uint64_t big = __ballot(lane < nrows && len > 32);
+    while (big) {
+        const int r = __builtin_ctzll(big);
+        big &= big - 1;
+        const int b = __builtin_amdgcn_readlane(rel, r), en = __builtin_amdgcn_readlane(rel_next, r);
+        float t = 0.0f;
+        for (int k = b + lane; k < en; k += 64) t += my[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (BAND) {
+            if (lane == 0) p.partials[slot0 + 8 * r] = t;
+        } else {
+            const EpiPre qr = epi_readlane(q, r);  // a row with edges here is the item's own
+            if (lane == 0) epi_store<MODE>(p, it.row0 + r, 0, t, qr, seed_pre);
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void step_kernel_1x(const Item *__restrict__ items, int64_t n_items,
+                                                           StepParams p) {
+    __shared__ float lds[kWaves][kGroupMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t wid = (int64_t)blockIdx.x * kWaves + wv;
+    if (wid >= n_items || (p.skip_on && *p.skip_on)) return;
+    const Item it = items[wid];
+    if (item_kind(it.meta) == kItemChunk)
+        item_1<MODE, false, false>(p, it, wid, lane, lds[wv]);
+    else if (it.meta & kItemBandBit)
+        item_1x<MODE, true>(p, it, lane, lds[wv]);
+    else
+        item_1x<MODE, false>(p, it, lane, lds[wv]);
+}
+
+// Finish of the medium rows of an XCD-sliced schedule: 8 lanes per row add
+// its 8 slice sums (a fixed xor order), then the epilogue.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void finish8_kernel(const LongRow *__restrict__ rows, int64_t n_rows,
+                                                           StepParams p) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 8 + (lane >> 3);
+    if (p.skip_on && *p.skip_on) return;
+    const bool ok = i < n_rows;
+    LongRow lr = {0, 0, 0, 0};
+    if (ok) lr = rows[i];
+    float t = ok ? p.partials[(int64_t)lr.first_item + (lane & 7)] : 0.0f;
+    t += __shfl_xor(t, 4, 64);
+    t += __shfl_xor(t, 2, 64);
+    t += __shfl_xor(t, 1, 64);
+    if (ok && (lane & 7) == 0) epilogue<MODE>(p, lr.row, 0, t);
+}
+
 // The second family step of a single seed, gated by the push plan's flag:
 // when the step was pushed, the launch converts the fixed-point sums of
 // every gather row; otherwise it pulls the step over A~^T.  Blocks stride
@@ -1460,7 +1567,15 @@ void launch_kt(const Schedule &s, const StepParams &p, hipStream_t st) {
     const Item *it = s.items;
     const int64_t ni = s.n_items;
     switch (p.kt) {
-        case 1: step_kernel_1<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p); break;
+        case 1:
+            if constexpr (!FIRST && !WEIGHTED) {
+                if (s.chunk_slot_in_item) {
+                    step_kernel_1x<MODE><<<grid, kThreads, 0, st>>>(it, ni, p);
+                    break;
+                }
+            }
+            step_kernel_1<MODE, FIRST, WEIGHTED><<<grid, kThreads, 0, st>>>(it, ni, p);
+            break;
         case 2: KT_LAUNCH(2); break;
         case 4: KT_LAUNCH(4); break;
         case 8: KT_LAUNCH(8); break;
@@ -1494,6 +1609,8 @@ StepParams with_group_order(const Schedule &s, const StepParams &p) {
     StepParams q = p;
     q.col_slots = 0;
     q.chunk_slot_in_item = s.chunk_slot_in_item ? 1 : 0;
+    q.rowptr_x = s.rowptr_x;
+    q.xrel = s.xrel;
     if (q.kt == 1 && s.colg && q.col == s.colg_src) {
         q.col = s.colg;
         q.col_slots = 1;
@@ -1508,7 +1625,8 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     if (p.kt != 1 && p.kt != 2 && p.kt != 4 && p.kt != 8 && p.kt != 16 && p.kt != 32 && p.kt != 64)
         return fail(TPA_ERR_INVALID_ARG, "seed tile must be 1, 2, 4, 8, 16, 32 or 64");
     if (mode == kStranger && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "stranger step is single-column");
-    if (s.chunk_slot_in_item && p.kt != 1) return fail(TPA_ERR_INVALID_ARG, "an XCD-sliced schedule is single-column");
+    if (s.chunk_slot_in_item && (p.kt != 1 || first || p.w))
+        return fail(TPA_ERR_INVALID_ARG, "an XCD-sliced schedule takes single-column pulls with 1/outdeg weights");
     if (p.kt == 1 && s.ew > kGroupMax) return fail(TPA_ERR_INVALID_ARG, "group items exceed the LDS slice");
     if (p.kt != 1 && s.eb > s.el) return fail(TPA_ERR_INVALID_ARG, "block items need a single-column step");
     if ((uint64_t)blocks_for(s.n_items) * kThreads > UINT32_MAX)
@@ -1544,6 +1662,17 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
             finish_kernel<kPlain><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
         else
             finish_kernel<kStranger><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
+        profile_end(slot, st);
+    }
+    if (s.n_long8 > 0) {
+        const int slot = profile_begin(127, st);
+        const unsigned grid = blocks_for((s.n_long8 + 7) / 8);
+        if (mode == kFamily)
+            finish8_kernel<kFamily><<<grid, kThreads, 0, st>>>(s.longs8, s.n_long8, p);
+        else if (mode == kPlain)
+            finish8_kernel<kPlain><<<grid, kThreads, 0, st>>>(s.longs8, s.n_long8, p);
+        else
+            finish8_kernel<kStranger><<<grid, kThreads, 0, st>>>(s.longs8, s.n_long8, p);
         profile_end(slot, st);
     }
     TPA_TRY_HIP(hipGetLastError());

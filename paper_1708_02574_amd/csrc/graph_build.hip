@@ -727,6 +727,20 @@ __global__ __launch_bounds__(256) void slice_scatter_kernel(const int64_t *__res
     }
 }
 
+// Short rows' edges into their section of the sliced ids (grid-stride
+// over rows; rows flagged foreign are placed by slice_scatter_kernel).
+__global__ __launch_bounds__(256) void short_copy_kernel(const int64_t *__restrict__ rp,
+                                                         const int64_t *__restrict__ rowx, int64_t n,
+                                                         const int32_t *__restrict__ col,
+                                                         int32_t *__restrict__ colx) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rx = rowx[r];
+        if ((rx >> kRowxForeignBit) & 1) continue;
+        const int64_t b = rp[r], d = rp[r + 1] - b, o = rx & kRowxMask;
+        for (int64_t k = 0; k < d; ++k) colx[o + k] = col[b + k];
+    }
+}
+
 }  // namespace
 
 namespace {
@@ -757,13 +771,23 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return TPA_OK;
     const int64_t n = g->n, m = g->m;
+    const int64_t lm = std::min<int64_t>(kSliceShortRow, ew);
     std::vector<int64_t> rp(n + 1);
     TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->t.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
     TPA_TRY_HIP(hipStreamSynchronize(st));
-    // long rows (more edges than a group item) and their counting segments
-    std::vector<int32_t> lrows;
+    // medium rows (one counting segment each) and long rows (segments of
+    // kSliceSegment edges), in row order
+    std::vector<int32_t> mrows, lrows;
     std::vector<int64_t> first_seg, seg_e0;
     std::vector<int32_t> seg_len;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d > lm && d <= ew) {
+            mrows.push_back((int32_t)r);
+            seg_e0.push_back(rp[r]);
+            seg_len.push_back((int32_t)d);
+        }
+    }
     for (int64_t r = 0; r < n; ++r) {
         const int64_t d = rp[r + 1] - rp[r];
         if (d <= ew) continue;
@@ -775,17 +799,18 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
         }
     }
     first_seg.push_back((int64_t)seg_e0.size());
-    if (lrows.empty()) {
+    if (lrows.empty() && mrows.empty()) {
         g->sched_x.release();
         g->sched_x = Schedule();
         g->sched_x_ew = ew;
         g->sched_x_none = true;
         return TPA_OK;
     }
-    // an optional copy: built only when it takes at most a quarter of the free memory
+    // an optional copy: built only when it (and the row offsets) take at
+    // most a quarter of the free memory
     size_t free_b = 0, total_b = 0;
-    if (!g->t_colx && (hipMemGetInfo(&free_b, &total_b) != hipSuccess || (size_t)m * sizeof(int32_t) > free_b / 4))
-        return TPA_OK;
+    const size_t extra = (g->t_colx ? 0 : (size_t)m * sizeof(int32_t)) + (size_t)(n + 1) * sizeof(int64_t);
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || extra > free_b / 4) return TPA_OK;
     const int64_t nseg = (int64_t)seg_e0.size();
     int64_t *d_e0 = nullptr, *d_out = nullptr;
     int32_t *d_len = nullptr, *d_cnt = nullptr;
@@ -810,33 +835,90 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
         cleanup();
         return fail(TPA_ERR_HIP, std::string("sliced sweep: ") + hipGetErrorString(e));
     }
-    // each long row: slice x's run follows slices 0..x-1, cut into chunks
-    // of at most 4*EW edges; chunk slots of a row are consecutive, in
-    // slice then chunk order (the finish pass adds them in that order)
-    const int64_t chunk = 4 * (int64_t)ew;
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+        int64_t sum = 0;
+        for (int x = 0; x < kSliceCount; ++x) sum += cnt[(size_t)sg * kSliceCount + x];
+        if (sum != seg_len[sg]) {
+            cleanup();
+            return fail(TPA_ERR_HIP, "sliced sweep: slice counts do not add up to the segment length");
+        }
+    }
+    // short section: offsets of the short rows, the others flagged
+    std::vector<int64_t> rowx(n + 1);
+    int64_t pos = 0;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d <= lm) {
+            rowx[r] = pos;
+            pos += d;
+        } else {
+            rowx[r] = pos | (int64_t(1) << kRowxForeignBit);
+        }
+    }
+    rowx[n] = pos;
     std::vector<int64_t> seg_out((size_t)nseg * kSliceCount);
     std::vector<Item> lists[kSliceCount];
-    std::vector<LongRow> longs;
-    longs.reserve(lrows.size());
+    std::vector<int32_t> xrel;
+    std::vector<LongRow> longs, longs8;
     int64_t slot = 0;
+    // long rows' chunk slots first: slice x's run follows slices 0..x-1,
+    // cut into chunks of at most 4*EW edges, slots in slice then chunk order
+    const int64_t chunk = 4 * (int64_t)ew;
+    int64_t lpos = 0;  // long rows' offset within their section (placed after the bands)
+    std::vector<int64_t> lstart(lrows.size());
     for (size_t l = 0; l < lrows.size(); ++l) {
-        const int64_t r = lrows[l], d = rp[r + 1] - rp[r];
+        lstart[l] = lpos;
+        lpos += rp[lrows[l] + 1] - rp[lrows[l]];
+    }
+    // bands of consecutive medium rows: at most 63 rows and kGroupEdges
+    // edges per slice
+    const int64_t band_section = pos;
+    for (size_t i = 0; i < mrows.size();) {
+        int64_t bc[kSliceCount] = {};
+        size_t j = i;
+        while (j < mrows.size() && j - i < 63) {
+            bool fits = true;
+            for (int x = 0; x < kSliceCount; ++x)
+                if (bc[x] + cnt[j * kSliceCount + x] > kGroupEdges) fits = false;
+            if (!fits) break;
+            for (int x = 0; x < kSliceCount; ++x) bc[x] += cnt[j * kSliceCount + x];
+            ++j;
+        }
+        const int R = (int)(j - i);  // >= 1: a medium row has at most EW <= kGroupEdges edges
+        const int64_t slot0 = slot;
+        slot += 8 * (int64_t)R;
+        for (int x = 0; x < kSliceCount; ++x) {
+            const int64_t tab = (int64_t)xrel.size();
+            xrel.push_back((int32_t)(slot0 + x));
+            int64_t run = 0;
+            for (size_t r = i; r < j; ++r) {
+                xrel.push_back((int32_t)run);
+                seg_out[r * kSliceCount + x] = pos + run;
+                run += cnt[r * kSliceCount + x];
+            }
+            xrel.push_back((int32_t)run);
+            lists[x].push_back({pos, (int32_t)tab, item_meta((uint32_t)R, (uint32_t)run, kItemGroup) | kItemBandBit});
+            pos += run;
+        }
+        for (size_t r = i; r < j; ++r) longs8.push_back({mrows[r], 8, (int32_t)(slot0 + 8 * (int64_t)(r - i)), 0});
+        if (slot > INT32_MAX || (int64_t)xrel.size() > INT32_MAX) {
+            cleanup();
+            return fail(TPA_ERR_INDEX_OVERFLOW, "too many sliced work items");
+        }
+        i = j;
+    }
+    const int64_t long_section = pos;
+    for (size_t l = 0; l < lrows.size(); ++l) {
         int64_t tot[kSliceCount] = {};
         for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg)
             for (int x = 0; x < kSliceCount; ++x) tot[x] += cnt[(size_t)sg * kSliceCount + x];
-        int64_t sum = 0;
-        for (int x = 0; x < kSliceCount; ++x) sum += tot[x];
-        if (sum != d) {
-            cleanup();
-            return fail(TPA_ERR_HIP, "sliced sweep: slice counts do not add up to the row length");
-        }
         const int64_t first_slot = slot;
-        int64_t start = rp[r];
+        int64_t start = long_section + lstart[l];
         for (int x = 0; x < kSliceCount; ++x) {
-            int64_t pos = start;
+            int64_t at = start;
             for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg) {
-                seg_out[(size_t)sg * kSliceCount + x] = pos;
-                pos += cnt[(size_t)sg * kSliceCount + x];
+                seg_out[(size_t)sg * kSliceCount + x] = at;
+                at += cnt[(size_t)sg * kSliceCount + x];
             }
             for (int64_t off = 0; off < tot[x]; off += chunk) {
                 const int64_t len = std::min(chunk, tot[x] - off);
@@ -849,37 +931,46 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
             cleanup();
             return fail(TPA_ERR_INDEX_OVERFLOW, "too many chunk items");
         }
-        longs.push_back({(int32_t)r, (int32_t)(slot - first_slot), (int32_t)first_slot, 0});
+        longs.push_back({lrows[l], (int32_t)(slot - first_slot), (int32_t)first_slot, 0});
     }
-    // block b of the sliced region holds slice b % 8's chunks (empty group
+    if (long_section + lpos != m || band_section != rowx[n]) {
+        cleanup();
+        return fail(TPA_ERR_HIP, "sliced sweep: sections do not cover the edges");
+    }
+    // block b of the sliced region holds slice b % 8's items (empty group
     // items pad the shorter slices), then the group items of the short rows
     size_t per = 0;
     for (int x = 0; x < kSliceCount; ++x) per = std::max(per, (lists[x].size() + 3) / 4);
     const Item pad = {0, 0, item_meta(0, 0, kItemGroup)};
     std::vector<Item> all;
-    all.reserve(per * 4 * kSliceCount + (size_t)(m / std::max(ew, 1)) + 64);
-    for (size_t j = 0; j < per; ++j)
+    all.reserve(per * 4 * kSliceCount + (size_t)(n / 32) + 64);
+    for (size_t jb = 0; jb < per; ++jb)
         for (int x = 0; x < kSliceCount; ++x)
             for (size_t w = 0; w < 4; ++w) {
-                const size_t i = j * 4 + w;
+                const size_t i = jb * 4 + w;
                 all.push_back(i < lists[x].size() ? lists[x][i] : pad);
             }
-    int64_t gstart = -1, gnnz = 0;
+    // short rows: greedy groups of consecutive rows (at most 63 rows and EW
+    // edges; medium and long rows inside add no edges), none without a
+    // short row
+    int64_t gstart = -1, gnnz = 0, gown = 0;
     auto close_group = [&](int64_t end) {
-        if (gstart >= 0 && end > gstart)
-            all.push_back({rp[gstart], (int32_t)gstart, item_meta((uint32_t)(end - gstart), (uint32_t)gnnz, kItemGroup)});
+        if (gstart >= 0 && end > gstart && gown > 0)
+            all.push_back({rowx[gstart] & kRowxMask, (int32_t)gstart,
+                           item_meta((uint32_t)(end - gstart), (uint32_t)gnnz, kItemGroup)});
         gstart = -1;
         gnnz = 0;
+        gown = 0;
     };
     for (int64_t r = 0; r < n; ++r) {
         const int64_t d = rp[r + 1] - rp[r];
-        if (d > ew) {
-            close_group(r);
-            continue;
-        }
-        if (gstart >= 0 && (r - gstart >= 63 || gnnz + d > ew)) close_group(r);
+        const bool shortrow = d <= lm;
+        const int64_t ds = shortrow ? d : 0;
+        if (gstart >= 0 && (r - gstart >= 63 || gnnz + ds > ew)) close_group(r);
+        if (gstart < 0 && !shortrow) continue;
         if (gstart < 0) gstart = r;
-        gnnz += d;
+        gnnz += ds;
+        gown += shortrow ? 1 : 0;
     }
     close_group(n);
     if ((uint64_t)((all.size() + 3) / 4) * 256 > UINT32_MAX) {
@@ -904,21 +995,32 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     sx.n_items = (int64_t)all.size();
     sx.n_chunk_items = slot;
     sx.n_long = (int64_t)longs.size();
+    sx.n_long8 = (int64_t)longs8.size();
     rc = dalloc(&sx.items, sx.n_items, st);
-    if (rc == TPA_OK) rc = dalloc(&sx.longs, sx.n_long, st);
+    if (rc == TPA_OK && sx.n_long) rc = dalloc(&sx.longs, sx.n_long, st);
+    if (rc == TPA_OK && sx.n_long8) rc = dalloc(&sx.longs8, sx.n_long8, st);
+    if (rc == TPA_OK) rc = dalloc(&sx.rowptr_x, n + 1, st);
+    if (rc == TPA_OK) rc = dalloc(&sx.xrel, std::max<size_t>(xrel.size(), 1), st);
     if (rc != TPA_OK) {
         sx.release();
         cleanup();
         return rc;
     }
     e = hipMemcpyAsync(d_out, seg_out.data(), sizeof(int64_t) * seg_out.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(g->t_colx, g->t_colz, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sx.rowptr_x, rowx.data(), sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         slice_scatter_kernel<<<(unsigned)((nseg + 3) / 4), 256, 0, st>>>(d_e0, d_len, nseg, d_out, g->t_colz, g->t_colx);
+        short_copy_kernel<<<grid_for(n), kBlock, 0, st>>>(g->t.rowptr, sx.rowptr_x, n, g->t_colz, g->t_colx);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpyAsync(sx.items, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sx.longs, longs.data(), sizeof(LongRow) * longs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && sx.n_long)
+        e = hipMemcpyAsync(sx.longs, longs.data(), sizeof(LongRow) * longs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && sx.n_long8)
+        e = hipMemcpyAsync(sx.longs8, longs8.data(), sizeof(LongRow) * longs8.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !xrel.empty())
+        e = hipMemcpyAsync(sx.xrel, xrel.data(), sizeof(int32_t) * xrel.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     cleanup();
     if (e != hipSuccess) {
@@ -943,9 +1045,15 @@ void Schedule::release() {
     dfree(items);
     dfree(longs);
     dfree(colg);
+    dfree(rowptr_x);
+    dfree(xrel);
+    dfree(longs8);
     items = nullptr;
     longs = nullptr;
     colg = nullptr;
+    rowptr_x = nullptr;
+    xrel = nullptr;
+    longs8 = nullptr;
     colg_src = nullptr;
     colg_from = nullptr;
 }
@@ -1294,6 +1402,8 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     add(g->t_colx, sizeof(int32_t) * m);
     add(g->sched_x.items, sizeof(Item) * (size_t)g->sched_x.n_items);
     add(g->sched_x.longs, sizeof(LongRow) * (size_t)g->sched_x.n_long);
+    add(g->sched_x.longs8, sizeof(LongRow) * (size_t)g->sched_x.n_long8);
+    add(g->sched_x.rowptr_x, sizeof(int64_t) * (n + 1));
     add(g->str, sizeof(float) * n);
     add(g->dev_err, sizeof(int32_t));
     add(g->ws, g->ws_bytes);

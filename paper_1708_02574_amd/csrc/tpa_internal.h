@@ -112,8 +112,13 @@ struct Schedule {
     const int32_t *colg_src = nullptr;
     const int32_t *colg_from = nullptr;  // the ids colg was built from (reused only for those)
     // XCD-sliced schedules: chunk items carry their partial slot in row0,
-    // and n_chunk_items counts the slots
+    // and n_chunk_items counts the slots; band items and the short-row
+    // offsets (see gather_slice); rows of longs8 have 8 consecutive slots
     bool chunk_slot_in_item = false;
+    int64_t *rowptr_x = nullptr;  // device, n+1
+    int32_t *xrel = nullptr;      // device
+    LongRow *longs8 = nullptr;    // device
+    int64_t n_long8 = 0;
     void release();
 };
 
@@ -129,8 +134,23 @@ struct Schedule {
 // alternate by row so that the slices carry equal work; the others go by
 // blocks of 1024 rows.  Used from kSliceMinN nodes (1/outdeg graphs in the
 // hub-first layout): below that the whole vector stays in the caches.
+//
+// Rows of up to kSliceShortRow edges are not split.  Medium rows (up to a
+// group item) are split into 8 runs as well: a band item holds slice x's
+// runs of up to 63 consecutive medium rows, laid out one after the other in
+// the sliced ids, so each band reads like a group item.  The sliced ids hold
+// the short rows first (row order), then the bands (slice-major per band),
+// then the long rows (slice-major per row).  rowptr_x gives each row's
+// offset in the short section with bit kRowxForeignBit set on medium and
+// long rows (no edges there; their epilogue is the finish pass's), and a
+// band item's row0 indexes xrel: [first partial slot, run offsets 0..R];
+// row i's slot of slice x is the band's first slot + 8 i + x.
 constexpr int kSliceCount = 8;
 constexpr int64_t kSliceMinN = int64_t(1) << 23;
+constexpr int kSliceShortRow = 32;
+constexpr uint32_t kItemBandBit = 1u << 26;
+constexpr int kRowxForeignBit = 62;
+constexpr int64_t kRowxMask = (int64_t(1) << kRowxForeignBit) - 1;
 __host__ __device__ inline int gather_slice(int32_t r) { return r < 8192 ? (r & 7) : ((r >> 10) & 7); }
 
 struct Csr {
