@@ -156,6 +156,7 @@ def profiled(tpa, torch, fn, codes, period=1):
 # launches outside the step-kernel numbering (tpa_profile_read codes)
 CODE_GATED_PULL = 118  # a pull that does nothing when the device pushed its step
 CODE_GATED, CODE_TILE_PLAN, CODE_TILE_PUSH, CODE_PUSH12, CODE_TILE_CONVERT, CODE_PUSH3 = 120, 122, 123, 124, 125, 126
+CODE_FINISH = 127  # the finish passes of rows summed in parts (chunks, XCD slices)
 
 
 def breakdown(prof: dict, labels: dict) -> dict:
@@ -275,7 +276,9 @@ def headline(tpa, torch, np, ti, args) -> dict:
                                          for i in range(k)], list(plain_codes.values()))
     prof.update(profiled(tpa, torch, lambda: g.query(seeds, C_RESTART, S_FAM, T_STR, out=out_batch),
                          list(batch_codes.values())))
-    prof.update(profiled(tpa, torch, lambda: g.preprocess(C_RESTART, T_STR), [cs]))
+    prof.update(profiled(tpa, torch, lambda: g.preprocess(C_RESTART, T_STR), [cs, CODE_FINISH]))
+    sliced = g.get_sliced_sweep()[1]
+    fin_n, fin_ms = prof[CODE_FINISH]
     rec = {
         "metric": "TPA query GTEPS & seeds/s, batched vs 1-seed, at L1 <=1e-5 vs FP64 oracle",
         "value": round((K + 2 * k * (S_FAM - 1)) * m / (ms_step * 1e-3) / 1e9, 3),
@@ -302,15 +305,21 @@ def headline(tpa, torch, np, ti, args) -> dict:
                   "plain": round(k * (S_FAM - 1) * m / (t_pl * 1e-3) / 1e9, 2)},
         "ms": {"preprocess": round(t_pre, 3), f"batched_{k}": round(t_bat, 3), f"plain_{k}": round(t_pl, 3),
                "graph_build": round(build_ms, 1), "first_preprocess": round(first_pre_ms, 1)},
-        "roofline": roofline("step_kernel_1<stranger> (preprocessing CPI step, one vector)",
+        "roofline": roofline("step_kernel_1x<stranger> (preprocessing CPI step, one vector, XCD-sliced)" if sliced
+                             else "step_kernel_1<stranger> (preprocessing CPI step, one vector)",
                              bytes_stranger(n, m, K, T_STR), *prof[cs],
                              traffic_from_profile("step_kernel_1_stranger_rmat27_traffic")),
+        "preprocess_finish_passes": {"launches": fin_n, "us_per_step": round(fin_ms * 1e3 / max(prof[cs][0], 1), 1),
+                                     "note": "per CPI step, after the step kernel: the sums of the rows split into "
+                                             "chunks or XCD slices, and their epilogue"},
         "roofline_batched": roofline(f"step_kernel_kt<16, family> ({k}-seed tile CPI step 3)",
                                      bytes_sweep(n, m, 16), *prof[cf16],
                                      traffic_from_profile("step_kernel_16_family_rmat27_traffic")),
         "roofline_batched_last": roofline(f"step_kernel_kt<16, family, last> ({k}-seed tile CPI step 4 with the "
                                           "combine)", bytes_sweep(n, m, 16), *prof[cf16l]),
-        "roofline_plain": roofline("step_kernel_1<family, last> (single-seed CPI step 4 with the combine)",
+        "roofline_plain": roofline(("step_kernel_1x<family, last> (single-seed CPI step 4 with the combine, "
+                                    "XCD-sliced)") if sliced else
+                                   "step_kernel_1<family, last> (single-seed CPI step 4 with the combine)",
                                    bytes_sweep(n, m, 1), *prof[cf1l]),
 
         "kernels_per_query": {"plain": breakdown(prof, plain_codes), "batched": breakdown(prof, batch_codes)},

@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1(const Item *__restrict
 // ------------------------------------------------------------ XCD-sliced, kt == 1
 // Group-kind items of an XCD-sliced schedule (kt == 1, 1/outdeg weights,
 // never a first step): BAND, slice x's runs of up to 63 medium rows into
-// their partial slots; otherwise consecutive rows whose offsets come from
+// consecutive partial slots (from xrel's first entry); otherwise consecutive rows whose offsets come from
 // rowptr_x, summed only for the short rows (medium and long rows have no
 // edges in that section and take their epilogue in the finish pass).  The
 // products go through the wave's LDS slice as in a group item.
@@ -498,7 +498,7 @@ __device__ __forceinline__ void item_1x(const StepParams &p, const Item it, int 
     if (lane < nrows && len <= 32) {
         float acc = 0.0f;
         for (int k = rel; k < rel_next; ++k) acc += my[k];
-        if (BAND) p.partials[slot0 + 8 * lane] = acc;
+        if (BAND) p.partials[slot0 + lane] = acc;
         else if (own) epi_store<MODE>(p, it.row0 + lane, 0, acc, q, seed_pre);
     }
     uint64_t big = __ballot(lane < nrows && len > 32);
@@ -511,7 +511,7 @@ __device__ __forceinline__ void item_1x(const StepParams &p, const Item it, int 
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
         if (BAND) {
-            if (lane == 0) p.partials[slot0 + 8 * r] = t;
+            if (lane == 0) p.partials[slot0 + r] = t;
         } else {
             const EpiPre qr = epi_readlane(q, r);  // a row with edges here is the item's own
             if (lane == 0) epi_store<MODE>(p, it.row0 + r, 0, t, qr, seed_pre);
@@ -536,7 +536,8 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1x(const Item *__restric
 }
 
 // Finish of the medium rows of an XCD-sliced schedule: 8 lanes per row add
-// its 8 slice sums (a fixed xor order), then the epilogue.
+// its 8 slice sums (slice x of medium row i in slot x * n_rows + i; a fixed
+// xor order), then the epilogue.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void finish8_kernel(const LongRow *__restrict__ rows, int64_t n_rows,
                                                            StepParams p) {
@@ -544,13 +545,12 @@ __global__ __launch_bounds__(kThreads) void finish8_kernel(const LongRow *__rest
     const int64_t i = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 8 + (lane >> 3);
     if (p.skip_on && *p.skip_on) return;
     const bool ok = i < n_rows;
-    LongRow lr = {0, 0, 0, 0};
-    if (ok) lr = rows[i];
-    float t = ok ? p.partials[(int64_t)lr.first_item + (lane & 7)] : 0.0f;
+    const int32_t row = ok ? rows[i].row : 0;
+    float t = ok ? p.partials[(int64_t)(lane & 7) * n_rows + i] : 0.0f;
     t += __shfl_xor(t, 4, 64);
     t += __shfl_xor(t, 2, 64);
     t += __shfl_xor(t, 1, 64);
-    if (ok && (lane & 7) == 0) epilogue<MODE>(p, lr.row, 0, t);
+    if (ok && (lane & 7) == 0) epilogue<MODE>(p, row, 0, t);
 }
 
 // The second family step of a single seed, gated by the push plan's flag:

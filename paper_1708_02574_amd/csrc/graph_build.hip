@@ -873,6 +873,14 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     // bands of consecutive medium rows: at most 63 rows and kGroupEdges
     // edges per slice
     const int64_t band_section = pos;
+    // medium row k's slot of slice x is x * M + k (a band item stores its
+    // rows' sums side by side); the long rows' slots follow
+    const int64_t M = (int64_t)mrows.size();
+    if (8 * M > INT32_MAX) {
+        cleanup();
+        return fail(TPA_ERR_INDEX_OVERFLOW, "too many sliced work items");
+    }
+    slot = 8 * M;
     for (size_t i = 0; i < mrows.size();) {
         int64_t bc[kSliceCount] = {};
         size_t j = i;
@@ -885,11 +893,9 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
             ++j;
         }
         const int R = (int)(j - i);  // >= 1: a medium row has at most EW <= kGroupEdges edges
-        const int64_t slot0 = slot;
-        slot += 8 * (int64_t)R;
         for (int x = 0; x < kSliceCount; ++x) {
             const int64_t tab = (int64_t)xrel.size();
-            xrel.push_back((int32_t)(slot0 + x));
+            xrel.push_back((int32_t)(x * M + (int64_t)i));
             int64_t run = 0;
             for (size_t r = i; r < j; ++r) {
                 xrel.push_back((int32_t)run);
@@ -900,8 +906,8 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
             lists[x].push_back({pos, (int32_t)tab, item_meta((uint32_t)R, (uint32_t)run, kItemGroup) | kItemBandBit});
             pos += run;
         }
-        for (size_t r = i; r < j; ++r) longs8.push_back({mrows[r], 8, (int32_t)(slot0 + 8 * (int64_t)(r - i)), 0});
-        if (slot > INT32_MAX || (int64_t)xrel.size() > INT32_MAX) {
+        for (size_t r = i; r < j; ++r) longs8.push_back({mrows[r], 8, (int32_t)r, 0});
+        if ((int64_t)xrel.size() > INT32_MAX) {
             cleanup();
             return fail(TPA_ERR_INDEX_OVERFLOW, "too many sliced work items");
         }

@@ -329,9 +329,11 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
     p.str = g->str;
     p.out = out;
     p.n = g->n;
-    // a pulled family step that gathers hub-first ids: sliced when available
-    auto pull = [&](const StepParams &pp) -> tpa_status {
-        if (sx && pp.col == g->t_colz) {
+    // a pulled family step that gathers hub-first ids: sliced when available,
+    // except step 3 behind a frontier skip (its sparse pulls pay for the
+    // slice sums of every split row and gain little from the locality)
+    auto pull = [&](const StepParams &pp, int step) -> tpa_status {
+        if (sx && pp.col == g->t_colz && (!pp.bits || step >= 4)) {
             StepParams px = pp;
             px.col = colx;
             return launch_step(*sx, kFamily, false, px, st);
@@ -397,7 +399,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
                 p3.bits = pp.bits;
                 p3.bits_on = pp.flag;
                 p3.skip_on = pp.flag3;
-                TPA_TRY(pull(p3));
+                TPA_TRY(pull(p3, step));
                 continue;
             }
             if (step == 2 && push2) {
@@ -431,7 +433,7 @@ tpa_status run_query(tpa_graph *g, const int32_t *seeds, const float *q, int64_t
             const bool first = step == 1 && !q;
             p.col = first ? g->t.col : col_gather;
             p.w = first ? (g->weighted ? g->t.w : nullptr) : w_gather;
-            TPA_TRY(first ? launch_step(*s, kFamily, true, p, st) : pull(p));
+            TPA_TRY(first ? launch_step(*s, kFamily, true, p, st) : pull(p, step));
         }
     }
     return TPA_OK;

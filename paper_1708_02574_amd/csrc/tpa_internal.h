@@ -143,8 +143,9 @@ struct Schedule {
 // then the long rows (slice-major per row).  rowptr_x gives each row's
 // offset in the short section with bit kRowxForeignBit set on medium and
 // long rows (no edges there; their epilogue is the finish pass's), and a
-// band item's row0 indexes xrel: [first partial slot, run offsets 0..R];
-// row i's slot of slice x is the band's first slot + 8 i + x.
+// band item's row0 indexes xrel: [first partial slot, run offsets 0..R].
+// Medium row k (in row order, M of them) keeps slice x's sum in slot
+// x * M + k; the long rows' chunk slots follow from 8 M.
 constexpr int kSliceCount = 8;
 constexpr int64_t kSliceMinN = int64_t(1) << 23;
 constexpr int kSliceShortRow = 32;
