@@ -62,6 +62,10 @@ struct AdjParams {
                                        // gather order, each entry with its LDS slot); set by adj_step
     const int32_t *lrow = nullptr;     // row of node v in lambda (rank by in-degree; null: v);
                                        // col then holds rows of lambda
+    // XCD-sliced schedules (kt == 1): a chunk item's partial slot is its row0
+    // and slot_row[slot] its row; set by adj_step from the schedule
+    int chunk_slot_in_item = 0;
+    const int32_t *slot_row = nullptr;
 };
 
 // Row of node u in the lambda vectors.
@@ -191,7 +195,9 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         return;
     }
     // one row or one chunk of a long row
-    const int64_t row = kind == (int)kItemRow ? (int64_t)it.row0 : (int64_t)p.longs[it.row0].row;
+    const int64_t row = kind == (int)kItemRow     ? (int64_t)it.row0
+                        : p.chunk_slot_in_item ? (int64_t)p.slot_row[it.row0]
+                                               : (int64_t)p.longs[it.row0].row;
     const float xr = WITHG ? p.omc * p.xprev[row] : 0.0f;
     const bool whole = kind == (int)kItemRow;
     const float gu = whole ? p.gvec[row] : 0.0f;
@@ -225,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void adj_kernel_1(const Item *__restrict_
         if (whole)
             p.lam_out[lam_row(p, row)] = fmaf(p.beta, gu, p.omc * (WEIGHTED ? s : s * iu));
         else
-            p.partials[wid] = s;
+            p.partials[p.chunk_slot_in_item ? (int64_t)it.row0 : wid] = s;
     }
 }
 
@@ -577,6 +583,9 @@ tpa_status adj_step(const Schedule &s, const AdjParams &p0, hipStream_t st) {
     // of A~'s own when it has them
     AdjParams p = p0;
     p.col_slots = 0;
+    p.chunk_slot_in_item = s.chunk_slot_in_item ? 1 : 0;
+    if (s.chunk_slot_in_item && (p.kt != 1 || p.w || !p.slot_row))
+        return fail(TPA_ERR_INVALID_ARG, "an XCD-sliced adjoint schedule takes single-column steps with 1/outdeg weights");
     if (p.kt == 1 && s.colg && p.col == s.colg_src) {
         p.col = s.colg;
         p.col_slots = 1;
@@ -692,6 +701,18 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     const int32_t *a_col = lam_hub ? g->a_colr : g->a.col;
     const int32_t *lrow = lam_hub ? g->lrank : nullptr;
     TPA_TRY(ensure_group_order(g, sa1, st, true));
+    // the stranger chain's adjoint steps in XCD slices on large graphs; its
+    // edge gradient is then in the sliced order until the chain ends
+    const SlicedAdj *sxa = nullptr;
+    if (grad_logits) TPA_TRY(ensure_sliced_adj(g, a_col, st, &sxa));
+    const Schedule *sas = sxa ? &sxa->s : sa1;
+    auto unslice_g = [&](Scratch &scr) -> tpa_status {
+        if (!sxa) return TPA_OK;
+        float *gx = nullptr;
+        TPA_TRY(scr.get(&gx, (size_t)m, st));
+        TPA_TRY_HIP(hipMemcpyAsync(gx, grad_logits, sizeof(float) * m, hipMemcpyDeviceToDevice, st));
+        return launch_unslice(*sxa, gx, grad_logits, st);
+    };
 
     if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
@@ -700,15 +721,16 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(sc.get(&gs, n, st));
         TPA_TRY(sc.get(&lam0, n, st));
         TPA_TRY(sc.get(&lam1, n, st));
-        TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
+        TPA_TRY(sc.get(&part_a, sas->n_chunk_items, st));
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         AdjParams ap;
         ap.rowptr = g->a.rowptr;
-        ap.col = a_col;
+        ap.col = sxa ? sxa->col : a_col;
+        ap.slot_row = sxa ? sxa->slot_row : nullptr;
         ap.lrow = lrow;
         ap.w = g->weighted ? g->a.w : nullptr;
         ap.inv = g->inv_deg;
-        ap.longs = sa1->longs;
+        ap.longs = sas->longs;
         ap.G = grad_logits;
         ap.gvec = gs;
         ap.omc = omc;
@@ -724,9 +746,10 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             ap.lam_in = lc;
             ap.lam_out = ln;
             ap.beta = (i - 1 >= T) ? 1.0f : 0.0f;
-            TPA_TRY(adj_step(*sa1, ap, st));
+            TPA_TRY(adj_step(*sas, ap, st));
             std::swap(lc, ln);
         }
+        TPA_TRY(unslice_g(sc));
     } else if (grad_logits) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
         // ---- stranger chain, checkpointed ----
@@ -751,7 +774,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         TPA_TRY(sc.get(&lam1, n, st));
         TPA_TRY(sc.get(&comp, n, st));
         TPA_TRY(sc.get(&part_f, sfs->n_chunk_items, st));
-        TPA_TRY(sc.get(&part_a, sa1->n_chunk_items, st));
+        TPA_TRY(sc.get(&part_a, sas->n_chunk_items, st));
         gsum_kernel<<<grid_1d(n), 256, 0, st>>>(grad_out, k, n, gs);
         // forward pass: checkpoints x'(0), x'(C), ...
         StepParams fp;
@@ -778,11 +801,12 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
         // backward over segments
         AdjParams ap;
         ap.rowptr = g->a.rowptr;
-        ap.col = a_col;
+        ap.col = sxa ? sxa->col : a_col;
+        ap.slot_row = sxa ? sxa->slot_row : nullptr;
         ap.lrow = lrow;
         ap.w = g->weighted ? g->a.w : nullptr;
         ap.inv = g->inv_deg;
-        ap.longs = sa1->longs;
+        ap.longs = sas->longs;
         ap.G = grad_logits;
         ap.gvec = gs;
         ap.omc = omc;
@@ -813,10 +837,11 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
                 ap.lam_in = lc;
                 ap.lam_out = ln;
                 ap.beta = (i - 1 >= T) ? 1.0f : 0.0f;
-                TPA_TRY(adj_step(*sa1, ap, st));
+                TPA_TRY(adj_step(*sas, ap, st));
                 std::swap(lc, ln);
             }
         }
+        TPA_TRY(unslice_g(sc));
     }
 
     // ---- family chains per seed tile ----

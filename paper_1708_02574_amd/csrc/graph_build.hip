@@ -727,6 +727,36 @@ __global__ __launch_bounds__(256) void slice_scatter_kernel(const int64_t *__res
     }
 }
 
+// The inverse of slice_scatter_kernel's placement for per-edge values:
+// edge k of segment sg (original order) takes the value at the position the
+// scatter gave it.
+__global__ __launch_bounds__(256) void slice_gather_back_kernel(const int64_t *__restrict__ seg_e0,
+                                                                const int32_t *__restrict__ seg_len, int64_t nseg,
+                                                                const int64_t *__restrict__ seg_out,
+                                                                const int32_t *__restrict__ col,
+                                                                const float *__restrict__ vx,
+                                                                float *__restrict__ v) {
+    const int lane = threadIdx.x & 63;
+    const int64_t sg = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (sg >= nseg) return;
+    const int64_t e0 = seg_e0[sg];
+    const int len = seg_len[sg];
+    int64_t o[kSliceCount];
+#pragma unroll
+    for (int k = 0; k < kSliceCount; ++k) o[k] = seg_out[sg * kSliceCount + k];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int b = 0; b < len; b += 64) {
+        const int e = b + lane;
+        const int x = e < len ? gather_slice(col[e0 + e]) : -1;
+#pragma unroll
+        for (int k = 0; k < kSliceCount; ++k) {
+            const uint64_t mk = __ballot(x == k);
+            if (x == k) v[e0 + e] = vx[o[k] + __popcll(mk & below)];
+            o[k] += __popcll(mk);
+        }
+    }
+}
+
 // Short rows' edges into their section of the sliced ids (grid-stride
 // over rows; rows flagged foreign are placed by slice_scatter_kernel).
 __global__ __launch_bounds__(256) void short_copy_kernel(const int64_t *__restrict__ rp,
@@ -1040,6 +1070,191 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     return TPA_OK;
 }
 
+void SlicedAdj::release() {
+    s.release();
+    dfree(col);
+    dfree(slot_row);
+    dfree(seg_e0);
+    dfree(seg_len);
+    dfree(seg_out);
+    *this = SlicedAdj();
+}
+
+tpa_status launch_unslice(const SlicedAdj &sa, const float *gx, float *G, hipStream_t st) {
+    if (sa.nseg == 0) return TPA_OK;
+    slice_gather_back_kernel<<<(unsigned)((sa.nseg + 3) / 4), 256, 0, st>>>(sa.seg_e0, sa.seg_len, sa.nseg, sa.seg_out,
+                                                                              sa.from, gx, G);
+    TPA_TRY_HIP(hipGetLastError());
+    return TPA_OK;
+}
+
+tpa_status ensure_sliced_adj(tpa_graph *g, const int32_t *src, hipStream_t st, const SlicedAdj **out) {
+    *out = nullptr;
+    if (g->sliced_sweep == 0 || (g->sliced_sweep == 1 && g->n < kSliceMinN)) return TPA_OK;
+    if (g->weighted || !src || g->n == 0) return TPA_OK;
+    SlicedAdj &sa = g->sax;
+    const int ew = choose_shape(g, 1).ew;
+    if (sa.ew == ew && sa.from == src && (sa.none || sa.s.items)) {
+        if (!sa.none) *out = &sa;
+        return TPA_OK;
+    }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return TPA_OK;
+    const int64_t n = g->n, m = g->m;
+    std::vector<int64_t> rp(n + 1);
+    TPA_TRY_HIP(hipMemcpyAsync(rp.data(), g->a.rowptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, st));
+    TPA_TRY_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> lrows;
+    std::vector<int64_t> first_seg, seg_e0;
+    std::vector<int32_t> seg_len;
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d <= ew) continue;
+        lrows.push_back((int32_t)r);
+        first_seg.push_back((int64_t)seg_e0.size());
+        for (int64_t off = 0; off < d; off += kSliceSegment) {
+            seg_e0.push_back(rp[r] + off);
+            seg_len.push_back((int32_t)std::min<int64_t>(kSliceSegment, d - off));
+        }
+    }
+    first_seg.push_back((int64_t)seg_e0.size());
+    sa.release();
+    if (lrows.empty()) {
+        sa.ew = ew;
+        sa.from = src;
+        sa.none = true;
+        return TPA_OK;
+    }
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || (size_t)m * sizeof(int32_t) > free_b / 4) return TPA_OK;
+    SlicedAdj nx;
+    const int64_t nseg = (int64_t)seg_e0.size();
+    int32_t *d_cnt = nullptr;
+    auto bail = [&](tpa_status rc) {
+        dfree(d_cnt);
+        nx.release();
+        return rc;
+    };
+    tpa_status rc = TPA_OK;
+    if ((rc = dalloc(&nx.seg_e0, nseg, st)) != TPA_OK || (rc = dalloc(&nx.seg_len, nseg, st)) != TPA_OK ||
+        (rc = dalloc(&d_cnt, nseg * kSliceCount, st)) != TPA_OK ||
+        (rc = dalloc(&nx.seg_out, nseg * kSliceCount, st)) != TPA_OK)
+        return bail(rc);
+    nx.nseg = nseg;
+    std::vector<int32_t> cnt((size_t)nseg * kSliceCount);
+    hipError_t e = hipMemcpyAsync(nx.seg_e0, seg_e0.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(nx.seg_len, seg_len.data(), sizeof(int32_t) * nseg, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        slice_count_kernel<<<(unsigned)((nseg + 3) / 4), 256, 0, st>>>(nx.seg_e0, nx.seg_len, nseg, src, d_cnt);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(cnt.data(), d_cnt, sizeof(int32_t) * cnt.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return bail(fail(TPA_ERR_HIP, std::string("sliced adjoint: ") + hipGetErrorString(e)));
+    // in place: slice x's run of a long row follows slices 0..x-1 within
+    // the row, cut into chunks of at most 4*EW edges
+    const int64_t chunk = 4 * (int64_t)ew;
+    std::vector<int64_t> seg_out((size_t)nseg * kSliceCount);
+    std::vector<Item> lists[kSliceCount];
+    std::vector<int32_t> slot_row;
+    std::vector<LongRow> longs;
+    int64_t slot = 0;
+    for (size_t l = 0; l < lrows.size(); ++l) {
+        const int64_t r = lrows[l], d = rp[r + 1] - rp[r];
+        int64_t tot[kSliceCount] = {};
+        for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg)
+            for (int x = 0; x < kSliceCount; ++x) tot[x] += cnt[(size_t)sg * kSliceCount + x];
+        int64_t sum = 0;
+        for (int x = 0; x < kSliceCount; ++x) sum += tot[x];
+        if (sum != d) return bail(fail(TPA_ERR_HIP, "sliced adjoint: slice counts do not add up to the row length"));
+        const int64_t first_slot = slot;
+        int64_t start = rp[r];
+        for (int x = 0; x < kSliceCount; ++x) {
+            int64_t at = start;
+            for (int64_t sg = first_seg[l]; sg < first_seg[l + 1]; ++sg) {
+                seg_out[(size_t)sg * kSliceCount + x] = at;
+                at += cnt[(size_t)sg * kSliceCount + x];
+            }
+            for (int64_t off = 0; off < tot[x]; off += chunk) {
+                const int64_t len = std::min(chunk, tot[x] - off);
+                lists[x].push_back({start + off, (int32_t)slot, item_meta(1, (uint32_t)len, kItemChunk)});
+                slot_row.push_back((int32_t)r);
+                ++slot;
+            }
+            start += tot[x];
+        }
+        if (slot > INT32_MAX) return bail(fail(TPA_ERR_INDEX_OVERFLOW, "too many chunk items"));
+        longs.push_back({(int32_t)r, (int32_t)(slot - first_slot), (int32_t)first_slot, 0});
+    }
+    size_t per = 0;
+    for (int x = 0; x < kSliceCount; ++x) per = std::max(per, (lists[x].size() + 3) / 4);
+    const Item pad = {0, 0, item_meta(0, 0, kItemGroup)};
+    std::vector<Item> all;
+    all.reserve(per * 4 * kSliceCount + (size_t)(m / std::max(ew, 1)) + 64);
+    for (size_t jb = 0; jb < per; ++jb)
+        for (int x = 0; x < kSliceCount; ++x)
+            for (size_t w = 0; w < 4; ++w) {
+                const size_t i = jb * 4 + w;
+                all.push_back(i < lists[x].size() ? lists[x][i] : pad);
+            }
+    int64_t gstart = -1, gnnz = 0;
+    auto close_group = [&](int64_t end) {
+        if (gstart >= 0 && end > gstart)
+            all.push_back({rp[gstart], (int32_t)gstart, item_meta((uint32_t)(end - gstart), (uint32_t)gnnz, kItemGroup)});
+        gstart = -1;
+        gnnz = 0;
+    };
+    for (int64_t r = 0; r < n; ++r) {
+        const int64_t d = rp[r + 1] - rp[r];
+        if (d > ew) {
+            close_group(r);
+            continue;
+        }
+        if (gstart >= 0 && (r - gstart >= 63 || gnnz + d > ew)) close_group(r);
+        if (gstart < 0) gstart = r;
+        gnnz += d;
+    }
+    close_group(n);
+    if ((uint64_t)((all.size() + 3) / 4) * 256 > UINT32_MAX)
+        return bail(fail(TPA_ERR_INDEX_OVERFLOW, "too many work items for one launch"));
+    Schedule &sx = nx.s;
+    sx.ew = ew;
+    sx.ds = std::min(32, ew);
+    sx.el = ew;
+    sx.chunk = (int)chunk;
+    sx.eb = 0;
+    sx.chunk_slot_in_item = true;
+    sx.n_items = (int64_t)all.size();
+    sx.n_chunk_items = slot;
+    sx.n_long = (int64_t)longs.size();
+    if ((rc = dalloc(&sx.items, sx.n_items, st)) != TPA_OK || (rc = dalloc(&sx.longs, sx.n_long, st)) != TPA_OK ||
+        (rc = dalloc(&nx.slot_row, (size_t)std::max<int64_t>(slot, 1), st)) != TPA_OK ||
+        (rc = dalloc(&nx.col, m, st)) != TPA_OK)
+        return bail(rc);
+    e = hipMemcpyAsync(nx.seg_out, seg_out.data(), sizeof(int64_t) * seg_out.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(nx.col, src, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        slice_scatter_kernel<<<(unsigned)((nseg + 3) / 4), 256, 0, st>>>(nx.seg_e0, nx.seg_len, nseg, nx.seg_out, src,
+                                                                          nx.col);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(sx.items, all.data(), sizeof(Item) * all.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sx.longs, longs.data(), sizeof(LongRow) * longs.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(nx.slot_row, slot_row.data(), sizeof(int32_t) * slot_row.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(d_cnt);
+    d_cnt = nullptr;
+    if (e != hipSuccess) return bail(fail(TPA_ERR_HIP, std::string("sliced adjoint: ") + hipGetErrorString(e)));
+    nx.from = src;
+    nx.ew = ew;
+    sa = nx;
+    *out = &sa;
+    return TPA_OK;
+}
+
 void drop_group_order(tpa_graph *g) {
     // the copies stay allocated (query graphs captured before may read them)
     for (auto &kv : g->sched_t) kv.second.colg_src = nullptr;
@@ -1170,6 +1385,7 @@ void graph_release(tpa_graph *g) {
     g->a_colr = nullptr;
     dfree(g->t_colx);
     g->t_colx = nullptr;
+    g->sax.release();
     g->sched_x.release();
     g->sched_x_ew = 0;
     g->sched_x_none = false;
@@ -1410,6 +1626,8 @@ extern "C" tpa_status tpa_graph_device_bytes(tpa_graph_t g, size_t *bytes) {
     add(g->sched_x.longs, sizeof(LongRow) * (size_t)g->sched_x.n_long);
     add(g->sched_x.longs8, sizeof(LongRow) * (size_t)g->sched_x.n_long8);
     add(g->sched_x.rowptr_x, sizeof(int64_t) * (n + 1));
+    add(g->sax.col, sizeof(int32_t) * m);
+    add(g->sax.s.items, sizeof(Item) * (size_t)g->sax.s.n_items);
     add(g->str, sizeof(float) * n);
     add(g->dev_err, sizeof(int32_t));
     add(g->ws, g->ws_bytes);

@@ -154,6 +154,28 @@ constexpr int kRowxForeignBit = 62;
 constexpr int64_t kRowxMask = (int64_t(1) << kRowxForeignBit) - 1;
 __host__ __device__ inline int gather_slice(int32_t r) { return r < 8192 ? (r & 7) : ((r >> 10) & 7); }
 
+// XCD-sliced adjoint sweep over the rows of A~ (the stranger chain's
+// single-vector step with the edge gradient, 1/outdeg graphs): rows longer
+// than a group item have their edges stably partitioned in place, within
+// the row, by the slice of the lambda row they gather, and each slice run
+// is summed in chunk items on its XCD; the other rows keep A~'s order in
+// group items.  The edge gradient accumulates in that order over the chain
+// and is put back in A~'s order after it (the segments of the partition are
+// kept for that).
+struct SlicedAdj {
+    Schedule s;                     // chunk items carry their partial slot in row0
+    int32_t *col = nullptr;         // device, m: the gathered ids, long rows partitioned
+    const int32_t *from = nullptr;  // the ids it was built from
+    int32_t *slot_row = nullptr;    // device: the row of each partial slot
+    int64_t *seg_e0 = nullptr;      // device: counting segments of the long rows
+    int32_t *seg_len = nullptr;
+    int64_t *seg_out = nullptr;     // device, [nseg][8]: where each slice's edges of a segment go
+    int64_t nseg = 0;
+    int ew = 0;
+    bool none = false;              // built for ew and from: no long rows
+    void release();
+};
+
 struct Csr {
     int64_t *rowptr = nullptr;  // n+1
     int32_t *col = nullptr;     // m
@@ -223,6 +245,7 @@ struct tpa_graph {
     tpa::Schedule sched_x;
     int sched_x_ew = 0;
     bool sched_x_none = false;
+    tpa::SlicedAdj sax;                     // the adjoint's (same mode)
     float *inv_deg = nullptr;               // 1/outdeg(u), FP32
     uint8_t *padded = nullptr;
     bool weighted = false;                  // weights from logits (a.w, t.w set)
@@ -321,6 +344,12 @@ tpa_status ensure_lam_layout(tpa_graph *g, hipStream_t stream);
 tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t stream, const Schedule **s, const int32_t **col);
 // The same when already built for the current shape, else null (never builds).
 const Schedule *find_sliced_sweep(const tpa_graph *g, const int32_t **col);
+// The XCD-sliced adjoint sweep for gathered ids `src` (A~'s destinations in
+// lambda's row order) when the graph takes one, else *out = nullptr; built
+// on first use (synchronous), never under stream capture.
+tpa_status ensure_sliced_adj(tpa_graph *g, const int32_t *src, hipStream_t stream, const SlicedAdj **out);
+// Edge gradient of the long rows from the sliced order (gx) back to A~'s (G).
+tpa_status launch_unslice(const SlicedAdj &sa, const float *gx, float *G, hipStream_t stream);
 tpa_status graph_alloc_common(tpa_graph *g, hipStream_t stream);
 void graph_release(tpa_graph *g);
 int key_bits(int64_t n);

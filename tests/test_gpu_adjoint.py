@@ -370,8 +370,11 @@ def test_backward_lambda_rank_order_large_graph(tpa, torch, weighted):
 
 def test_backward_sliced_sweep(tpa, torch):
     """The adjoint recomputes the stranger chain in XCD slices as
-    preprocessing computed it: the gradients are bitwise equal with the
-    iterates kept, recomputed or checkpointed, and match the oracle's."""
+    preprocessing computed it, and sums the long rows of A~ in slices too
+    (the edge gradient put back in A~'s order after the chain): the
+    gradients are bitwise equal with the iterates kept, recomputed or
+    checkpointed, agree with the unsliced adjoint to FP32 rounding, and
+    match the oracle's."""
     og = oracle.Graph.rmat(12, 1 << 16, 41)
     og.preprocess(c, T, EPS)
     gg = tpa.Graph.rmat(12, 1 << 16, 41)
@@ -390,8 +393,58 @@ def test_backward_sliced_sweep(tpa, torch):
         kept = gg.backward(Wt, c, S, T, seeds=sd)
         for a, b, d in zip(ref, ck, kept):
             assert torch.equal(a, b) and torch.equal(a, d)
+        gg.set_keep_iterates(False)
+        gg.set_sliced_sweep(0)
+        gg.preprocess(c, T)
+        plain = gg.backward(Wt, c, S, T, seeds=sd)
     finally:
         gg.set_keep_iterates(False)
+    for a, b in zip(ref, plain):
+        a, b = a.double().cpu().numpy(), b.double().cpu().numpy()
+        assert nl1(a, b) <= 1e-6
     odth, _, odq = og.backward(onehot(og.n, seeds), W.astype(np.float64), c, S, T, og.K)
     assert nl1(ref[0].cpu().numpy(), odth) <= TOL
     assert nl1(ref[1].cpu().numpy(), odq) <= TOL
+
+
+def test_backward_sliced_adjoint_large_graph(tpa, torch):
+    """From 2^23 nodes the stranger chain's adjoint sums the rows of A~
+    longer than a group item (here hub sources of 600..5000 out-edges, whose
+    destinations spread over lambda's rank order) in XCD slices, with the
+    edge gradient put back in A~'s order after the chain: against the
+    oracle, against the unsliced adjoint to FP32 rounding, and bitwise
+    between checkpointed and recomputed iterates."""
+    n = 1 << 23
+    rng = np.random.default_rng(58)
+    core = rng.integers(0, 2048, size=(2, 30000))
+    hubs = np.array([5, 700, 2047, n - 3, n - 2000], np.int64)
+    deg = np.array([600, 1500, 5000, 900, 2600])
+    hsrc = np.repeat(hubs, deg)
+    hdst = np.concatenate([rng.choice(n, d, replace=False) for d in deg])
+    back = rng.integers(0, 2048, size=(2, 8000))
+    src = np.concatenate([core[0], hsrc, hdst[:8000]]).astype(np.int32)
+    dst = np.concatenate([core[1], hdst, back[1]]).astype(np.int32)
+    gg = tpa.Graph.from_edges(n, src, dst)
+    og = oracle.Graph(n, src, dst)
+    assert og.m == gg.m
+    seeds_np = np.array([5, 100, n - 3, int(hdst[3])], np.int32)
+    seeds = torch.from_numpy(seeds_np).cuda()
+    W = ti.draw_loss_weights((4, n), 59)
+    Wd = torch.from_numpy(W).cuda()
+    out = {}
+    for mode in (0, 1):
+        gg.set_sliced_sweep(mode)
+        gg.preprocess(c, T)
+        out[mode] = gg.backward(Wd, c, S, T, seeds=seeds)
+        if mode == 1:
+            ck = gg.backward(Wd, c, S, T, seeds=seeds, checkpoint_every=7)
+            for a, b in zip(out[1], ck):
+                assert torch.equal(a, b)
+    for a, b in zip(out[1], out[0]):
+        assert nl1(a.double().cpu().numpy(), b.double().cpu().numpy()) <= 1e-6
+    og.preprocess(c, T, EPS)
+    odth, _, odq = og.backward(onehot(n, seeds_np), W.astype(np.float64), c, S, T, og.K)
+    dth, dq = out[1]
+    assert nl1(dth.cpu().numpy(), odth) <= TOL
+    assert nl1(dq.cpu().numpy(), odq) <= TOL
+    gg.close()
