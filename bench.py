@@ -339,7 +339,9 @@ def headline(tpa, torch, np, ti, args) -> dict:
         rec["adjoint"] = {"seeds": 4, "ms": round(bwd, 1), "checkpoint_every": ck,
                           "note": "gradients w.r.t. edge logits (at theta = 0) and the restart vectors; the "
                                   "stranger chain recomputed per checkpoint segment",
-                          "roofline": roofline("adj_kernel_1<edge gradient> (stranger-chain adjoint step)",
+                          "roofline": roofline("adj_kernel_1<edge gradient> (stranger-chain adjoint step, "
+                                               "long rows XCD-sliced)" if sliced else
+                                               "adj_kernel_1<edge gradient> (stranger-chain adjoint step)",
                                                bytes_adjoint(n, m, 1), *pa[ca],
                                                traffic_from_profile("adj_kernel_1_rmat27_traffic", ADJ_SRC))}
     g.close()

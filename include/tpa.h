@@ -407,7 +407,13 @@ tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
  * slice) and the work items, built at the first sweep that takes them
  * (synchronous; when the copy takes at most a quarter of the free device
  * memory, and never under stream capture).  Only graphs with 1/outdeg
- * weights in the hub-first gather layout take it.  mode: 0 off, 1 (the
+ * weights in the hub-first gather layout take it.  The same mode slices the
+ * adjoint steps of the stranger chain in tpa_backward (1/outdeg graphs):
+ * rows of A~ longer than a group item are summed per slice of the lambda
+ * rows they gather (their edges partitioned within the row, in one more
+ * int32[m] copy of the gathered ids), and the edge gradient, accumulated in
+ * that order over the chain, is put back in A~'s order after it (a
+ * float[m] temporary).  mode: 0 off, 1 (the
  * default) from 2^23 nodes, 2 on every such graph.  The results agree with
  * the unsliced sweep up to FP32 rounding (the long rows are added in
  * another order).  tpa_get_sliced_sweep reports the mode and, in *active
