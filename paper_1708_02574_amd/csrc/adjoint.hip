@@ -616,10 +616,22 @@ constexpr size_t kAdjCacheBytes = (size_t)8 << 30;
 struct Scratch {
     tpa_graph *g;
     size_t next = 0;
+    bool keep_sax = false;  // the sliced adjoint sweep is in use
     std::vector<void *> own;  // this call's uncached buffers
     explicit Scratch(tpa_graph *graph) : g(graph) {}
     ~Scratch() {
         for (void *b : own) dfree(b);
+    }
+    // Device memory, or, when the device is out of it, again after dropping
+    // the sliced adjoint sweep (rebuilt at its next use).
+    tpa_status alloc(void **p, size_t bytes, hipStream_t st) {
+        tpa_status rc = dmalloc(p, bytes, st);
+        if (rc == TPA_ERR_OUT_OF_MEMORY && g->sax.col && !keep_sax) {
+            (void)hipStreamSynchronize(st);
+            g->sax.release();
+            rc = dmalloc(p, bytes, st);
+        }
+        return rc;
     }
     template <class T>
     tpa_status get(T **p, size_t count, hipStream_t st) {
@@ -639,13 +651,15 @@ struct Scratch {
                 cache[slot] = {nullptr, 0};
             }
             void *b = nullptr;
-            TPA_TRY(dmalloc(&b, bytes, st));
+            TPA_TRY(alloc(&b, bytes, st));
             if (slot < cache.size()) cache[slot] = {b, bytes};
             else cache.push_back({b, bytes});  // slot == cache.size(): slots fill in order
             *p = static_cast<T *>(b);
             return TPA_OK;
         }
-        TPA_TRY(dalloc(p, std::max<size_t>(count, 1), st));
+        void *b = nullptr;
+        TPA_TRY(alloc(&b, bytes, st));
+        *p = static_cast<T *>(b);
         own.push_back(*p);
         return TPA_OK;
     }
@@ -705,13 +719,22 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
     // edge gradient is then in the sliced order until the chain ends
     const SlicedAdj *sxa = nullptr;
     if (grad_logits) TPA_TRY(ensure_sliced_adj(g, a_col, st, &sxa));
+    sc.keep_sax = sxa != nullptr;
     const Schedule *sas = sxa ? &sxa->s : sa1;
-    auto unslice_g = [&](Scratch &scr) -> tpa_status {
+    // (a temporary copy of G, freed before the family chains allocate)
+    auto unslice_g = [&]() -> tpa_status {
         if (!sxa) return TPA_OK;
         float *gx = nullptr;
-        TPA_TRY(scr.get(&gx, (size_t)m, st));
-        TPA_TRY_HIP(hipMemcpyAsync(gx, grad_logits, sizeof(float) * m, hipMemcpyDeviceToDevice, st));
-        return launch_unslice(*sxa, gx, grad_logits, st);
+        TPA_TRY(dalloc(&gx, (size_t)m, st));
+        hipError_t e = hipMemcpyAsync(gx, grad_logits, sizeof(float) * m, hipMemcpyDeviceToDevice, st);
+        tpa_status rc = e == hipSuccess ? launch_unslice(*sxa, gx, grad_logits, st) : TPA_ERR_HIP;
+        if (rc == TPA_OK) e = hipStreamSynchronize(st);
+        dfree(gx);
+        if (rc != TPA_OK || e != hipSuccess)
+            return rc != TPA_OK ? rc : fail(TPA_ERR_HIP, std::string("edge gradient order: ") + hipGetErrorString(e));
+        sxa = nullptr;  // the sliced sweep may be dropped from here on (see Scratch::alloc)
+        sc.keep_sax = false;
+        return TPA_OK;
     };
 
     if (grad_logits && checkpoint_every == 0 && g->xiter_K == K && g->xiter) {
@@ -749,7 +772,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
             TPA_TRY(adj_step(*sas, ap, st));
             std::swap(lc, ln);
         }
-        TPA_TRY(unslice_g(sc));
+        TPA_TRY(unslice_g());
     } else if (grad_logits) {
         TPA_TRY_HIP(hipMemsetAsync(grad_logits, 0, sizeof(float) * m, st));
         // ---- stranger chain, checkpointed ----
@@ -841,7 +864,7 @@ extern "C" tpa_status tpa_backward(tpa_graph_t g, const int32_t *seeds, const fl
                 std::swap(lc, ln);
             }
         }
-        TPA_TRY(unslice_g(sc));
+        TPA_TRY(unslice_g());
     }
 
     // ---- family chains per seed tile ----

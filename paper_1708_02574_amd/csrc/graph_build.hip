@@ -849,7 +849,7 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     if ((rc = dalloc(&d_e0, nseg, st)) != TPA_OK || (rc = dalloc(&d_len, nseg, st)) != TPA_OK ||
         (rc = dalloc(&d_cnt, nseg * kSliceCount, st)) != TPA_OK || (rc = dalloc(&d_out, nseg * kSliceCount, st)) != TPA_OK) {
         cleanup();
-        return rc;
+        return rc == TPA_ERR_OUT_OF_MEMORY ? TPA_OK : rc;  // optional: the sweep runs unsliced
     }
     std::vector<int32_t> cnt((size_t)nseg * kSliceCount);
     hipError_t e = hipMemcpyAsync(d_e0, seg_e0.data(), sizeof(int64_t) * nseg, hipMemcpyHostToDevice, st);
@@ -1015,7 +1015,7 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     }
     if (!g->t_colx && (rc = dalloc(&g->t_colx, m, st)) != TPA_OK) {
         cleanup();
-        return rc;
+        return rc == TPA_ERR_OUT_OF_MEMORY ? TPA_OK : rc;
     }
     g->sched_x.release();
     g->sched_x = Schedule();
@@ -1040,7 +1040,7 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
     if (rc != TPA_OK) {
         sx.release();
         cleanup();
-        return rc;
+        return rc == TPA_ERR_OUT_OF_MEMORY ? TPA_OK : rc;
     }
     e = hipMemcpyAsync(d_out, seg_out.data(), sizeof(int64_t) * seg_out.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -1133,7 +1133,8 @@ tpa_status ensure_sliced_adj(tpa_graph *g, const int32_t *src, hipStream_t st, c
     auto bail = [&](tpa_status rc) {
         dfree(d_cnt);
         nx.release();
-        return rc;
+        // optional: without the memory the steps run unsliced
+        return rc == TPA_ERR_OUT_OF_MEMORY ? TPA_OK : rc;
     };
     tpa_status rc = TPA_OK;
     if ((rc = dalloc(&nx.seg_e0, nseg, st)) != TPA_OK || (rc = dalloc(&nx.seg_len, nseg, st)) != TPA_OK ||
