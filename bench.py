@@ -331,14 +331,20 @@ def headline(tpa, torch, np, ti, args) -> dict:
         del out_plain, out_batch
         torch.cuda.empty_cache()
         ck = int(np.ceil(np.sqrt(K)))
-        bwd = time_ms(torch, lambda: g.backward(W, C_RESTART, S_FAM, T_STR, seeds=seeds[:4], checkpoint_every=ck),
-                      reps=1)
+        # the kernel timing pass is the first call (it builds the adjoint's
+        # layouts of A~), then the timed call
         ca = tpa.profile_code(1, 3, True, False)
+        t0 = time.time()
         pa = profiled(tpa, torch, lambda: g.backward(W, C_RESTART, S_FAM, T_STR, seeds=seeds[:4],
                                                      checkpoint_every=ck), [ca])
+        first_ms = (time.time() - t0) * 1e3
+        bwd = time_ms(torch, lambda: g.backward(W, C_RESTART, S_FAM, T_STR, seeds=seeds[:4], checkpoint_every=ck),
+                      reps=1)
         rec["adjoint"] = {"seeds": 4, "ms": round(bwd, 1), "checkpoint_every": ck,
+                          "first_call_ms": round(first_ms, 1),
                           "note": "gradients w.r.t. edge logits (at theta = 0) and the restart vectors; the "
-                                  "stranger chain recomputed per checkpoint segment",
+                                  "stranger chain recomputed per checkpoint segment; the first call (with "
+                                  "the kernel timing pass) also builds the adjoint's layouts of A~",
                           "roofline": roofline("adj_kernel_1<edge gradient> (stranger-chain adjoint step, "
                                                "long rows XCD-sliced)" if sliced else
                                                "adj_kernel_1<edge gradient> (stranger-chain adjoint step)",
