@@ -923,6 +923,10 @@ tpa_status ensure_sliced_sweep(tpa_graph *g, hipStream_t st, const Schedule **ou
             ++j;
         }
         const int R = (int)(j - i);  // >= 1: a medium row has at most EW <= kGroupEdges edges
+        if (R == 0) {
+            cleanup();
+            return fail(TPA_ERR_HIP, "sliced sweep: a medium row exceeds a band");
+        }
         for (int x = 0; x < kSliceCount; ++x) {
             const int64_t tab = (int64_t)xrel.size();
             xrel.push_back((int32_t)(x * M + (int64_t)i));
