@@ -393,33 +393,39 @@ tpa_status tpa_set_keep_iterates(tpa_graph_t g, int keep);
 tpa_status tpa_set_gather_layout(tpa_graph_t g, int hub_first);
 tpa_status tpa_get_gather_layout(tpa_graph_t g, int *hub_first);
 
-/* XCD-sliced sweep of the stranger chain (Section 3.3's preprocessing CPI,
- * Algorithm 2; the same chain recomputed by tpa_backward).  The chip deals
- * the workgroups of a launch to its 8 XCDs in turn and each XCD caches in an
- * L2 of its own, so a cache line gathered by blocks on several XCDs is
- * fetched into each of their L2s.  In the sliced sweep every row of A~^T
- * with more edges than a group item (512 by default) is summed as 8 runs,
- * one per slice of the hub-first gather rows (rows below 8192 by row mod 8,
- * the others by blocks of 1024 rows), and slice x's runs run on XCD x, so
- * that each L2 holds its own eighth of the gathered vector; a finish pass
- * adds each row's run sums in slice order.  It needs one more int32[m] copy
- * of the hub-first column ids (each long row's edges stably partitioned by
- * slice) and the work items, built at the first sweep that takes them
- * (synchronous; when the copy takes at most a quarter of the free device
- * memory, and never under stream capture).  Only graphs with 1/outdeg
+/* XCD-sliced sweeps (Section 3.3's preprocessing CPI, Algorithm 2; the same
+ * chain recomputed by tpa_backward; the dense family pulls of single-seed
+ * queries).  The chip deals the workgroups of a launch to its 8 XCDs in turn
+ * and each XCD caches in an L2 of its own, so a cache line gathered by
+ * blocks on several XCDs is fetched into each of their L2s.  In the sliced
+ * sweep every row of A~^T with more than 32 edges is summed as 8 runs, one
+ * per slice of the hub-first gather rows (rows below 8192 by row mod 8, the
+ * others by blocks of 1024 rows), and slice x's runs run on XCD x, so that
+ * each L2 holds its own eighth of the gathered vector: rows up to a group
+ * item's budget (512 edges by default) in band items that hold one slice's
+ * runs of up to 63 such rows, longer rows in chunks; finish passes add each
+ * row's run sums in slice order and apply the epilogue.  Shorter rows are
+ * summed whole.  It needs one more int32[m] copy of the hub-first column
+ * ids (rearranged: short rows, then the bands, then the long rows), int64
+ * row offsets and the work items, built at the first preprocessing that
+ * takes them (synchronous; when the copy takes at most a quarter of the
+ * free device memory, and never under stream capture).  Single-seed queries
+ * on the handle's own workspace then use it for their dense pulls (not
+ * captured query graphs, nor tpa_query_noalloc).  Only graphs with 1/outdeg
  * weights in the hub-first gather layout take it.  The same mode slices the
  * adjoint steps of the stranger chain in tpa_backward (1/outdeg graphs):
  * rows of A~ longer than a group item are summed per slice of the lambda
  * rows they gather (their edges partitioned within the row, in one more
- * int32[m] copy of the gathered ids), and the edge gradient, accumulated in
- * that order over the chain, is put back in A~'s order after it (a
- * float[m] temporary).  mode: 0 off, 1 (the
- * default) from 2^23 nodes, 2 on every such graph.  The results agree with
- * the unsliced sweep up to FP32 rounding (the long rows are added in
- * another order).  tpa_get_sliced_sweep reports the mode and, in *active
- * (may be NULL), whether the sliced schedule is built and in use for the
- * graph's current work-item shape.  Errors: INVALID_ARG (mode not 0, 1 or
- * 2, NULL handle). */
+ * int32[m] copy of the gathered ids, dropped and rebuilt when a later
+ * adjoint buffer does not fit), and the edge gradient, accumulated in that
+ * order over the chain, is put back in A~'s order after it (a float[m]
+ * temporary).  mode: 0 off, 1 (the default) from 2^23 nodes, 2 on every
+ * such graph.  The results agree with the unsliced sweeps up to FP32
+ * rounding (the split rows are added in another order).
+ * tpa_get_sliced_sweep reports the mode and, in *active (may be NULL),
+ * whether the forward sliced schedule is built and in use for the graph's
+ * current work-item shape.  Errors: INVALID_ARG (mode not 0, 1 or 2, NULL
+ * handle). */
 tpa_status tpa_set_sliced_sweep(tpa_graph_t g, int mode);
 tpa_status tpa_get_sliced_sweep(tpa_graph_t g, int *mode, int *active);
 tpa_status tpa_get_push_limit(tpa_graph_t g, int64_t *max_edges);
