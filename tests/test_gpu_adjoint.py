@@ -158,7 +158,11 @@ def test_backward_long_rows(g10, tpa, torch):
         assert nl1(dq.cpu().numpy(), odq) <= TOL
 
 
-def test_backward_packed_blocks(tpa, torch):
+@pytest.mark.parametrize("sliced", [False, True])
+def test_backward_packed_blocks(tpa, torch, sliced):
+    """A block-diagonal batch: the adjoint per block against the oracle of
+    each graph; sliced: the XCD-sliced stranger sweep and adjoint steps
+    forced on (64-edge group items, so many rows are split)."""
     params = [(9, 4000, 1, 400), (10, 9000, 2, 0), (8, 1500, 3, 200)]
     ogs, ggs = [], []
     for scale, samples, seed, nn in params:
@@ -166,7 +170,11 @@ def test_backward_packed_blocks(tpa, torch):
         ogs.append(oracle.Graph.rmat(scale, samples, seed, n_nodes=n_nodes))
         ggs.append(tpa.Graph.rmat(scale, samples, seed, n_nodes=n_nodes))
     pk = tpa.Graph.pack(ggs)
+    if sliced:
+        pk.set_sliced_sweep(2)
+        pk.set_tuning(0, 64)
     pk.preprocess(c, T)
+    assert pk.get_sliced_sweep()[1] == sliced
     off = pk.block_offsets()
     P = 2
     loc = [ti.draw_seeds(og.export()["padded"] == 0, P, 30 + b) for b, og in enumerate(ogs)]
