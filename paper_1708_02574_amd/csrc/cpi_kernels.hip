@@ -535,22 +535,39 @@ __global__ __launch_bounds__(kThreads) void step_kernel_1x(const Item *__restric
         item_1x<MODE, false>(p, it, lane, lds[wv]);
 }
 
-// Finish of the medium rows of an XCD-sliced schedule: 8 lanes per row add
-// its 8 slice sums (slice x of medium row i in slot x * n_rows + i; a fixed
-// xor order), then the epilogue.
+// Finish of the medium rows of an XCD-sliced schedule, one thread per row:
+// its 8 slice sums (slice x of medium row i in slot x * n_rows + i, added
+// pairwise in a fixed order), then the epilogue.
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void finish8_kernel(const LongRow *__restrict__ rows, int64_t n_rows,
                                                            StepParams p) {
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n_rows || (p.skip_on && *p.skip_on)) return;
+    const int32_t row = rows[i].row;
+    float v[kSliceCount];
+#pragma unroll
+    for (int x = 0; x < kSliceCount; ++x) v[x] = p.partials[(int64_t)x * n_rows + i];
+    const float t = ((v[0] + v[4]) + (v[2] + v[6])) + ((v[1] + v[5]) + (v[3] + v[7]));
+    epilogue<MODE>(p, row, 0, t);
+}
+
+// Finish of the long rows of an XCD-sliced schedule: 8 lanes per row stride
+// over its chunk sums (slice, then chunk order; a fixed xor order).
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void finish_long8_kernel(const LongRow *__restrict__ longs, int64_t n_long,
+                                                                StepParams p) {
     const int lane = threadIdx.x & 63;
     const int64_t i = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * 8 + (lane >> 3);
     if (p.skip_on && *p.skip_on) return;
-    const bool ok = i < n_rows;
-    const int32_t row = ok ? rows[i].row : 0;
-    float t = ok ? p.partials[(int64_t)(lane & 7) * n_rows + i] : 0.0f;
+    const bool ok = i < n_long;
+    LongRow lr = {0, 0, 0, 0};
+    if (ok) lr = longs[i];
+    float t = 0.0f;
+    for (int k = lane & 7; k < lr.nchunks; k += 8) t += p.partials[(int64_t)lr.first_item + k];
     t += __shfl_xor(t, 4, 64);
     t += __shfl_xor(t, 2, 64);
     t += __shfl_xor(t, 1, 64);
-    if (ok && (lane & 7) == 0) epilogue<MODE>(p, row, 0, t);
+    if (ok && (lane & 7) == 0) epilogue<MODE>(p, lr.row, 0, t);
 }
 
 // The second family step of a single seed, gated by the push plan's flag:
@@ -1654,7 +1671,17 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
         }
         profile_end(slot, st);
     }
-    if (s.n_long > 0) {
+    if (s.n_long > 0 && s.chunk_slot_in_item) {
+        const int slot = profile_begin(127, st);
+        const unsigned grid = blocks_for((s.n_long + 7) / 8);
+        if (mode == kFamily)
+            finish_long8_kernel<kFamily><<<grid, kThreads, 0, st>>>(s.longs, s.n_long, p);
+        else if (mode == kPlain)
+            finish_long8_kernel<kPlain><<<grid, kThreads, 0, st>>>(s.longs, s.n_long, p);
+        else
+            finish_long8_kernel<kStranger><<<grid, kThreads, 0, st>>>(s.longs, s.n_long, p);
+        profile_end(slot, st);
+    } else if (s.n_long > 0) {
         const int slot = profile_begin(127, st);
         if (mode == kFamily)
             finish_kernel<kFamily><<<blocks_for(s.n_long), kThreads, 0, st>>>(s.longs, s.n_long, p);
@@ -1666,7 +1693,7 @@ tpa_status launch_step(const Schedule &s, int mode, bool first, const StepParams
     }
     if (s.n_long8 > 0) {
         const int slot = profile_begin(127, st);
-        const unsigned grid = blocks_for((s.n_long8 + 7) / 8);
+        const unsigned grid = (unsigned)((s.n_long8 + kThreads - 1) / kThreads);
         if (mode == kFamily)
             finish8_kernel<kFamily><<<grid, kThreads, 0, st>>>(s.longs8, s.n_long8, p);
         else if (mode == kPlain)
